@@ -1,0 +1,190 @@
+/*
+ * pe3d.h - C ABI of the MI355X (gfx950) 3D wide-angle parabolic-equation
+ * range march.
+ *
+ * The library advances the PE envelope u(r, theta, z) by the split
+ * Crank-Nicolson scheme of Xu, Wang, Chronopoulos & Yue, Eq. (4):
+ *
+ *   [1 + (1/4 - d/4) X][1 - (d/4) Y] u^{j+1} = [1 + (1/4 + d/4) X][1 + (d/4) Y] u^j,
+ *   d = i k0 dr,
+ *
+ * solved each step by the two-step procedure of Eqs. (5)-(8): one complex
+ * tridiagonal system in depth per azimuth, then one (periodic) complex
+ * tridiagonal system in azimuth per depth.  X is the depth operator
+ * (n^2 - 1) + k0^-2 d^2/dz^2 (density-weighted second difference) and Y the
+ * azimuth operator (k0 r)^-2 d^2/dtheta^2 (3-point second difference), both
+ * from Eq. (3).  The problem statement (frequency, source, sound-speed
+ * profile, range step, boundary conditions, field and transmission loss)
+ * follows the algorithm of Fig. 2.
+ *
+ * Conventions: lengths in m, speeds in m/s, densities in g/cm^3 (only ratios
+ * matter), angles in rad, attenuation in dB per wavelength, frequency in Hz.
+ * Every call returns a pe3d_status; nothing throws or aborts.
+ *
+ * Field layout: a field is a device array of ntheta rows of nz complex
+ * values, depth contiguous (row-major [ntheta][nz]), interleaved (re, im).
+ * Element type: float2 (complex64) for PE3D_C64, double2 (complex128) for
+ * PE3D_C128.  It must be 16-byte aligned.  The caller owns it.
+ *
+ * Streams: a `stream` argument is a hipStream_t passed as void* (NULL is the
+ * default stream).  Marching calls are asynchronous and stream ordered: they
+ * return after enqueueing; device faults surface at the caller's next
+ * synchronisation with that stream.
+ *
+ * Threads: a handle is not thread-safe; distinct handles are independent.
+ * Calls that enqueue work on one handle from several streams race.
+ */
+#ifndef PE3D_H
+#define PE3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pe3d_handle_s* pe3d_handle;
+
+typedef enum {
+  PE3D_OK = 0,
+  PE3D_EINVAL = -1,       /* bad argument; nothing was changed or enqueued  */
+  PE3D_ENOMEM = -2,       /* device or host allocation failed               */
+  PE3D_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed     */
+  PE3D_EUNSUPPORTED = -4, /* valid but outside the built kernels' limits,
+                             or a depth system with a vanishing pivot       */
+  PE3D_ESTATE = -5        /* call not valid in the handle's current state   */
+} pe3d_status;
+
+typedef enum { PE3D_FLOOR_PRESSURE_RELEASE = 0, PE3D_FLOOR_RIGID = 1 } pe3d_floor;
+typedef enum { PE3D_C64 = 0, PE3D_C128 = 1 } pe3d_precision;
+
+/* Ocean environment (the sound sources, receivers and sound-speed profiles
+ * read by Fig. 2, line 2).  Water: sound speed c(z) piecewise linear through
+ * (ssp_z[i], ssp_c[i]) with ssp_z strictly ascending, constant beyond the
+ * ends; uniform density rho_w and attenuation atten_w.  Water depth D(theta)
+ * is periodic piecewise linear through (bathy_theta[i], bathy_depth[i]) with
+ * bathy_theta strictly ascending over less than 2*pi (n_bathy == 1: flat).
+ * A node at depth z is water iff z <= D(theta); below it is a homogeneous
+ * fluid half-space (c_b, rho_b, atten_b).  zmax is the computational floor
+ * with boundary condition `floor`.  The surface is pressure release.
+ * Index of refraction n^2 = (c0/c)^2 (1 + i*eta*atten)^2, eta = 1/(40 pi log10 e).
+ * The arrays are copied by pe3d_create; the caller may free them after. */
+typedef struct {
+  double c0;                  /* reference sound speed, k0 = 2 pi f / c0   */
+  int32_t n_ssp;
+  const double* ssp_z;
+  const double* ssp_c;
+  double rho_w, atten_w;
+  double c_b, rho_b, atten_b;
+  int32_t n_bathy;
+  const double* bathy_theta;
+  const double* bathy_depth;
+  double zmax;
+  int32_t floor;              /* pe3d_floor */
+} pe3d_env;
+
+/* Computational grid.  Depth nodes z_l = l*dz, l = 1..nz, with
+ * dz = zmax/nz (rigid floor, node nz on the floor) or dz = zmax/(nz+1)
+ * (pressure-release floor).  width >= 2*pi*(1 - 1e-12) is the full circle,
+ * periodic in azimuth with dtheta = 2 pi/ntheta and theta_m = theta0 + m dtheta;
+ * a smaller width is a sector centred on theta0 with dtheta = width/(ntheta+1),
+ * theta_m = theta0 - width/2 + (m+1) dtheta and zero field on the two edge
+ * azimuths.  The march starts at range r0 with range step dr (Fig. 2, lines 3-5):
+ * r_j = r0 + j*dr. */
+typedef struct {
+  int32_t nz, ntheta;
+  double theta0, width;
+  double dr, r0;
+  int32_t precision;          /* pe3d_precision */
+} pe3d_grid;
+
+typedef struct { double f_hz; } pe3d_freq;
+
+/* Build a march for one frequency (Fig. 2, lines 1-2 and 7): validates all
+ * arguments before touching the device, builds the medium and the depth
+ * operator in FP64 on the host, factors the depth system [1 + (1/4 - d/4) X]
+ * once (the medium depends on (theta, z) only, so it is range invariant),
+ * and allocates the handle's device buffers (coefficient tables and one
+ * scratch field).  The range counter starts at step j = 0 (range r0).
+ * Limits of the built kernels: complex64 nz <= 4096, ntheta <= 2048;
+ * complex128 nz <= 2048, ntheta <= 1024; nz >= 2; ntheta >= 3 (periodic) or
+ * >= 1 (sector).  Errors: PE3D_EINVAL (null pointer, non-finite or
+ * non-positive f, c0, dr, zmax, speeds or densities, r0 < 0, r0 == 0 when
+ * dr would put r_1 at 0, unordered samples, unknown enum), PE3D_EUNSUPPORTED
+ * (outside the limits, or a depth pivot smaller than 1e-10 of the largest
+ * diagonal), PE3D_ENOMEM, PE3D_EDEVICE.  On error *out is set to NULL. */
+pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,
+                        const pe3d_freq* freq, pe3d_handle* out);
+
+/* Advance the field by nsteps range steps of Eq. (4) (Fig. 2, lines 4-9):
+ * u_dev holds u^j on entry and u^{j+nsteps} on exit (in place).  Each step
+ * forms RHS = [1 + (1/4 + d/4) X][1 + (d/4) Y] u^j, solves Eq. (5) per
+ * azimuth column and Eq. (6) per depth.  Launches one kernel per pass per
+ * step on `stream` (the plain, per-problem march).  nsteps == 0 is a no-op.
+ * The handle's step counter advances by nsteps at enqueue.  Errors:
+ * PE3D_EINVAL (null handle or field, nsteps < 0, misaligned field),
+ * PE3D_EDEVICE (launch failure). */
+pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream);
+
+/* Release every device and host resource of the handle.  NULL is OK.  The
+ * caller must make sure no enqueued work of the handle is still running. */
+pe3d_status pe3d_destroy(pe3d_handle h);
+
+/* Device bytes pe3d_create would allocate for these arguments (coefficient
+ * tables + scratch field), excluding the caller's field.  Host only. */
+pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid,
+                           const pe3d_freq* freq, size_t* bytes);
+
+/* Current step index j and range r_j of the handle. */
+pe3d_status pe3d_get_step(pe3d_handle h, int64_t* j, double* r);
+
+/* Set the step index (resume from a saved field u^j: the march is Markov in
+ * (u^j, j)).  j >= 0.  Synchronises the device with the handle's last
+ * stream before writing. */
+pe3d_status pe3d_set_step(pe3d_handle h, int64_t j);
+
+/* Fill u_dev with the Gaussian starter field of a source at depth zs
+ * (Fig. 2, line 2; the same on every azimuth):
+ *   u(z) = sqrt(k0) [exp(-k0^2 (z - zs)^2 / 2) - exp(-k0^2 (z + zs)^2 / 2)].
+ * Asynchronous on `stream`.  Errors: PE3D_EINVAL (zs not finite or < 0). */
+pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
+
+/* Advance n problems together (the frequency loop of Fig. 2, lines 1 and
+ * 12, distributed over MPI ranks in Sec. 3.2.3): problem i moves by
+ * nsteps[i] >= 0 steps, its field u_devs[i] in place.  All handles must have
+ * the same precision and be distinct.  Each step runs one launch per pass
+ * and kernel class over every problem still stepping (a device work table
+ * of (problem, tile) items).  When use_graph != 0 the whole sequence is
+ * captured once into a hipGraph, cached on the first handle under the exact
+ * argument tuple (handles, steps, field pointers), and replayed on later
+ * identical calls.  Results are bitwise identical to pe3d_march of each
+ * problem alone.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
+pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
+                             const int32_t* nsteps, void* const* u_devs,
+                             int32_t use_graph, void* stream);
+
+/* Transmission loss of a field at the handle's current step (Sec. 4.1,
+ * Fig. 5): tl[m*nz + l] = -20 log10 |u| + 10 log10 r_j, in FP32, written to a
+ * device array of ntheta*nz floats.  Asynchronous on `stream`. */
+pe3d_status pe3d_tl(pe3d_handle h, const void* u_dev, float* tl_dev, void* stream);
+
+/* Static description of the handle (host memory, copied to *info). */
+typedef struct {
+  int32_t nz, ntheta, periodic, precision;
+  double k0, dz, dtheta, dr, r0;
+  int32_t pass_a_lanes;   /* lanes per depth column in the depth pass  */
+  int32_t pass_a_chunk;   /* rows per lane                              */
+  int32_t pass_b_chunks;  /* azimuth chunks per depth in the azimuth pass */
+  int32_t pass_b_depths;  /* depths per workgroup                       */
+  size_t device_bytes;    /* what pe3d_footprint reports                */
+} pe3d_info;
+pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info);
+
+/* Static string for a status code. */
+const char* pe3d_strerror(pe3d_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PE3D_H */

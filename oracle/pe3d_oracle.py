@@ -30,7 +30,7 @@ ETA = 1.0 / (40.0 * math.pi * math.log10(math.e))
 
 __all__ = [
     "ETA", "Setup", "setup", "is_periodic", "interp_ssp", "interp_bathy",
-    "thomas", "periodic_thomas_sm", "apply_tridiag", "y_apply", "x_apply",
+    "thomas", "periodic_thomas_sm", "apply_tridiag", "d_theta", "y_apply", "x_apply",
     "step", "march", "starter", "tl", "rel_l2",
 ]
 

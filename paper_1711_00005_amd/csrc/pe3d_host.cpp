@@ -1,0 +1,782 @@
+// Host runtime of the PE range march: argument validation, the FP64
+// coefficient builder and depth-system factorisation, kernel shape choice,
+// the plain per-problem march and the batched march with hipGraph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <list>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "pe3d.h"
+#include "pe3d_internal.h"
+
+using namespace pe3d;
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+// k = k_r (1 + i*eta*a) for an attenuation of a dB per wavelength, since
+// a = 20 log10(e) k_i lambda
+const double kEta = 1.0 / (40.0 * kPi * std::log10(std::exp(1.0)));
+
+bool is_fin(double x) { return std::isfinite(x); }
+bool is_periodic(double width) { return width >= 2.0 * kPi * (1.0 - 1e-12); }
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// ------------------------------------------------------------------ validation
+pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) {
+  if (!e || !g || !f) return PE3D_EINVAL;
+  if (!is_fin(f->f_hz) || f->f_hz <= 0.0) return PE3D_EINVAL;
+  if (!is_fin(e->c0) || e->c0 <= 0.0) return PE3D_EINVAL;
+  if (e->n_ssp < 1 || !e->ssp_z || !e->ssp_c) return PE3D_EINVAL;
+  for (int i = 0; i < e->n_ssp; ++i) {
+    if (!is_fin(e->ssp_z[i]) || !is_fin(e->ssp_c[i]) || e->ssp_c[i] <= 0.0) return PE3D_EINVAL;
+    if (i > 0 && !(e->ssp_z[i] > e->ssp_z[i - 1])) return PE3D_EINVAL;
+  }
+  if (!is_fin(e->rho_w) || e->rho_w <= 0.0 || !is_fin(e->atten_w) || e->atten_w < 0.0) return PE3D_EINVAL;
+  if (!is_fin(e->c_b) || e->c_b <= 0.0 || !is_fin(e->rho_b) || e->rho_b <= 0.0 ||
+      !is_fin(e->atten_b) || e->atten_b < 0.0)
+    return PE3D_EINVAL;
+  if (e->n_bathy < 1 || !e->bathy_theta || !e->bathy_depth) return PE3D_EINVAL;
+  for (int i = 0; i < e->n_bathy; ++i) {
+    if (!is_fin(e->bathy_theta[i]) || !is_fin(e->bathy_depth[i])) return PE3D_EINVAL;
+    if (i > 0 && !(e->bathy_theta[i] > e->bathy_theta[i - 1])) return PE3D_EINVAL;
+  }
+  if (e->n_bathy > 1 && !(e->bathy_theta[e->n_bathy - 1] - e->bathy_theta[0] < 2.0 * kPi))
+    return PE3D_EINVAL;
+  if (!is_fin(e->zmax) || e->zmax <= 0.0) return PE3D_EINVAL;
+  if (e->floor != PE3D_FLOOR_PRESSURE_RELEASE && e->floor != PE3D_FLOOR_RIGID) return PE3D_EINVAL;
+  if (g->nz < 2) return PE3D_EINVAL;
+  if (!is_fin(g->theta0) || !is_fin(g->width) || g->width <= 0.0) return PE3D_EINVAL;
+  if (is_periodic(g->width) ? g->ntheta < 3 : g->ntheta < 1) return PE3D_EINVAL;
+  if (!is_fin(g->dr) || g->dr <= 0.0 || !is_fin(g->r0) || g->r0 < 0.0) return PE3D_EINVAL;
+  if (g->precision != PE3D_C64 && g->precision != PE3D_C128) return PE3D_EINVAL;
+  if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 2048)) return PE3D_EUNSUPPORTED;
+  if (g->precision == PE3D_C128 && (g->nz > 2048 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
+  return PE3D_OK;
+}
+
+// ------------------------------------------------------------------ medium
+double interp_ssp(const pe3d_env& e, double z) {
+  const int n = e.n_ssp;
+  if (n == 1 || z <= e.ssp_z[0]) return e.ssp_c[0];
+  if (z >= e.ssp_z[n - 1]) return e.ssp_c[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (e.ssp_z[mid] <= z) lo = mid;
+    else hi = mid;
+  }
+  // same evaluation order as the usual linear-interpolation formula:
+  // slope * (z - z_lo) + c_lo
+  double slope = (e.ssp_c[hi] - e.ssp_c[lo]) / (e.ssp_z[hi] - e.ssp_z[lo]);
+  return slope * (z - e.ssp_z[lo]) + e.ssp_c[lo];
+}
+
+double interp_bathy(const pe3d_env& e, double th) {
+  const int n = e.n_bathy;
+  if (n == 1) return e.bathy_depth[0];
+  const double t0 = e.bathy_theta[0];
+  double md = std::fmod(th - t0, 2.0 * kPi);
+  if (md < 0.0) md += 2.0 * kPi;
+  const double t = t0 + md;
+  // segment i covers [theta_i, theta_{i+1}); the last one wraps to theta_0 + 2 pi
+  for (int i = 0; i < n; ++i) {
+    double a = e.bathy_theta[i];
+    double b = (i + 1 < n) ? e.bathy_theta[i + 1] : t0 + 2.0 * kPi;
+    if (t >= a && t < b) {
+      double da = e.bathy_depth[i];
+      double db = (i + 1 < n) ? e.bathy_depth[i + 1] : e.bathy_depth[0];
+      if (t == a) return da;
+      double slope = (db - da) / (b - a);
+      return slope * (t - a) + da;
+    }
+  }
+  return e.bathy_depth[0];
+}
+
+// FP64 problem description built on the host
+struct Built {
+  int N = 0, NT = 0, prec = 0, periodic = 0, rigid = 0;
+  double k0 = 0, dz = 0, dth = 0, h = 0;
+  cd qb, bp, bm;
+  std::vector<cd> qw, pw, pb;
+  std::vector<int> k;
+  std::vector<std::array<cd, 12>> blk;
+  int lpc = 0, ma = 0, maxm_a = 0, ntile_a = 0;
+  int nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
+};
+
+
+// Kernel shapes (see pe3d_kernels.hip): pass A uses L lanes per column with M
+// rows per lane; pass B uses nc azimuth chunks of mb nodes times td depths.
+pe3d_status choose_shapes(Built& b) {
+  const int N = b.N, NT = b.NT;
+  const int cands_a64[3] = {16, 32, 64}, cands_a128[3] = {8, 16, 32};
+  const int* ca = b.prec ? cands_a128 : cands_a64;
+  b.maxm_a = 0;
+  for (int i = 0; i < 3; ++i)
+    if (64 * ca[i] >= N) { b.maxm_a = ca[i]; break; }
+  if (!b.maxm_a) return PE3D_EUNSUPPORTED;
+  b.lpc = std::min(64, next_pow2((N + b.maxm_a - 1) / b.maxm_a));
+  b.ma = (N + b.lpc - 1) / b.lpc;
+  const int cpw = 64 / b.lpc;
+  b.ntile_a = (NT + cpw - 1) / cpw;
+
+  const int target = b.prec ? 8 : 16;
+  const int mmax = b.prec ? 16 : 32;
+  int nc = std::min(32, next_pow2((NT + target - 1) / target));
+  int mb = (NT + nc - 1) / nc;
+  if (mb > mmax) {
+    nc = 64;
+    mb = (NT + nc - 1) / nc;
+  }
+  if (mb > mmax) return PE3D_EUNSUPPORTED;
+  b.td = kPassBThreads / nc;
+  b.nc = (NT + mb - 1) / mb;  // every chunk non-empty
+  b.mb = mb;
+  const int cands_b64[3] = {8, 16, 32}, cands_b128[3] = {4, 8, 16};
+  const int* cb = b.prec ? cands_b128 : cands_b64;
+  b.maxm_b = 0;
+  for (int i = 0; i < 3; ++i)
+    if (cb[i] >= mb) { b.maxm_b = cb[i]; break; }
+  if (!b.maxm_b) return PE3D_EUNSUPPORTED;
+  b.ntile_b = (N + b.td - 1) / b.td;
+  return PE3D_OK;
+}
+
+// Build the medium, the depth operator X and the factorisation of
+// [I + beta_- X] (Eqs. (4), (5), (7)).  The medium is water above D(theta)
+// and a homogeneous half-space below, so every column equals the all-water
+// column above its interface rows and the all-bottom column below them; the
+// shared pivots of those two columns (top-down and bottom-up) plus a 2x2
+// interface block per column factor every depth system exactly.
+pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Built& b) {
+  const int N = g.nz, NT = g.ntheta;
+  b.N = N;
+  b.NT = NT;
+  b.prec = g.precision;
+  b.rigid = e.floor == PE3D_FLOOR_RIGID;
+  b.periodic = is_periodic(g.width);
+  b.k0 = 2.0 * kPi * f.f_hz / e.c0;
+  b.dz = b.rigid ? e.zmax / N : e.zmax / (N + 1);
+  b.dth = b.periodic ? 2.0 * kPi / NT : g.width / (NT + 1);
+  b.h = 1.0 / ((b.k0 * b.dz) * (b.k0 * b.dz));
+  b.bp = cd(1.0, b.k0 * g.dr) / 4.0;
+  b.bm = cd(1.0, -b.k0 * g.dr) / 4.0;
+  const double h = b.h;
+  const cd bm = b.bm;
+  auto nsq = [&](double c, double a) {
+    cd n = cd(1.0, kEta * a);
+    return (e.c0 / c) * (e.c0 / c) * n * n - 1.0;
+  };
+  b.qb = nsq(e.c_b, e.atten_b);
+  b.qw.resize(N);
+  for (int l = 0; l < N; ++l) b.qw[l] = nsq(interp_ssp(e, (l + 1) * b.dz), e.atten_w);
+
+  // all-water and all-bottom columns: X diagonals with uniform density
+  auto col_x = [&](int l, cd q, cd& xl, cd& xd, cd& xu) {
+    xl = (l == 0) ? 0.0 : h;
+    xu = (l == N - 1) ? 0.0 : h;
+    xd = q - 2.0 * h;
+    if (l == N - 1 && b.rigid) xl = 2.0 * h;
+  };
+  // top-down pivots of the all-water column
+  b.pw.assign(N, 0.0);
+  std::vector<cd> dw(N);
+  {
+    cd cprev = 0.0;
+    for (int l = 0; l < N; ++l) {
+      cd xl, xd, xu;
+      col_x(l, b.qw[l], xl, xd, xu);
+      cd a = bm * xl, bb = 1.0 + bm * xd, c = bm * xu;
+      dw[l] = (l == 0) ? bb : bb - a * cprev / dw[l - 1];
+      cprev = c;
+      b.pw[l] = 1.0 / dw[l];
+    }
+  }
+  // bottom-up pivots of the all-bottom column
+  b.pb.assign(N, 0.0);
+  std::vector<cd> eb(N);
+  {
+    cd anext = 0.0;
+    for (int l = N - 1; l >= 0; --l) {
+      cd xl, xd, xu;
+      col_x(l, b.qb, xl, xd, xu);
+      cd a = bm * xl, bb = 1.0 + bm * xd, c = bm * xu;
+      eb[l] = (l == N - 1) ? bb : bb - c * anext / eb[l + 1];
+      anext = a;
+      b.pb[l] = 1.0 / eb[l];
+    }
+  }
+  // per-column interface rows
+  b.k.resize(NT);
+  b.blk.resize(NT);
+  double maxb = 0.0, minpiv = 1e300;
+  int kmin = N, kmax = 0;
+  std::vector<double> rho(N);
+  for (int m = 0; m < NT; ++m) {
+    double th = b.periodic ? g.theta0 + m * b.dth : g.theta0 - 0.5 * g.width + (m + 1) * b.dth;
+    double D = interp_bathy(e, th);
+    int nw = 0;
+    while (nw < N && (nw + 1) * b.dz <= D) ++nw;  // z_l = (l+1) dz <= D
+    int k = std::min(std::max(nw - 1, 0), N - 2);
+    b.k[m] = k;
+    kmin = std::min(kmin, k);
+    kmax = std::max(kmax, k);
+    // the column's own X rows k-1..k+2 from the density-weighted operator
+    auto rho_at = [&](int l) {
+      l = std::min(std::max(l, 0), N - 1);  // ghost densities
+      return l < nw ? e.rho_w : e.rho_b;
+    };
+    auto q_at = [&](int l) { return l < nw ? b.qw[l] : b.qb; };
+    auto xrow = [&](int l, cd& xl, cd& xd, cd& xu) {
+      double rm = rho_at(l - 1), r = rho_at(l), rp = rho_at(l + 1);
+      double lm = 2.0 * r / (rm + r), lp = 2.0 * r / (r + rp);
+      xl = (l == 0) ? 0.0 : h * lm;
+      xd = q_at(l) - h * (lm + lp);
+      xu = h * lp;
+      if (l == N - 1) {
+        if (b.rigid) xl += xu;
+        xu = 0.0;
+      }
+    };
+    cd xl0, xd0, xu0, xl1, xd1, xu1;
+    xrow(k, xl0, xd0, xu0);
+    xrow(k + 1, xl1, xd1, xu1);
+    cd fk = 0.0, gk1 = 0.0;
+    cd P = 1.0 + bm * xd0, Q = 1.0 + bm * xd1;
+    if (k >= 1) {
+      cd pxl, pxd, pxu;
+      xrow(k - 1, pxl, pxd, pxu);  // a water row: its upper coefficient is h
+      fk = -(bm * xl0) / dw[k - 1];
+      P += fk * (bm * pxu);
+    }
+    if (k + 2 <= N - 1) {
+      cd nxl, nxd, nxu;
+      xrow(k + 2, nxl, nxd, nxu);  // a bottom row
+      gk1 = -(bm * xu1) / eb[k + 2];
+      Q += gk1 * (bm * nxl);
+    }
+    cd c01 = bm * xu0, c10 = bm * xl1;
+    cd det = P * Q - c01 * c10;
+    maxb = std::max({maxb, std::abs(P), std::abs(Q)});
+    minpiv = std::min(minpiv, std::abs(det) / std::max(std::abs(P), std::abs(Q)));
+    if (det == 0.0 || !std::isfinite(std::abs(det))) return PE3D_EUNSUPPORTED;
+    cd id = 1.0 / det;
+    b.blk[m] = {xl0, xd0, xu0, xl1, xd1, xu1, fk, gk1, Q * id, -c01 * id, -c10 * id, P * id};
+  }
+  // pivots actually used: water rows < kmax, bottom rows > kmin + 1
+  for (int l = 0; l < kmax; ++l) {
+    minpiv = std::min(minpiv, std::abs(dw[l]));
+    maxb = std::max(maxb, std::abs(1.0 + bm * (b.qw[l] - 2.0 * h)));
+  }
+  for (int l = kmin + 2; l < N; ++l) {
+    minpiv = std::min(minpiv, std::abs(eb[l]));
+    maxb = std::max(maxb, std::abs(1.0 + bm * (b.qb - 2.0 * h)));
+  }
+  if (!(minpiv > 1e-10 * maxb)) return PE3D_EUNSUPPORTED;
+  return choose_shapes(b);
+}
+
+size_t table_bytes(const Built& b) {
+  const size_t csz = b.prec ? 16 : 8;
+  size_t n = 0;
+  n += 3 * (size_t)b.N * csz;             // qw, pw, pb
+  n += (size_t)b.NT * 12 * csz;           // column blocks
+  n += (size_t)b.NT * sizeof(int);        // kcol
+  n = (n + 255) & ~size_t(255);
+  n += 256;                               // step counter
+  return n;
+}
+size_t field_bytes(const Built& b) { return (size_t)b.N * b.NT * (b.prec ? 16 : 8); }
+
+template <typename R>
+void pack(const std::vector<cd>& v, std::vector<unsigned char>& out, size_t off) {
+  R* p = reinterpret_cast<R*>(out.data() + off);
+  for (size_t i = 0; i < v.size(); ++i) {
+    p[2 * i] = R(v[i].real());
+    p[2 * i + 1] = R(v[i].imag());
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+
+
+struct pe3d_handle_s {
+  int prec = 0;
+  int maxm_a = 0, maxm_b = 0;
+  ProbDesc desc{};
+  void* d_tables = nullptr;
+  void* d_scr = nullptr;
+  long long* d_j = nullptr;
+  long long j = 0;
+  size_t bytes = 0;
+  int device = 0;
+  double r0 = 0, dr = 0;
+};
+
+namespace {
+
+struct BatchPlan {
+  std::vector<uintptr_t> key;
+  std::vector<pe3d_handle> handles;
+  int prec = 0;
+  int maxsteps = 0;
+  void* d_mem = nullptr;               // descs, items, jdev pointers, adds
+  ProbDesc* d_descs = nullptr;
+  long long** d_jdevs = nullptr;
+  int* d_adds = nullptr;
+  int n = 0;
+  struct Class {
+    int maxm;
+    WorkItem* d_items;
+    std::vector<int> nitems_at;        // active items at step k (problems sorted by steps)
+  };
+  std::vector<Class> a, b;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  ~BatchPlan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_mem) (void)hipFree(d_mem);
+  }
+};
+
+std::mutex g_mu;
+std::map<std::vector<uintptr_t>, std::unique_ptr<BatchPlan>> g_plans;
+std::list<std::vector<uintptr_t>> g_lru;  // most recent first
+constexpr size_t kMaxPlans = 64;
+
+void touch(const std::vector<uintptr_t>& key) {
+  for (auto it = g_lru.begin(); it != g_lru.end(); ++it)
+    if (*it == key) {
+      g_lru.erase(it);
+      break;
+    }
+  g_lru.push_front(key);
+}
+
+// Caller holds g_mu.  A plan's device tables may still be read by enqueued
+// work, so the device is drained before the oldest plan is freed.
+void evict_if_full() {
+  if (g_plans.size() < kMaxPlans) return;
+  (void)hipDeviceSynchronize();
+  while (g_plans.size() >= kMaxPlans && !g_lru.empty()) {
+    g_plans.erase(g_lru.back());
+    g_lru.pop_back();
+  }
+}
+
+void drop_plans_of(pe3d_handle h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto it = g_plans.begin(); it != g_plans.end();) {
+    auto& hs = it->second->handles;
+    if (std::find(hs.begin(), hs.end(), h) != hs.end()) {
+      g_lru.remove(it->first);
+      it = g_plans.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pe3d_strerror(pe3d_status s) {
+  switch (s) {
+    case PE3D_OK: return "ok";
+    case PE3D_EINVAL: return "invalid argument";
+    case PE3D_ENOMEM: return "out of memory";
+    case PE3D_EDEVICE: return "HIP runtime or kernel launch error";
+    case PE3D_EUNSUPPORTED: return "outside the supported sizes or a vanishing depth pivot";
+    case PE3D_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
+                           size_t* bytes) {
+  if (!bytes) return PE3D_EINVAL;
+  pe3d_status st = validate(env, grid, freq);
+  if (st != PE3D_OK) return st;
+  Built b;
+  b.N = grid->nz;
+  b.NT = grid->ntheta;
+  b.prec = grid->precision;
+  st = choose_shapes(b);
+  if (st != PE3D_OK) return st;
+  *bytes = table_bytes(b) + field_bytes(b);
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
+                        pe3d_handle* out) {
+  if (!out) return PE3D_EINVAL;
+  *out = nullptr;
+  pe3d_status st = validate(env, grid, freq);
+  if (st != PE3D_OK) return st;
+  Built b;
+  st = build(*env, *grid, *freq, b);
+  if (st != PE3D_OK) return st;
+
+  // host image of the coefficient tables
+  const size_t csz = b.prec ? 16 : 8;
+  const size_t tb = table_bytes(b);
+  std::vector<unsigned char> img(tb, 0);
+  const size_t o_qw = 0, o_pw = o_qw + b.N * csz, o_pb = o_pw + b.N * csz;
+  const size_t o_blk = o_pb + b.N * csz, o_k = o_blk + (size_t)b.NT * 12 * csz;
+  const size_t o_j = tb - 256;
+  std::vector<cd> blkflat;
+  blkflat.reserve((size_t)b.NT * 12);
+  for (auto& a : b.blk)
+    for (auto& z : a) blkflat.push_back(z);
+  if (b.prec) {
+    pack<double>(b.qw, img, o_qw);
+    pack<double>(b.pw, img, o_pw);
+    pack<double>(b.pb, img, o_pb);
+    pack<double>(blkflat, img, o_blk);
+  } else {
+    pack<float>(b.qw, img, o_qw);
+    pack<float>(b.pw, img, o_pw);
+    pack<float>(b.pb, img, o_pb);
+    pack<float>(blkflat, img, o_blk);
+  }
+  std::memcpy(img.data() + o_k, b.k.data(), b.NT * sizeof(int));
+
+  pe3d_handle h = new (std::nothrow) pe3d_handle_s();
+  if (!h) return PE3D_ENOMEM;
+  h->prec = b.prec;
+  h->maxm_a = b.maxm_a;
+  h->maxm_b = b.maxm_b;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return PE3D_EDEVICE;
+  }
+  if (hipMalloc(&h->d_tables, tb) != hipSuccess) {
+    delete h;
+    return PE3D_ENOMEM;
+  }
+  if (hipMalloc(&h->d_scr, field_bytes(b)) != hipSuccess) {
+    (void)hipFree(h->d_tables);
+    delete h;
+    return PE3D_ENOMEM;
+  }
+  if (hipMemcpy(h->d_tables, img.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(h->d_tables);
+    (void)hipFree(h->d_scr);
+    delete h;
+    return PE3D_EDEVICE;
+  }
+  unsigned char* base = static_cast<unsigned char*>(h->d_tables);
+  h->d_j = reinterpret_cast<long long*>(base + o_j);
+  h->bytes = tb + field_bytes(b);
+  h->r0 = grid->r0;
+  h->dr = grid->dr;
+
+  ProbDesc& d = h->desc;
+  d.u = nullptr;
+  d.scr = h->d_scr;
+  d.jdev = h->d_j;
+  d.nsteps = 0;
+  d.nz = b.N;
+  d.nth = b.NT;
+  d.periodic = b.periodic;
+  d.rigid = b.rigid;
+  d.lpc = b.lpc;
+  d.ma = b.ma;
+  d.ntile_a = b.ntile_a;
+  d.qw = base + o_qw;
+  d.pw = base + o_pw;
+  d.pb = base + o_pb;
+  d.blk = base + o_blk;
+  d.kcol = reinterpret_cast<const int*>(base + o_k);
+  d.h = b.h;
+  d.qb_re = b.qb.real();
+  d.qb_im = b.qb.imag();
+  d.bp_re = b.bp.real();
+  d.bp_im = b.bp.imag();
+  d.bm_re = b.bm.real();
+  d.bm_im = b.bm.imag();
+  d.nc = b.nc;
+  d.td = b.td;
+  d.mb = b.mb;
+  d.ntile_b = b.ntile_b;
+  d.k0 = b.k0;
+  d.dr = grid->dr;
+  d.r0 = grid->r0;
+  d.dth = b.dth;
+  d.dz = b.dz;
+  *out = h;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_destroy(pe3d_handle h) {
+  if (!h) return PE3D_OK;
+  drop_plans_of(h);
+  (void)hipFree(h->d_scr);
+  (void)hipFree(h->d_tables);
+  delete h;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_get_step(pe3d_handle h, int64_t* j, double* r) {
+  if (!h) return PE3D_EINVAL;
+  if (j) *j = h->j;
+  if (r) *r = h->r0 + double(h->j) * h->dr;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_set_step(pe3d_handle h, int64_t j) {
+  if (!h || j < 0) return PE3D_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return PE3D_EDEVICE;
+  long long jj = j;
+  if (hipMemcpy(h->d_j, &jj, sizeof(jj), hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
+  h->j = j;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info) {
+  if (!h || !info) return PE3D_EINVAL;
+  const ProbDesc& d = h->desc;
+  info->nz = d.nz;
+  info->ntheta = d.nth;
+  info->periodic = d.periodic;
+  info->precision = h->prec;
+  info->k0 = d.k0;
+  info->dz = d.dz;
+  info->dtheta = d.dth;
+  info->dr = d.dr;
+  info->r0 = d.r0;
+  info->pass_a_lanes = d.lpc;
+  info->pass_a_chunk = d.ma;
+  info->pass_b_chunks = d.nc;
+  info->pass_b_depths = d.td;
+  info->device_bytes = h->bytes;
+  return PE3D_OK;
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream) {
+  if (!h || !u_dev || nsteps < 0 || !aligned16(u_dev)) return PE3D_EINVAL;
+  if (nsteps == 0) return PE3D_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ProbDesc d = h->desc;
+  d.u = u_dev;
+  d.nsteps = nsteps;
+  for (int k = 0; k < nsteps; ++k) {
+    if (launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, st) != hipSuccess)
+      return PE3D_EDEVICE;
+    if (launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, st) != hipSuccess)
+      return PE3D_EDEVICE;
+  }
+  if (launch_advance(nullptr, nullptr, 0, h->d_j, nsteps, st) != hipSuccess) return PE3D_EDEVICE;
+  h->j += nsteps;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream) {
+  if (!h || !u_dev || !is_fin(zs) || zs < 0.0 || !aligned16(u_dev)) return PE3D_EINVAL;
+  if (launch_starter(h->prec, h->desc, zs, u_dev, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return PE3D_EDEVICE;
+  return PE3D_OK;
+}
+
+pe3d_status pe3d_tl(pe3d_handle h, const void* u_dev, float* tl_dev, void* stream) {
+  if (!h || !u_dev || !tl_dev || !aligned16(u_dev)) return PE3D_EINVAL;
+  if (launch_tl(h->prec, h->desc, u_dev, tl_dev, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return PE3D_EDEVICE;
+  return PE3D_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+namespace {
+
+pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
+                       BatchPlan& P) {
+  // problems sorted by steps (descending) so that the problems still stepping
+  // at step k are a prefix of every item list
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i)
+    if (nsteps[i] > 0) order.push_back(i);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nsteps[a] > nsteps[b]; });
+  const int np = int(order.size());
+  P.n = np;
+  P.prec = hs[0]->prec;
+  P.maxsteps = np ? nsteps[order[0]] : 0;
+  std::vector<ProbDesc> descs(np);
+  std::vector<long long*> jdevs(np);
+  std::vector<int> adds(np);
+  std::map<int, std::vector<WorkItem>> ia, ib;
+  std::map<int, std::vector<int>> ia_steps, ib_steps;  // steps of the problem of each item
+  for (int p = 0; p < np; ++p) {
+    pe3d_handle h = hs[order[p]];
+    descs[p] = h->desc;
+    descs[p].u = u[order[p]];
+    descs[p].nsteps = nsteps[order[p]];
+    jdevs[p] = h->d_j;
+    adds[p] = nsteps[order[p]];
+    for (int t = 0; t < h->desc.ntile_a; ++t) {
+      ia[h->maxm_a].push_back({p, t});
+      ia_steps[h->maxm_a].push_back(nsteps[order[p]]);
+    }
+    for (int t = 0; t < h->desc.ntile_b; ++t) {
+      ib[h->maxm_b].push_back({p, t});
+      ib_steps[h->maxm_b].push_back(nsteps[order[p]]);
+    }
+  }
+  size_t nitems = 0;
+  for (auto& kv : ia) nitems += kv.second.size();
+  for (auto& kv : ib) nitems += kv.second.size();
+  size_t off_desc = 0;
+  size_t off_j = (off_desc + np * sizeof(ProbDesc) + 255) & ~size_t(255);
+  size_t off_add = (off_j + np * sizeof(long long*) + 255) & ~size_t(255);
+  size_t off_it = (off_add + np * sizeof(int) + 255) & ~size_t(255);
+  size_t total = off_it + nitems * sizeof(WorkItem) + 256;
+  std::vector<unsigned char> img(total, 0);
+  std::memcpy(img.data() + off_desc, descs.data(), np * sizeof(ProbDesc));
+  std::memcpy(img.data() + off_j, jdevs.data(), np * sizeof(long long*));
+  std::memcpy(img.data() + off_add, adds.data(), np * sizeof(int));
+  if (hipMalloc(&P.d_mem, total) != hipSuccess) return PE3D_ENOMEM;
+  unsigned char* base = static_cast<unsigned char*>(P.d_mem);
+  P.d_descs = reinterpret_cast<ProbDesc*>(base + off_desc);
+  P.d_jdevs = reinterpret_cast<long long**>(base + off_j);
+  P.d_adds = reinterpret_cast<int*>(base + off_add);
+  size_t cur = off_it;
+  auto emit = [&](std::map<int, std::vector<WorkItem>>& src, std::map<int, std::vector<int>>& stp,
+                  std::vector<BatchPlan::Class>& dst) {
+    for (auto& kv : src) {
+      BatchPlan::Class c;
+      c.maxm = kv.first;
+      c.d_items = reinterpret_cast<WorkItem*>(base + cur);
+      std::memcpy(img.data() + cur, kv.second.data(), kv.second.size() * sizeof(WorkItem));
+      cur += kv.second.size() * sizeof(WorkItem);
+      const auto& s = stp[kv.first];
+      c.nitems_at.resize(P.maxsteps);
+      for (int k = 0; k < P.maxsteps; ++k) {
+        // s is non-increasing: count items whose problem has more than k steps
+        int cnt = int(std::lower_bound(s.begin(), s.end(), k, [](int a, int v) { return a > v; }) - s.begin());
+        c.nitems_at[k] = cnt;
+      }
+      dst.push_back(c);
+    }
+  };
+  emit(ia, ia_steps, P.a);
+  emit(ib, ib_steps, P.b);
+  if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
+  return PE3D_OK;
+}
+
+pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
+  for (int k = 0; k < P.maxsteps; ++k) {
+    for (auto& c : P.a) {
+      int ni = c.nitems_at[k];
+      if (ni > 0 && launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+        return PE3D_EDEVICE;
+    }
+    for (auto& c : P.b) {
+      int ni = c.nitems_at[k];
+      if (ni > 0 && launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+        return PE3D_EDEVICE;
+    }
+  }
+  if (launch_advance(P.d_jdevs, P.d_adds, P.n, nullptr, 0, st) != hipSuccess) return PE3D_EDEVICE;
+  return PE3D_OK;
+}
+
+}  // namespace
+
+extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const int32_t* nsteps,
+                                        void* const* u_devs, int32_t use_graph, void* stream) {
+  if (!hs || !nsteps || !u_devs || n < 1) return PE3D_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || nsteps[i] < 0 || !u_devs[i] || !aligned16(u_devs[i])) return PE3D_EINVAL;
+    if (hs[i]->prec != hs[0]->prec) return PE3D_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i] || u_devs[k] == u_devs[i]) return PE3D_EINVAL;
+  }
+  bool any = false;
+  for (int i = 0; i < n; ++i) any = any || nsteps[i] > 0;
+  if (!any) return PE3D_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  std::vector<uintptr_t> key;
+  key.reserve(3 * n + 1);
+  for (int i = 0; i < n; ++i) {
+    key.push_back(reinterpret_cast<uintptr_t>(hs[i]));
+    key.push_back(reinterpret_cast<uintptr_t>(u_devs[i]));
+    key.push_back(uintptr_t(uint32_t(nsteps[i])));
+  }
+  BatchPlan* plan = nullptr;
+  std::unique_ptr<BatchPlan> fresh;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+      plan = it->second.get();
+      touch(key);
+    }
+  }
+  if (!plan) {
+    fresh.reset(new (std::nothrow) BatchPlan());
+    if (!fresh) return PE3D_ENOMEM;
+    fresh->key = key;
+    fresh->handles.assign(hs, hs + n);
+    pe3d_status s = build_plan(hs, n, nsteps, u_devs, *fresh);
+    if (s != PE3D_OK) return s;
+    plan = fresh.get();
+    std::lock_guard<std::mutex> lk(g_mu);
+    evict_if_full();
+    g_plans[key] = std::move(fresh);
+    touch(key);
+  }
+  if (use_graph) {
+    if (!plan->exec) {
+      hipStream_t cap;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
+      pe3d_status s = PE3D_OK;
+      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
+      if (s == PE3D_OK) s = enqueue_plan(*plan, cap);
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
+      (void)hipStreamDestroy(cap);
+      if (s != PE3D_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+      }
+      plan->graph = g;
+      if (hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        plan->exec = nullptr;
+        return PE3D_EDEVICE;
+      }
+    }
+    if (hipGraphLaunch(plan->exec, st) != hipSuccess) return PE3D_EDEVICE;
+  } else {
+    pe3d_status s = enqueue_plan(*plan, st);
+    if (s != PE3D_OK) return s;
+  }
+  for (int i = 0; i < n; ++i) hs[i]->j += nsteps[i];
+  return PE3D_OK;
+}

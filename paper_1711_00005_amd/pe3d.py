@@ -1,0 +1,293 @@
+"""Python binding of libpe3d.so (include/pe3d.h): argument marshalling only.
+
+Every step of the march runs in the HIP library.  There is no fallback: if the
+shared library is missing this module raises at import.  PyTorch is used only
+to hold device fields and to name the current HIP stream.
+
+The module-level functions carry the C names (pe3d_create, pe3d_march, ...)
+and return/raise on the C status codes; `Pe3d` is a small owning wrapper.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpe3d.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1711_00005_amd.build_lib` "
+        "(the PE march has no CPU fallback)")
+
+_lib = ct.CDLL(LIB_PATH)
+
+PE3D_OK = 0
+PE3D_EINVAL = -1
+PE3D_ENOMEM = -2
+PE3D_EDEVICE = -3
+PE3D_EUNSUPPORTED = -4
+PE3D_ESTATE = -5
+PE3D_FLOOR_PRESSURE_RELEASE = 0
+PE3D_FLOOR_RIGID = 1
+PE3D_C64 = 0
+PE3D_C128 = 1
+
+EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
+            "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_get_info",
+            "pe3d_strerror")
+
+
+class pe3d_env(ct.Structure):
+    _fields_ = [("c0", ct.c_double), ("n_ssp", ct.c_int32),
+                ("ssp_z", ct.POINTER(ct.c_double)), ("ssp_c", ct.POINTER(ct.c_double)),
+                ("rho_w", ct.c_double), ("atten_w", ct.c_double),
+                ("c_b", ct.c_double), ("rho_b", ct.c_double), ("atten_b", ct.c_double),
+                ("n_bathy", ct.c_int32),
+                ("bathy_theta", ct.POINTER(ct.c_double)), ("bathy_depth", ct.POINTER(ct.c_double)),
+                ("zmax", ct.c_double), ("floor", ct.c_int32)]
+
+
+class pe3d_grid(ct.Structure):
+    _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("theta0", ct.c_double),
+                ("width", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
+                ("precision", ct.c_int32)]
+
+
+class pe3d_freq(ct.Structure):
+    _fields_ = [("f_hz", ct.c_double)]
+
+
+class pe3d_info(ct.Structure):
+    _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("periodic", ct.c_int32),
+                ("precision", ct.c_int32), ("k0", ct.c_double), ("dz", ct.c_double),
+                ("dtheta", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
+                ("pass_a_lanes", ct.c_int32), ("pass_a_chunk", ct.c_int32),
+                ("pass_b_chunks", ct.c_int32), ("pass_b_depths", ct.c_int32),
+                ("device_bytes", ct.c_size_t)]
+
+
+_H = ct.c_void_p
+_lib.pe3d_create.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), ct.POINTER(pe3d_freq),
+                             ct.POINTER(_H)]
+_lib.pe3d_march.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_destroy.argtypes = [_H]
+_lib.pe3d_footprint.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid),
+                                ct.POINTER(pe3d_freq), ct.POINTER(ct.c_size_t)]
+_lib.pe3d_get_step.argtypes = [_H, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_double)]
+_lib.pe3d_set_step.argtypes = [_H, ct.c_int64]
+_lib.pe3d_starter.argtypes = [_H, ct.c_double, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_march_batch.argtypes = [ct.POINTER(_H), ct.c_int32, ct.POINTER(ct.c_int32),
+                                  ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p]
+_lib.pe3d_tl.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_get_info.argtypes = [_H, ct.POINTER(pe3d_info)]
+_lib.pe3d_strerror.argtypes = [ct.c_int]
+_lib.pe3d_strerror.restype = ct.c_char_p
+for _n in EXPORTED[:-1]:
+    getattr(_lib, _n).restype = ct.c_int
+
+
+class Pe3dError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {pe3d_strerror(status)} ({status})")
+
+
+def _check(st: int, where: str) -> None:
+    if st != PE3D_OK:
+        raise Pe3dError(st, where)
+
+
+def pe3d_strerror(status: int) -> str:
+    return _lib.pe3d_strerror(int(status)).decode()
+
+
+def _darr(vals):
+    vals = [float(v) for v in vals]
+    return (ct.c_double * max(1, len(vals)))(*vals)
+
+
+def make_env(env):
+    """ctypes pe3d_env from any object with the Env attributes; returns the
+    struct and the arrays it points to (keep both alive across the call)."""
+    keep = [_darr(env.ssp_z), _darr(env.ssp_c), _darr(env.bathy_theta), _darr(env.bathy_depth)]
+    s = pe3d_env(c0=env.c0, n_ssp=len(env.ssp_z), ssp_z=keep[0], ssp_c=keep[1],
+                 rho_w=env.rho_w, atten_w=env.atten_w, c_b=env.c_b, rho_b=env.rho_b,
+                 atten_b=env.atten_b, n_bathy=len(env.bathy_theta), bathy_theta=keep[2],
+                 bathy_depth=keep[3], zmax=env.zmax, floor=int(env.floor))
+    return s, keep
+
+
+def make_grid(grid):
+    return pe3d_grid(nz=int(grid.nz), ntheta=int(grid.ntheta), theta0=float(grid.theta0),
+                     width=float(grid.width), dr=float(grid.dr), r0=float(getattr(grid, "r0", 0.0)),
+                     precision=int(getattr(grid, "precision", PE3D_C64)))
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _field_ptr(u, nz: int, nth: int, prec: int) -> int:
+    import torch
+    want = torch.complex128 if prec == PE3D_C128 else torch.complex64
+    if not (isinstance(u, torch.Tensor) and u.is_cuda and u.dtype == want
+            and u.is_contiguous() and tuple(u.shape) == (nth, nz)):
+        raise ValueError(f"field must be a contiguous CUDA {want} tensor of shape ({nth}, {nz})")
+    return u.data_ptr()
+
+
+# ----------------------------------------------------------------------- C calls
+def pe3d_footprint(env, grid, f_hz: float) -> int:
+    e, keep = make_env(env)
+    g = make_grid(grid)
+    out = ct.c_size_t(0)
+    _check(_lib.pe3d_footprint(ct.byref(e), ct.byref(g), ct.byref(pe3d_freq(f_hz)), ct.byref(out)),
+           "pe3d_footprint")
+    return int(out.value)
+
+
+def pe3d_create(env, grid, f_hz: float) -> int:
+    e, keep = make_env(env)
+    g = make_grid(grid)
+    h = _H()
+    _check(_lib.pe3d_create(ct.byref(e), ct.byref(g), ct.byref(pe3d_freq(f_hz)), ct.byref(h)),
+           "pe3d_create")
+    return h.value
+
+
+def pe3d_create_status(env, grid, f_hz: float) -> int:
+    """Status of pe3d_create only (the handle, if any, is destroyed)."""
+    e, keep = make_env(env)
+    g = make_grid(grid)
+    h = _H()
+    st = _lib.pe3d_create(ct.byref(e), ct.byref(g), ct.byref(pe3d_freq(f_hz)), ct.byref(h))
+    if st == PE3D_OK:
+        _lib.pe3d_destroy(h)
+    return st
+
+
+def pe3d_destroy(h) -> None:
+    _check(_lib.pe3d_destroy(h), "pe3d_destroy")
+
+
+def pe3d_march(h, nsteps: int, u_ptr: int, stream_ptr) -> None:
+    _check(_lib.pe3d_march(h, int(nsteps), ct.c_void_p(u_ptr), ct.c_void_p(stream_ptr)), "pe3d_march")
+
+
+def pe3d_starter(h, zs: float, u_ptr: int, stream_ptr) -> None:
+    _check(_lib.pe3d_starter(h, float(zs), ct.c_void_p(u_ptr), ct.c_void_p(stream_ptr)),
+           "pe3d_starter")
+
+
+def pe3d_get_step(h):
+    j = ct.c_int64(0)
+    r = ct.c_double(0.0)
+    _check(_lib.pe3d_get_step(h, ct.byref(j), ct.byref(r)), "pe3d_get_step")
+    return int(j.value), float(r.value)
+
+
+def pe3d_set_step(h, j: int) -> None:
+    _check(_lib.pe3d_set_step(h, int(j)), "pe3d_set_step")
+
+
+def pe3d_get_info(h) -> pe3d_info:
+    info = pe3d_info()
+    _check(_lib.pe3d_get_info(h, ct.byref(info)), "pe3d_get_info")
+    return info
+
+
+def pe3d_tl(h, u_ptr: int, tl_ptr: int, stream_ptr) -> None:
+    _check(_lib.pe3d_tl(h, ct.c_void_p(u_ptr), ct.c_void_p(tl_ptr), ct.c_void_p(stream_ptr)), "pe3d_tl")
+
+
+def pe3d_march_batch(handles: Sequence[int], nsteps: Sequence[int], u_ptrs: Sequence[int],
+                     use_graph: bool, stream_ptr) -> None:
+    n = len(handles)
+    hs = (_H * n)(*handles)
+    ns = (ct.c_int32 * n)(*[int(s) for s in nsteps])
+    us = (ct.c_void_p * n)(*u_ptrs)
+    _check(_lib.pe3d_march_batch(hs, n, ns, us, int(bool(use_graph)), ct.c_void_p(stream_ptr)),
+           "pe3d_march_batch")
+
+
+# ----------------------------------------------------------------------- wrapper
+class Pe3d:
+    """Owning handle of one march (one frequency, one grid)."""
+
+    def __init__(self, env, grid, f_hz: float):
+        self.env, self.grid, self.f_hz = env, grid, float(f_hz)
+        self.nz, self.ntheta = int(grid.nz), int(grid.ntheta)
+        self.precision = int(getattr(grid, "precision", PE3D_C64))
+        self.h = pe3d_create(env, grid, f_hz)
+
+    def close(self) -> None:
+        if self.h:
+            pe3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.complex128 if self.precision == PE3D_C128 else torch.complex64
+
+    def new_field(self):
+        import torch
+        return torch.zeros((self.ntheta, self.nz), dtype=self.dtype, device="cuda")
+
+    def starter(self, zs: float, u=None, stream=None):
+        if u is None:
+            u = self.new_field()
+        pe3d_starter(self.h, zs, _field_ptr(u, self.nz, self.ntheta, self.precision), _stream_ptr(stream))
+        return u
+
+    def march(self, nsteps: int, u, stream=None):
+        pe3d_march(self.h, nsteps, _field_ptr(u, self.nz, self.ntheta, self.precision), _stream_ptr(stream))
+        return u
+
+    def tl(self, u, stream=None):
+        import torch
+        out = torch.empty((self.ntheta, self.nz), dtype=torch.float32, device=u.device)
+        pe3d_tl(self.h, _field_ptr(u, self.nz, self.ntheta, self.precision), out.data_ptr(),
+                _stream_ptr(stream))
+        return out
+
+    @property
+    def step(self) -> int:
+        return pe3d_get_step(self.h)[0]
+
+    @property
+    def range_m(self) -> float:
+        return pe3d_get_step(self.h)[1]
+
+    def set_step(self, j: int) -> None:
+        pe3d_set_step(self.h, j)
+
+    def info(self) -> pe3d_info:
+        return pe3d_get_info(self.h)
+
+
+def march_batch(marches: Sequence[Pe3d], nsteps, fields, use_graph: bool = True, stream=None) -> None:
+    if isinstance(nsteps, int):
+        nsteps = [nsteps] * len(marches)
+    ptrs = [_field_ptr(u, m.nz, m.ntheta, m.precision) for m, u in zip(marches, fields)]
+    pe3d_march_batch([m.h for m in marches], nsteps, ptrs, use_graph, _stream_ptr(stream))

@@ -1,0 +1,96 @@
+"""CPU-only checks of the C ABI: the built library loads, exports every
+function include/pe3d.h declares, and rejects invalid arguments before any
+device call (so these run without a GPU)."""
+import ctypes as ct
+import math
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pe3d.h")
+LIB = os.path.join(ROOT, "paper_1711_00005_amd", "libpe3d.so")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pe3d_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not os.path.exists(LIB):
+        pytest.fail("libpe3d.so is not built (run __graft_entry__.build())")
+    import paper_1711_00005_amd.pe3d as _P
+    return _P
+
+
+def test_library_exports_every_declared_function(P):
+    lib = ct.CDLL(LIB)
+    names = declared_functions()
+    assert "pe3d_create" in names and "pe3d_march" in names and "pe3d_destroy" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(P.EXPORTED) == set(names)
+
+
+def test_strerror(P):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert P.pe3d_strerror(s)
+    assert P.pe3d_strerror(7) == "unknown status"
+
+
+def test_footprint_is_tables_plus_one_field(P):
+    p = W.config2()
+    b = P.pe3d_footprint(p.env, p.grid, p.f_hz)
+    field = 2048 * 512 * 8
+    assert field < b < field + 2 * 1024 * 1024
+    b128 = P.pe3d_footprint(p.env, W.Grid(nz=2048, ntheta=512, theta0=0, width=W.TWO_PI, dr=10,
+                                           precision=W.PREC_C128), p.f_hz)
+    assert b128 > 2 * field
+
+
+def _status(P, env, grid, f=100.0):
+    return P.pe3d_create_status(env, grid, f)
+
+
+def test_create_rejects_invalid_arguments_without_a_device(P):
+    env = W.wedge_env()
+    ok = dict(nz=64, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    bad_grids = [
+        dict(ok, nz=1), dict(ok, ntheta=2), dict(ok, dr=0.0), dict(ok, dr=float("nan")),
+        dict(ok, r0=-1.0), dict(ok, width=0.0), dict(ok, precision=7),
+    ]
+    for g in bad_grids:
+        assert _status(P, env, W.Grid(**g)) == P.PE3D_EINVAL, g
+    g = W.Grid(**ok)
+    assert _status(P, env, g, f=0.0) == P.PE3D_EINVAL
+    assert _status(P, env, g, f=float("inf")) == P.PE3D_EINVAL
+    from dataclasses import replace
+    for e in (replace(env, c0=0.0), replace(env, ssp_z=(10.0, 5.0), ssp_c=(1500.0, 1500.0)),
+              replace(env, rho_b=-1.0), replace(env, atten_b=-0.1), replace(env, floor=3),
+              replace(env, bathy_theta=(0.0, 7.0), bathy_depth=(10.0, 20.0)), replace(env, zmax=0.0)):
+        assert _status(P, e, g) == P.PE3D_EINVAL, e
+    # sector with one azimuth is valid; a periodic grid needs three
+    sec = W.Grid(nz=64, ntheta=1, theta0=0.0, width=math.radians(30), dr=10.0)
+    assert _status(P, env, sec) != P.PE3D_EINVAL
+
+
+def test_create_reports_unsupported_sizes(P):
+    env = W.wedge_env()
+    assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED
+    assert _status(P, env, W.Grid(nz=64, ntheta=2049, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED
+    assert _status(P, env, W.Grid(nz=2049, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0,
+                                  precision=W.PREC_C128)) == P.PE3D_EUNSUPPORTED
+
+
+def test_null_handles_are_rejected(P):
+    with pytest.raises(P.Pe3dError):
+        P.pe3d_march(None, 1, 16, None)
+    with pytest.raises(P.Pe3dError):
+        P.pe3d_get_step(None)
+    P.pe3d_destroy(None)
