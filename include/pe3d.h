@@ -107,11 +107,13 @@ typedef struct { double f_hz; } pe3d_freq;
  * once (the medium depends on (theta, z) only, so it is range invariant),
  * and allocates the handle's device buffers (coefficient tables and one
  * scratch field).  The range counter starts at step j = 0 (range r0).
- * Limits of the built kernels: complex64 nz <= 4096, ntheta <= 2048;
- * complex128 nz <= 2048, ntheta <= 1024; nz >= 2; ntheta >= 3 (periodic) or
- * >= 1 (sector).  Errors: PE3D_EINVAL (null pointer, non-finite or
- * non-positive f, c0, dr, zmax, speeds or densities, r0 < 0, r0 == 0 when
- * dr would put r_1 at 0, unordered samples, unknown enum), PE3D_EUNSUPPORTED
+ * Limits of the built kernels: complex64 nz <= 4096, complex128 nz <= 2048,
+ * ntheta <= 1024; nz >= 2; ntheta >= 3 (periodic) or >= 1 (sector).
+ * Precision: in both modes every coefficient and every arithmetic operation
+ * is FP64; PE3D_C64 stores the field (and values held between sweeps) in
+ * complex64.  Errors: PE3D_EINVAL (null pointer, non-finite or non-positive
+ * f, c0, dr, zmax, speeds or densities, negative attenuation, r0 < 0,
+ * unordered samples, unknown enum), PE3D_EUNSUPPORTED
  * (outside the limits, or a depth pivot smaller than 1e-10 of the largest
  * diagonal), PE3D_ENOMEM, PE3D_EDEVICE.  On error *out is set to NULL. */
 pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,
@@ -180,6 +182,37 @@ typedef struct {
   size_t device_bytes;    /* what pe3d_footprint reports                */
 } pe3d_info;
 pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info);
+
+/* Measurement support.  While enabled, every kernel launch made by
+ * pe3d_march and by pe3d_march_batch with use_graph == 0 is bracketed by a
+ * pair of HIP events recorded on the launch stream, together with the
+ * launch's algorithmic bytes (the field read once and written once over the
+ * columns or depth lines the launch covers).  pe3d_profile_read waits for
+ * those events, writes up to `cap` per-kernel aggregates (in first-launch
+ * order) to `stats`, sets *n to the number of distinct kernels, and clears the
+ * record.  Not thread-safe against concurrent marching calls. */
+typedef struct {
+  char name[48];
+  int32_t launches;
+  double total_ms;
+  double algo_bytes;
+} pe3d_kernel_stat;
+pe3d_status pe3d_profile_enable(int32_t on);
+pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, int32_t* n);
+
+/* Host only, for tests of the coefficient builder: the FP64 tables
+ * pe3d_create would upload, without touching the device.  Arrays are
+ * caller-allocated, complex values as (re, im) double pairs:
+ *   qw[2*nz]  n^2 - 1 of the water column at z_l,
+ *   pw[2*nz]  reciprocal top-down pivots of [1 + (1/4 - d/4) X] for the
+ *             all-water column, pb[2*nz] reciprocal bottom-up pivots for the
+ *             all-bottom column,
+ *   kcol[ntheta]   interface row k(m) of each column,
+ *   blk[24*ntheta] per column: X diagonals (lower, diag, upper) of rows k and
+ *             k+1, the two elimination multipliers and the inverse 2x2 block.
+ * Same validation and errors as pe3d_create (minus device errors). */
+pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
+                             double* qw, double* pw, double* pb, int32_t* kcol, double* blk);
 
 /* Static string for a status code. */
 const char* pe3d_strerror(pe3d_status s);

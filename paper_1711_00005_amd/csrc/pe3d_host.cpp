@@ -13,6 +13,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <cstdio>
 #include <new>
 #include <vector>
 
@@ -66,7 +68,7 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (is_periodic(g->width) ? g->ntheta < 3 : g->ntheta < 1) return PE3D_EINVAL;
   if (!is_fin(g->dr) || g->dr <= 0.0 || !is_fin(g->r0) || g->r0 < 0.0) return PE3D_EINVAL;
   if (g->precision != PE3D_C64 && g->precision != PE3D_C128) return PE3D_EINVAL;
-  if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 2048)) return PE3D_EUNSUPPORTED;
+  if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   if (g->precision == PE3D_C128 && (g->nz > 2048 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   return PE3D_OK;
 }
@@ -138,24 +140,14 @@ pe3d_status choose_shapes(Built& b) {
   const int cpw = 64 / b.lpc;
   b.ntile_a = (NT + cpw - 1) / cpw;
 
-  const int target = b.prec ? 8 : 16;
-  const int mmax = b.prec ? 16 : 32;
-  int nc = std::min(32, next_pow2((NT + target - 1) / target));
-  int mb = (NT + nc - 1) / nc;
-  if (mb > mmax) {
-    nc = 64;
-    mb = (NT + nc - 1) / nc;
-  }
-  if (mb > mmax) return PE3D_EUNSUPPORTED;
+  // about 16 azimuth nodes per chunk, at most 64 chunks (8 depths per workgroup)
+  const int nc = std::min(64, next_pow2((NT + 15) / 16));
+  const int mb = (NT + nc - 1) / nc;
+  if (mb > 16) return PE3D_EUNSUPPORTED;
   b.td = kPassBThreads / nc;
   b.nc = (NT + mb - 1) / mb;  // every chunk non-empty
   b.mb = mb;
-  const int cands_b64[3] = {8, 16, 32}, cands_b128[3] = {4, 8, 16};
-  const int* cb = b.prec ? cands_b128 : cands_b64;
-  b.maxm_b = 0;
-  for (int i = 0; i < 3; ++i)
-    if (cb[i] >= mb) { b.maxm_b = cb[i]; break; }
-  if (!b.maxm_b) return PE3D_EUNSUPPORTED;
+  b.maxm_b = mb <= 8 ? 8 : 16;
   b.ntile_b = (N + b.td - 1) / b.td;
   return PE3D_OK;
 }
@@ -295,7 +287,7 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
 }
 
 size_t table_bytes(const Built& b) {
-  const size_t csz = b.prec ? 16 : 8;
+  const size_t csz = 16;  // coefficient tables are FP64 in both precisions
   size_t n = 0;
   n += 3 * (size_t)b.N * csz;             // qw, pw, pb
   n += (size_t)b.NT * 12 * csz;           // column blocks
@@ -349,6 +341,7 @@ struct BatchPlan {
     int maxm;
     WorkItem* d_items;
     std::vector<int> nitems_at;        // active items at step k (problems sorted by steps)
+    std::vector<double> bytes_prefix;  // algorithmic bytes of the first i items
   };
   std::vector<Class> a, b;
   hipGraphExec_t exec = nullptr;
@@ -383,6 +376,56 @@ void evict_if_full() {
     g_plans.erase(g_lru.back());
     g_lru.pop_back();
   }
+}
+
+// ------------------------------------------------------------------ profiling
+struct ProfRec {
+  int name;
+  double bytes;
+  hipEvent_t a, b;
+};
+std::mutex g_pmu;
+bool g_prof = false;
+std::vector<std::string> g_pnames;
+std::vector<ProfRec> g_precs;
+std::vector<hipEvent_t> g_epool;
+
+hipEvent_t take_event() {
+  if (!g_epool.empty()) {
+    hipEvent_t e = g_epool.back();
+    g_epool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_name(const char* pass, int prec, int maxm) {
+  char buf[48];
+  std::snprintf(buf, sizeof buf, "%s<%s,%d>", pass, prec ? "c128" : "c64", maxm);
+  for (size_t i = 0; i < g_pnames.size(); ++i)
+    if (g_pnames[i] == buf) return int(i);
+  g_pnames.push_back(buf);
+  return int(g_pnames.size() - 1);
+}
+
+// Launch through `fn`, bracketed by events when profiling is on.
+template <typename F>
+hipError_t prof_launch(const char* pass, int prec, int maxm, double bytes, hipStream_t st, F fn) {
+  if (!g_prof) return fn();
+  std::lock_guard<std::mutex> lk(g_pmu);
+  ProfRec r;
+  r.name = prof_name(pass, prec, maxm);
+  r.bytes = bytes;
+  r.a = take_event();
+  r.b = take_event();
+  if (!r.a || !r.b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(r.a, st);
+  if (e == hipSuccess) e = fn();
+  if (e == hipSuccess) e = hipEventRecord(r.b, st);
+  g_precs.push_back(r);
+  return e;
 }
 
 void drop_plans_of(pe3d_handle h) {
@@ -429,6 +472,32 @@ pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3
   return PE3D_OK;
 }
 
+pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
+                             double* qw, double* pw, double* pb, int32_t* kcol, double* blk) {
+  if (!qw || !pw || !pb || !kcol || !blk) return PE3D_EINVAL;
+  pe3d_status st = validate(env, grid, freq);
+  if (st != PE3D_OK) return st;
+  Built b;
+  st = build(*env, *grid, *freq, b);
+  if (st != PE3D_OK) return st;
+  for (int l = 0; l < b.N; ++l) {
+    qw[2 * l] = b.qw[l].real();
+    qw[2 * l + 1] = b.qw[l].imag();
+    pw[2 * l] = b.pw[l].real();
+    pw[2 * l + 1] = b.pw[l].imag();
+    pb[2 * l] = b.pb[l].real();
+    pb[2 * l + 1] = b.pb[l].imag();
+  }
+  for (int m = 0; m < b.NT; ++m) {
+    kcol[m] = b.k[m];
+    for (int q = 0; q < 12; ++q) {
+      blk[24 * m + 2 * q] = b.blk[m][q].real();
+      blk[24 * m + 2 * q + 1] = b.blk[m][q].imag();
+    }
+  }
+  return PE3D_OK;
+}
+
 pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
                         pe3d_handle* out) {
   if (!out) return PE3D_EINVAL;
@@ -439,8 +508,8 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   st = build(*env, *grid, *freq, b);
   if (st != PE3D_OK) return st;
 
-  // host image of the coefficient tables
-  const size_t csz = b.prec ? 16 : 8;
+  // host image of the coefficient tables (FP64 in both precisions)
+  const size_t csz = 16;
   const size_t tb = table_bytes(b);
   std::vector<unsigned char> img(tb, 0);
   const size_t o_qw = 0, o_pw = o_qw + b.N * csz, o_pb = o_pw + b.N * csz;
@@ -450,17 +519,10 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   blkflat.reserve((size_t)b.NT * 12);
   for (auto& a : b.blk)
     for (auto& z : a) blkflat.push_back(z);
-  if (b.prec) {
-    pack<double>(b.qw, img, o_qw);
-    pack<double>(b.pw, img, o_pw);
-    pack<double>(b.pb, img, o_pb);
-    pack<double>(blkflat, img, o_blk);
-  } else {
-    pack<float>(b.qw, img, o_qw);
-    pack<float>(b.pw, img, o_pw);
-    pack<float>(b.pb, img, o_pb);
-    pack<float>(blkflat, img, o_blk);
-  }
+  pack<double>(b.qw, img, o_qw);
+  pack<double>(b.pw, img, o_pw);
+  pack<double>(b.pb, img, o_pb);
+  pack<double>(blkflat, img, o_blk);
   std::memcpy(img.data() + o_k, b.k.data(), b.NT * sizeof(int));
 
   pe3d_handle h = new (std::nothrow) pe3d_handle_s();
@@ -584,10 +646,15 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   ProbDesc d = h->desc;
   d.u = u_dev;
   d.nsteps = nsteps;
+  const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
-    if (launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, st) != hipSuccess)
+    if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
+          return launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, st);
+        }) != hipSuccess)
       return PE3D_EDEVICE;
-    if (launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, st) != hipSuccess)
+    if (prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
+          return launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, st);
+        }) != hipSuccess)
       return PE3D_EDEVICE;
   }
   if (launch_advance(nullptr, nullptr, 0, h->d_j, nsteps, st) != hipSuccess) return PE3D_EDEVICE;
@@ -631,6 +698,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::vector<int> adds(np);
   std::map<int, std::vector<WorkItem>> ia, ib;
   std::map<int, std::vector<int>> ia_steps, ib_steps;  // steps of the problem of each item
+  std::map<int, std::vector<double>> ia_bytes, ib_bytes;
   for (int p = 0; p < np; ++p) {
     pe3d_handle h = hs[order[p]];
     descs[p] = h->desc;
@@ -638,13 +706,20 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     descs[p].nsteps = nsteps[order[p]];
     jdevs[p] = h->d_j;
     adds[p] = nsteps[order[p]];
-    for (int t = 0; t < h->desc.ntile_a; ++t) {
+    const ProbDesc& hd = h->desc;
+    const double esz = h->prec ? 16.0 : 8.0;
+    const int cpw = 64 / hd.lpc;
+    for (int t = 0; t < hd.ntile_a; ++t) {
       ia[h->maxm_a].push_back({p, t});
       ia_steps[h->maxm_a].push_back(nsteps[order[p]]);
+      const int ncol = std::min(cpw, hd.nth - t * cpw);
+      ia_bytes[h->maxm_a].push_back(2.0 * esz * ncol * hd.nz);
     }
-    for (int t = 0; t < h->desc.ntile_b; ++t) {
+    for (int t = 0; t < hd.ntile_b; ++t) {
       ib[h->maxm_b].push_back({p, t});
       ib_steps[h->maxm_b].push_back(nsteps[order[p]]);
+      const int nd = std::min(hd.td, hd.nz - t * hd.td);
+      ib_bytes[h->maxm_b].push_back(2.0 * esz * nd * hd.nth);
     }
   }
   size_t nitems = 0;
@@ -666,10 +741,13 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   P.d_adds = reinterpret_cast<int*>(base + off_add);
   size_t cur = off_it;
   auto emit = [&](std::map<int, std::vector<WorkItem>>& src, std::map<int, std::vector<int>>& stp,
-                  std::vector<BatchPlan::Class>& dst) {
+                  std::map<int, std::vector<double>>& byt, std::vector<BatchPlan::Class>& dst) {
     for (auto& kv : src) {
       BatchPlan::Class c;
       c.maxm = kv.first;
+      const auto& bb = byt[kv.first];
+      c.bytes_prefix.assign(bb.size() + 1, 0.0);
+      for (size_t i = 0; i < bb.size(); ++i) c.bytes_prefix[i + 1] = c.bytes_prefix[i] + bb[i];
       c.d_items = reinterpret_cast<WorkItem*>(base + cur);
       std::memcpy(img.data() + cur, kv.second.data(), kv.second.size() * sizeof(WorkItem));
       cur += kv.second.size() * sizeof(WorkItem);
@@ -683,8 +761,8 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
       dst.push_back(c);
     }
   };
-  emit(ia, ia_steps, P.a);
-  emit(ib, ib_steps, P.b);
+  emit(ia, ia_steps, ia_bytes, P.a);
+  emit(ib, ib_steps, ib_bytes, P.b);
   if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
 }
@@ -693,12 +771,16 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
   for (int k = 0; k < P.maxsteps; ++k) {
     for (auto& c : P.a) {
       int ni = c.nitems_at[k];
-      if (ni > 0 && launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+      if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
+            return launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st);
+          }) != hipSuccess)
         return PE3D_EDEVICE;
     }
     for (auto& c : P.b) {
       int ni = c.nitems_at[k];
-      if (ni > 0 && launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+      if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
+            return launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st);
+          }) != hipSuccess)
         return PE3D_EDEVICE;
     }
   }
@@ -707,6 +789,42 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
 }
 
 }  // namespace
+
+extern "C" pe3d_status pe3d_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_pmu);
+  g_prof = on != 0;
+  return PE3D_OK;
+}
+
+extern "C" pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, int32_t* n) {
+  if (!n || cap < 0 || (cap > 0 && !stats)) return PE3D_EINVAL;
+  std::lock_guard<std::mutex> lk(g_pmu);
+  std::vector<pe3d_kernel_stat> agg(g_pnames.size());
+  std::vector<char> used(g_pnames.size(), 0);
+  std::vector<int> order;
+  pe3d_status st = PE3D_OK;
+  for (auto& r : g_precs) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+      st = PE3D_EDEVICE;
+    pe3d_kernel_stat& a = agg[r.name];
+    if (!used[r.name]) {
+      used[r.name] = 1;
+      order.push_back(r.name);
+      std::memset(&a, 0, sizeof a);
+      std::snprintf(a.name, sizeof a.name, "%s", g_pnames[r.name].c_str());
+    }
+    a.launches += 1;
+    a.total_ms += ms;
+    a.algo_bytes += r.bytes;
+    g_epool.push_back(r.a);
+    g_epool.push_back(r.b);
+  }
+  g_precs.clear();
+  *n = int(order.size());
+  for (int i = 0; i < int(order.size()) && i < cap; ++i) stats[i] = agg[order[i]];
+  return st;
+}
 
 extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const int32_t* nsteps,
                                         void* const* u_devs, int32_t use_graph, void* stream) {
@@ -758,7 +876,10 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
       if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
       pe3d_status s = PE3D_OK;
       if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
+      const bool was = g_prof;
+      g_prof = false;  // no event records inside a captured graph
       if (s == PE3D_OK) s = enqueue_plan(*plan, cap);
+      g_prof = was;
       hipGraph_t g = nullptr;
       if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
       (void)hipStreamDestroy(cap);

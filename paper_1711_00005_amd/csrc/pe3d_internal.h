@@ -38,10 +38,10 @@ struct ProbDesc {
   int lpc;              // lanes per column (power of two, <= 64)
   int ma;               // rows per lane
   int ntile_a;          // number of 64-lane tiles = ceil(nth / (64/lpc))
-  const void* qw;       // [nz] cplx<R>: n^2-1 of the water column
-  const void* pw;       // [nz] cplx<R>: 1/pivot of the all-water column (top-down)
-  const void* pb;       // [nz] cplx<R>: 1/pivot of the all-bottom column (bottom-up)
-  const void* blk;      // [nth] ColBlock<R>
+  const void* qw;       // [nz] cplx<double>: n^2-1 of the water column
+  const void* pw;       // [nz] cplx<double>: 1/pivot of the all-water column (top-down)
+  const void* pb;       // [nz] cplx<double>: 1/pivot of the all-bottom column (bottom-up)
+  const void* blk;      // [nth] ColBlock<double>
   const int* kcol;      // [nth] row k(m)
   double h;             // (k0 dz)^-2
   double qb_re, qb_im;  // n^2-1 of the bottom half-space
@@ -49,7 +49,7 @@ struct ProbDesc {
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
   // azimuth pass (pass B)
   int nc;               // chunks per depth line
-  int td;               // depths per workgroup (nc * td == 256)
+  int td;               // depths per workgroup (nc * td == kPassBThreads)
   int mb;               // azimuth nodes per chunk (nc * mb >= nth, all chunks non-empty)
   int ntile_b;          // ceil(nz / td)
   double k0, dr, r0, dth;
@@ -61,7 +61,7 @@ struct WorkItem {
   int tile;
 };
 
-constexpr int kPassBThreads = 256;
+constexpr int kPassBThreads = 512;
 
 // kernel launchers (pe3d_kernels.hip); all return a hipError_t
 // single != nullptr: one problem, grid from single->ntile_a / ntile_b, the
@@ -75,6 +75,5 @@ hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int 
 hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipStream_t st);
 hipError_t launch_tl(int prec, const ProbDesc& d, const void* u, float* tl, hipStream_t st);
 
-int pass_a_lds_bytes(int prec, int maxm);
 
 }  // namespace pe3d

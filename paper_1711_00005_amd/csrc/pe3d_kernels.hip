@@ -29,8 +29,13 @@
 //    also applies the next step's azimuth factor [I + s_{j+1} D_theta] before
 //    storing, so pass A of the next step is column-local.
 //
-// Kernels are templated on the real type R (float: complex64 storage and
-// arithmetic; double: complex128) and on the maximum chunk length.
+// Precision split: kernels are templated on the storage type S of the field
+// (float: complex64, double: complex128) and on the maximum chunk length.
+// Every arithmetic operation and every coefficient is FP64 in both modes; in
+// complex64 mode only the values held between sweeps are rounded to FP32.  A
+// coefficient rounded to FP32 would perturb the per-step propagator by the same
+// amount on every step and the error would grow linearly with range; data
+// roundings change from step to step and only accumulate as a random walk.
 #include <hip/hip_runtime.h>
 
 #include "pe3d_internal.h"
@@ -80,6 +85,7 @@ template <typename R>
 __device__ __forceinline__ C<R> from_d(C<double> z) { return mk<R>(R(z.re), R(z.im)); }
 template <typename R>
 __device__ __forceinline__ C<double> to_d(C<R> z) { return mk<double>(double(z.re), double(z.im)); }
+using D = C<double>;
 
 // ---------------------------------------------------------------- FP64 helpers
 __device__ __forceinline__ C<double> cdiv(C<double> a, C<double> b) {
@@ -121,13 +127,13 @@ __device__ __forceinline__ double sigma_of(const ProbDesc& d, long long j) {
 __device__ __forceinline__ C<double> rho_of(double sigma) {
   C<double> s = mk<double>(0.0, sigma);
   C<double> q = csqrt(mk<double>(1.0, 4.0 * sigma));
-  C<double> den = mk<double>(2.0 + q.re, 2.0 * sigma + q.im);
+  C<double> den = mk<double>(1.0 + q.re, 2.0 * sigma + q.im);
   return cdiv(mk<double>(2.0 * s.re, 2.0 * s.im), den);
 }
 
 // ============================================================== pass A
-template <typename R, int MAXM>
-__device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, C<R>* lds) {
+template <typename S, int MAXM>
+__device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, C<S>* lds) {
   const int lane = threadIdx.x;
   const int L = d.lpc;
   const int cpw = 64 / L;
@@ -138,19 +144,19 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const int m = m0 + cw;
   const bool colok = m < NT;
   const bool first = (koff == 0);
-  const C<R>* __restrict__ src = (const C<R>*)(first ? d.u : d.scr);
-  C<R>* __restrict__ dst = (C<R>*)d.scr;
+  const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
+  C<S>* __restrict__ dst = (C<S>*)d.scr;
   const int stride = L * (M + 1);
   const int ncols = min(cpw, NT - m0);
-  C<R>* slots = lds + cpw * stride;  // 4 complex per column
+  D* slots = reinterpret_cast<D*>(lds + 64 * (MAXM + 1));  // 4 per column
   const float invM = 1.0f / float(M);
 
-  for (int q = t; q < 4; q += L) slots[cw * 4 + q] = zero<R>();
+  for (int q = t; q < 4; q += L) slots[cw * 4 + q] = zero<double>();
 
   // ---- stage the columns into LDS; on the first step apply [I + s_0 D_theta]
   if (!first) {
     for (int c = 0; c < ncols; ++c) {
-      const C<R>* col = src + (size_t)(m0 + c) * N;
+      const C<S>* col = src + (size_t)(m0 + c) * N;
       for (int r = lane; r < N; r += 64) {
         int q = int((float(r) + 0.5f) * invM);
         lds[c * stride + r + q] = col[r];
@@ -158,10 +164,10 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     }
   } else {
     const long long j = *d.jdev + koff;
-    const R s0 = R(sigma_of(d, j));  // s_0 = i * s0
+    const double s0 = sigma_of(d, j);  // s_0 = i * s0
     for (int c = 0; c < ncols; ++c) {
       const int mm = m0 + c;
-      const C<R>* col = src + (size_t)mm * N;
+      const C<S>* col = src + (size_t)mm * N;
       int ml = mm - 1, mr = mm + 1;
       bool hl = true, hr = true;
       if (d.periodic) {
@@ -171,102 +177,99 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         hl = ml >= 0;
         hr = mr < NT;
       }
-      const C<R>* coll = src + (size_t)(hl ? ml : mm) * N;
-      const C<R>* colr = src + (size_t)(hr ? mr : mm) * N;
+      const C<S>* coll = src + (size_t)(hl ? ml : mm) * N;
+      const C<S>* colr = src + (size_t)(hr ? mr : mm) * N;
       for (int r = lane; r < N; r += 64) {
-        C<R> uc = col[r];
-        C<R> ul = hl ? coll[r] : zero<R>();
-        C<R> ur = hr ? colr[r] : zero<R>();
-        C<R> dd = sub(add(ul, ur), scl(R(2), uc));
-        // w = u + i s0 dd
-        C<R> w = mk<R>(uc.re - s0 * dd.im, uc.im + s0 * dd.re);
+        D uc = to_d(col[r]);
+        D ul = hl ? to_d(coll[r]) : zero<double>();
+        D ur = hr ? to_d(colr[r]) : zero<double>();
+        D dd = sub(add(ul, ur), scl(2.0, uc));
+        D w = mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re);  // u + i s0 dd
         int q = int((float(r) + 0.5f) * invM);
-        lds[c * stride + r + q] = w;
+        lds[c * stride + r + q] = from_d<S>(w);
       }
     }
   }
   __syncthreads();
 
-  // ---- per-column constants
-  const R h = R(d.h);
-  const C<R> qb = mk<R>(R(d.qb_re), R(d.qb_im));
-  const C<R> bp = mk<R>(R(d.bp_re), R(d.bp_im));
-  const C<R> bmh = mk<R>(R(d.bm_re * d.h), R(d.bm_im * d.h));
-  const C<R> nbmh = mk<R>(-bmh.re, -bmh.im);
-  const C<R>* __restrict__ qw = (const C<R>*)d.qw;
-  const C<R>* __restrict__ pw = (const C<R>*)d.pw;
-  const C<R>* __restrict__ pb = (const C<R>*)d.pb;
+  // ---- per-column constants (FP64)
+  const double h = d.h;
+  const D qb = mk<double>(d.qb_re, d.qb_im);
+  const D bp = mk<double>(d.bp_re, d.bp_im);
+  const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
+  const D* __restrict__ qw = (const D*)d.qw;
+  const D* __restrict__ pw = (const D*)d.pw;
+  const D* __restrict__ pb = (const D*)d.pb;
   int k = 0;
-  ColBlock<R> B;
+  ColBlock<double> B;
   if (colok) {
     k = d.kcol[m];
-    B = ((const ColBlock<R>*)d.blk)[m];
+    B = ((const ColBlock<double>*)d.blk)[m];
   } else {
-    B.xl0 = B.xd0 = B.xu0 = B.xl1 = B.xd1 = B.xu1 = zero<R>();
-    B.fk = B.gk1 = B.i00 = B.i01 = B.i10 = B.i11 = zero<R>();
+    B.xl0 = B.xd0 = B.xu0 = B.xl1 = B.xd1 = B.xu1 = zero<double>();
+    B.fk = B.gk1 = B.i00 = B.i01 = B.i10 = B.i11 = zero<double>();
   }
   const bool rigid = d.rigid != 0;
+  const D nbmh_floor = rigid ? scl(2.0, nbmh) : nbmh;  // lower coefficient of a rigid floor row
   const int r0 = t * M;
-  const C<R>* my = lds + cw * stride + t * (M + 1);
+  const C<S>* my = lds + cw * stride + t * (M + 1);
 
   // ---- RHS R = w + beta_+ X w over the lane's rows (sliding window)
-  C<R> Rv[MAXM];
+  C<S> Rv[MAXM];
   {
-    C<R> wm = (r0 >= 1 && r0 - 1 < N) ? my[-2] : zero<R>();
-    C<R> wc = (r0 < N) ? my[0] : zero<R>();
+    D wm = (r0 >= 1 && r0 - 1 < N) ? to_d(my[-2]) : zero<double>();
+    D wc = (r0 < N) ? to_d(my[0]) : zero<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       const int r = r0 + i;
-      C<R> wp = zero<R>();
-      if (i < M && r + 1 < N) wp = (i + 1 < M) ? my[i + 1] : my[M + 1];
-      C<R> X;
+      D wp = zero<double>();
+      if (i < M && r + 1 < N) wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
+      D X;
       if (r < k) {
-        C<R> qv = (i < M && r < N) ? qw[r] : zero<R>();
-        C<R> dg = mk<R>(qv.re - R(2) * h, qv.im);
-        X = fma(dg, wc, scl(h, add(wm, wp)));
+        D qv = (i < M && r < N) ? qw[r] : zero<double>();
+        X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
       } else if (r > k + 1) {
-        R hl = (rigid && r == N - 1) ? R(2) * h : h;
-        C<R> dg = mk<R>(qb.re - R(2) * h, qb.im);
-        X = fma(dg, wc, add(scl(hl, wm), scl(h, wp)));
+        double hl = (rigid && r == N - 1) ? 2.0 * h : h;
+        X = fma(mk<double>(qb.re - 2.0 * h, qb.im), wc, add(scl(hl, wm), scl(h, wp)));
       } else if (r == k) {
         X = fma(B.xl0, wm, fma(B.xd0, wc, mul(B.xu0, wp)));
       } else {
         X = fma(B.xl1, wm, fma(B.xd1, wc, mul(B.xu1, wp)));
       }
-      Rv[i] = (i < M && r < N) ? fma(bp, X, wc) : zero<R>();
+      Rv[i] = (i < M && r < N) ? from_d<S>(fma(bp, X, wc)) : zero<S>();
       wm = wc;
       wc = wp;
     }
   }
 
   // ---- elimination: top rows r < k downward, bottom rows r > k+1 upward
-  C<R> Ft = one<R>(), Et = zero<R>(), Gb = one<R>(), Sb = zero<R>();
+  D Ft = one<double>(), Et = zero<double>(), Gb = one<double>(), Sb = zero<double>();
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) {
     const int r = r0 + i;
     if (i < M && r < N && r < k) {
-      C<R> f = (r == 0) ? zero<R>() : mul(nbmh, pw[r - 1]);
-      Et = fma(f, Et, Rv[i]);
+      D f = (r == 0) ? zero<double>() : mul(nbmh, pw[r - 1]);
+      Et = fma(f, Et, to_d(Rv[i]));
       Ft = mul(Ft, f);
-      Rv[i] = Et;
+      Rv[i] = from_d<S>(Et);
     }
   }
 #pragma unroll
   for (int i = MAXM - 1; i >= 0; --i) {
     const int r = r0 + i;
     if (i < M && r < N && r > k + 1) {
-      C<R> g = (r == N - 1) ? zero<R>() : mul(nbmh, pb[r + 1]);
-      Sb = fma(g, Sb, Rv[i]);
+      D g = (r == N - 1) ? zero<double>() : mul(nbmh, pb[r + 1]);
+      Sb = fma(g, Sb, to_d(Rv[i]));
       Gb = mul(Gb, g);
-      Rv[i] = Sb;
+      Rv[i] = from_d<S>(Sb);
     }
   }
-  // segmented scans over the L lanes of the column
+  // segmented scans over the L lanes of the column (FP64)
   {
-    C<R> A = Ft, Bv = Et, A2 = Gb, B2 = Sb;
+    D A = Ft, Bv = Et, A2 = Gb, B2 = Sb;
     for (int dd = 1; dd < L; dd <<= 1) {
-      C<R> Ap = shfl_up(A, dd, L), Bp = shfl_up(Bv, dd, L);
-      C<R> A2p = shfl_down(A2, dd, L), B2p = shfl_down(B2, dd, L);
+      D Ap = shfl_up(A, dd, L), Bp = shfl_up(Bv, dd, L);
+      D A2p = shfl_down(A2, dd, L), B2p = shfl_down(B2, dd, L);
       if (t >= dd) {
         Bv = fma(A, Bp, Bv);
         A = mul(A, Ap);
@@ -276,28 +279,28 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         A2 = mul(A2, A2p);
       }
     }
-    C<R> ctop = shfl_up(Bv, 1, L);
-    C<R> cbot = shfl_down(B2, 1, L);
-    if (t == 0) ctop = zero<R>();
-    if (t == L - 1) cbot = zero<R>();
-    C<R> P = one<R>();
+    D ctop = shfl_up(Bv, 1, L);
+    D cbot = shfl_down(B2, 1, L);
+    if (t == 0) ctop = zero<double>();
+    if (t == L - 1) cbot = zero<double>();
+    D P = one<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       const int r = r0 + i;
       if (i < M && r < N && r < k) {
-        C<R> f = (r == 0) ? zero<R>() : mul(nbmh, pw[r - 1]);
+        D f = (r == 0) ? zero<double>() : mul(nbmh, pw[r - 1]);
         P = mul(P, f);
-        Rv[i] = fma(P, ctop, Rv[i]);
+        Rv[i] = from_d<S>(fma(P, ctop, to_d(Rv[i])));
       }
     }
-    P = one<R>();
+    P = one<double>();
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
       const int r = r0 + i;
       if (i < M && r < N && r > k + 1) {
-        C<R> g = (r == N - 1) ? zero<R>() : mul(nbmh, pb[r + 1]);
+        D g = (r == N - 1) ? zero<double>() : mul(nbmh, pb[r + 1]);
         P = mul(P, g);
-        Rv[i] = fma(P, cbot, Rv[i]);
+        Rv[i] = from_d<S>(fma(P, cbot, to_d(Rv[i])));
       }
     }
   }
@@ -307,39 +310,39 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   for (int i = 0; i < MAXM; ++i) {
     const int r = r0 + i;
     if (i < M && r < N) {
-      if (r == k - 1) slots[cw * 4 + 0] = Rv[i];
-      if (r == k) slots[cw * 4 + 1] = Rv[i];
-      if (r == k + 1) slots[cw * 4 + 2] = Rv[i];
-      if (r == k + 2) slots[cw * 4 + 3] = Rv[i];
+      if (r == k - 1) slots[cw * 4 + 0] = to_d(Rv[i]);
+      if (r == k) slots[cw * 4 + 1] = to_d(Rv[i]);
+      if (r == k + 1) slots[cw * 4 + 2] = to_d(Rv[i]);
+      if (r == k + 2) slots[cw * 4 + 3] = to_d(Rv[i]);
     }
   }
   __syncthreads();
-  C<R> vk, vk1;
+  D vk, vk1;
   {
-    C<R> ykm1 = slots[cw * 4 + 0], Rk = slots[cw * 4 + 1];
-    C<R> Rk1 = slots[cw * 4 + 2], zk2 = slots[cw * 4 + 3];
-    C<R> rk = fma(B.fk, ykm1, Rk);
-    C<R> rk1 = fma(B.gk1, zk2, Rk1);
+    D ykm1 = slots[cw * 4 + 0], Rk = slots[cw * 4 + 1];
+    D Rk1 = slots[cw * 4 + 2], zk2 = slots[cw * 4 + 3];
+    D rk = fma(B.fk, ykm1, Rk);
+    D rk1 = fma(B.gk1, zk2, Rk1);
     vk = fma(B.i00, rk, mul(B.i01, rk1));
     vk1 = fma(B.i10, rk, mul(B.i11, rk1));
   }
 
   // ---- back substitution: top rows upward from v_k, bottom rows downward from v_{k+1}
-  C<R> Ht = one<R>(), Eu = zero<R>(), Hb = one<R>(), Ed = zero<R>();
+  D Ht = one<double>(), Eu = zero<double>(), Hb = one<double>(), Ed = zero<double>();
 #pragma unroll
   for (int i = MAXM - 1; i >= 0; --i) {
     const int r = r0 + i;
     if (i < M && r < N) {
       if (r < k) {
-        C<R> p = pw[r];
-        C<R> hh = mul(nbmh, p);
-        Eu = fma(hh, Eu, mul(p, Rv[i]));
+        D p = pw[r];
+        D hh = mul(nbmh, p);
+        Eu = fma(hh, Eu, mul(p, to_d(Rv[i])));
         Ht = mul(Ht, hh);
-        Rv[i] = Eu;
+        Rv[i] = from_d<S>(Eu);
       } else if (r == k) {
-        Rv[i] = vk;
+        Rv[i] = from_d<S>(vk);
       } else if (r == k + 1) {
-        Rv[i] = vk1;
+        Rv[i] = from_d<S>(vk1);
       }
     }
   }
@@ -347,19 +350,18 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   for (int i = 0; i < MAXM; ++i) {
     const int r = r0 + i;
     if (i < M && r < N && r > k + 1) {
-      C<R> p = pb[r];
-      C<R> a = (rigid && r == N - 1) ? scl(R(2), nbmh) : nbmh;
-      C<R> hh = mul(a, p);
-      Ed = fma(hh, Ed, mul(p, Rv[i]));
+      D p = pb[r];
+      D hh = mul((r == N - 1) ? nbmh_floor : nbmh, p);
+      Ed = fma(hh, Ed, mul(p, to_d(Rv[i])));
       Hb = mul(Hb, hh);
-      Rv[i] = Ed;
+      Rv[i] = from_d<S>(Ed);
     }
   }
   {
-    C<R> A = Ht, Bv = Eu, A2 = Hb, B2 = Ed;
+    D A = Ht, Bv = Eu, A2 = Hb, B2 = Ed;
     for (int dd = 1; dd < L; dd <<= 1) {
-      C<R> Ap = shfl_down(A, dd, L), Bp = shfl_down(Bv, dd, L);
-      C<R> A2p = shfl_up(A2, dd, L), B2p = shfl_up(B2, dd, L);
+      D Ap = shfl_down(A, dd, L), Bp = shfl_down(Bv, dd, L);
+      D A2p = shfl_up(A2, dd, L), B2p = shfl_up(B2, dd, L);
       if (t + dd < L) {
         Bv = fma(A, Bp, Bv);
         A = mul(A, Ap);
@@ -369,44 +371,41 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         A2 = mul(A2, A2p);
       }
     }
-    // carries: top chain enters from below with v_k, bottom chain from above with v_{k+1}
-    C<R> An = shfl_down(A, 1, L), Bn = shfl_down(Bv, 1, L);
-    C<R> A2n = shfl_up(A2, 1, L), B2n = shfl_up(B2, 1, L);
-    C<R> cup = (t == L - 1) ? vk : fma(An, vk, Bn);
-    C<R> cdn = (t == 0) ? vk1 : fma(A2n, vk1, B2n);
-    C<R> P = one<R>();
+    // carries: the top chain enters from below with v_k, the bottom chain from above with v_{k+1}
+    D An = shfl_down(A, 1, L), Bn = shfl_down(Bv, 1, L);
+    D A2n = shfl_up(A2, 1, L), B2n = shfl_up(B2, 1, L);
+    D cup = (t == L - 1) ? vk : fma(An, vk, Bn);
+    D cdn = (t == 0) ? vk1 : fma(A2n, vk1, B2n);
+    D P = one<double>();
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
       const int r = r0 + i;
       if (i < M && r < N && r < k) {
-        C<R> hh = mul(nbmh, pw[r]);
-        P = mul(P, hh);
-        Rv[i] = fma(P, cup, Rv[i]);
+        P = mul(P, mul(nbmh, pw[r]));
+        Rv[i] = from_d<S>(fma(P, cup, to_d(Rv[i])));
       }
     }
-    P = one<R>();
+    P = one<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       const int r = r0 + i;
       if (i < M && r < N && r > k + 1) {
-        C<R> a = (rigid && r == N - 1) ? scl(R(2), nbmh) : nbmh;
-        C<R> hh = mul(a, pb[r]);
-        P = mul(P, hh);
-        Rv[i] = fma(P, cdn, Rv[i]);
+        P = mul(P, mul((r == N - 1) ? nbmh_floor : nbmh, pb[r]));
+        Rv[i] = from_d<S>(fma(P, cdn, to_d(Rv[i])));
       }
     }
   }
 
   // ---- write back through LDS, coalesced store
   __syncthreads();
-  C<R>* myw = lds + cw * stride + t * (M + 1);
+  C<S>* myw = lds + cw * stride + t * (M + 1);
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) {
     if (i < M && r0 + i < N) myw[i] = Rv[i];
   }
   __syncthreads();
   for (int c = 0; c < ncols; ++c) {
-    C<R>* col = dst + (size_t)(m0 + c) * N;
+    C<S>* col = dst + (size_t)(m0 + c) * N;
     for (int r = lane; r < N; r += 64) {
       int q = int((float(r) + 0.5f) * invM);
       col[r] = lds[c * stride + r + q];
@@ -414,29 +413,34 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   }
 }
 
-template <typename R, int MAXM>
-__global__ __launch_bounds__(64) void pass_a_single(ProbDesc d, int koff) {
-  extern __shared__ __align__(16) unsigned char smem_a[];
-  pass_a_body<R, MAXM>(d, blockIdx.x, koff, (C<R>*)smem_a);
+template <typename S, int MAXM>
+constexpr int pass_a_lds() {
+  return int(sizeof(C<S>) * 64 * (MAXM + 1) + sizeof(D) * 4 * 64);
 }
 
-template <typename R, int MAXM>
+template <typename S, int MAXM>
+__global__ __launch_bounds__(64) void pass_a_single(ProbDesc d, int koff) {
+  extern __shared__ __align__(16) unsigned char smem_a[];
+  pass_a_body<S, MAXM>(d, blockIdx.x, koff, (C<S>*)smem_a);
+}
+
+template <typename S, int MAXM>
 __global__ __launch_bounds__(64) void pass_a_batch(const ProbDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ items, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_a_body<R, MAXM>(d, it.tile, koff, (C<R>*)smem_a);
+  pass_a_body<S, MAXM>(d, it.tile, koff, (C<S>*)smem_a);
 }
 
 // ============================================================== pass B
-template <typename R, int MAXM>
+template <typename S, int MAXM>
 __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int koff) {
   constexpr int NTHR = kPassBThreads;
-  __shared__ C<double> sE1[NTHR], sC1[NTHR], sE2[NTHR], sC2[NTHR];
-  __shared__ C<R> sUf[NTHR], sUl[NTHR];
-  __shared__ C<R> sPow[MAXM + 2];
-  __shared__ C<double> sK[NTHR];
+  // sE1/sC1: forward chunk ends and carries, reused for the edge exchange;
+  // sE2/sC2: backward chunk starts and carries, sE2 reused for the sector term
+  __shared__ D sE1[NTHR], sC1[NTHR], sE2[NTHR], sC2[NTHR];
+  __shared__ D sPow[MAXM + 2];
 
   const int tid = threadIdx.x;
   const int TD = d.td, NC = d.nc, M = d.mb;
@@ -453,60 +457,59 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   const bool periodic = d.periodic != 0;
 
   const double sig = sigma_of(d, j);
-  const C<double> rho = rho_of(sig);
-  const C<R> rhoR = from_d<R>(rho);
-  if (tid <= MAXM + 1) sPow[tid] = from_d<R>(cpow(rho, tid));
+  const D rho = rho_of(sig);
+  if (tid <= MAXM + 1) sPow[tid] = cpow(rho, tid);
 
-  const C<R>* __restrict__ src = (const C<R>*)d.scr;
-  C<R>* __restrict__ dst = (C<R>*)(last ? d.u : d.scr);
+  const C<S>* __restrict__ src = (const C<S>*)d.scr;
+  C<S>* __restrict__ dst = (C<S>*)(last ? d.u : d.scr);
 
   // ---- load the chunk and its two azimuth neighbours
-  C<R> v[MAXM], x[MAXM];
-  C<R> vl = zero<R>(), vr = zero<R>();
+  C<S> v[MAXM];
+  D x[MAXM];
+  D vl = zero<double>(), vr = zero<double>();
   if (act) {
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-      v[i] = (i < len) ? src[(size_t)(m0 + i) * N + z] : zero<R>();
+      v[i] = (i < len) ? src[(size_t)(m0 + i) * N + z] : zero<S>();
     int ml = m0 - 1, mr = m0 + len;
     if (periodic) {
       if (ml < 0) ml = NT - 1;
       if (mr >= NT) mr = 0;
-      vl = src[(size_t)ml * N + z];
-      vr = src[(size_t)mr * N + z];
+      vl = to_d(src[(size_t)ml * N + z]);
+      vr = to_d(src[(size_t)mr * N + z]);
     } else {
-      if (ml >= 0) vl = src[(size_t)ml * N + z];
-      if (mr < NT) vr = src[(size_t)mr * N + z];
+      if (ml >= 0) vl = to_d(src[(size_t)ml * N + z]);
+      if (mr < NT) vr = to_d(src[(size_t)mr * N + z]);
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) v[i] = zero<R>();
+    for (int i = 0; i < MAXM; ++i) v[i] = zero<S>();
   }
   // ---- D_theta v, forward recurrence y_m = t_m + rho y_{m-1} with zero carry
-  C<R> E = zero<R>();
+  D E = zero<double>();
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) {
     if (i < len) {
-      C<R> a = (i == 0) ? vl : v[i - 1];
-      C<R> b = (i + 1 < len) ? v[i + 1] : vr;
-      C<R> tt = sub(add(a, b), scl(R(2), v[i]));
-      E = fma(rhoR, E, tt);
+      D a = (i == 0) ? vl : to_d(v[i - 1]);
+      D b = (i + 1 < len) ? to_d(v[i + 1]) : vr;
+      D tt = sub(add(a, b), scl(2.0, to_d(v[i])));
+      E = fma(rho, E, tt);
       x[i] = E;
     } else {
-      x[i] = zero<R>();
+      x[i] = zero<double>();
     }
   }
-  sE1[tid] = to_d(E);
+  sE1[tid] = E;
   __syncthreads();
-  // ---- carries across chunks (FP64); periodic closure y_{-1} = y_{N-1}
+  // ---- carries across chunks; periodic closure y_{-1} = y_{N-1}
   if (c == 0) {
-    const C<double> rM = cpow(rho, M);
-    const int lastlen = NT - (NC - 1) * M;
-    const C<double> rL = cpow(rho, lastlen);
-    C<double> carry = zero<double>();
+    const D rM = cpow(rho, M);
+    const D rL = cpow(rho, NT - (NC - 1) * M);
+    D carry = zero<double>();
     if (periodic) {
-      C<double> tot = zero<double>();
+      D tot = zero<double>();
       for (int cc = 0; cc < NC; ++cc) tot = add(mul(cc == NC - 1 ? rL : rM, tot), sE1[cc * TD + dl]);
-      C<double> rN = cpow(rho, NT);
+      D rN = cpow(rho, NT);
       carry = cdiv(tot, mk<double>(1.0 - rN.re, -rN.im));
     }
     for (int cc = 0; cc < NC; ++cc) {
@@ -516,31 +519,30 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   }
   __syncthreads();
   {
-    C<R> cin = from_d<R>(sC1[tid]);
+    const D cin = sC1[tid];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
       if (i < len) x[i] = fma(sPow[i + 1], cin, x[i]);
   }
   // ---- backward recurrence x_m = y_m + rho x_{m+1} with zero carry
-  C<R> S = zero<R>();
+  D Sv = zero<double>();
 #pragma unroll
   for (int i = MAXM - 1; i >= 0; --i) {
     if (i < len) {
-      S = fma(rhoR, S, x[i]);
-      x[i] = S;
+      Sv = fma(rho, Sv, x[i]);
+      x[i] = Sv;
     }
   }
-  sE2[tid] = to_d(S);
+  sE2[tid] = Sv;
   __syncthreads();
   if (c == 0) {
-    const C<double> rM = cpow(rho, M);
-    const int lastlen = NT - (NC - 1) * M;
-    const C<double> rL = cpow(rho, lastlen);
-    C<double> carry = zero<double>();
+    const D rM = cpow(rho, M);
+    const D rL = cpow(rho, NT - (NC - 1) * M);
+    D carry = zero<double>();
     if (periodic) {
-      C<double> tot = zero<double>();
+      D tot = zero<double>();
       for (int cc = NC - 1; cc >= 0; --cc) tot = add(mul(cc == NC - 1 ? rL : rM, tot), sE2[cc * TD + dl]);
-      C<double> rN = cpow(rho, NT);
+      D rN = cpow(rho, NT);
       carry = cdiv(tot, mk<double>(1.0 - rN.re, -rN.im));
     }
     for (int cc = NC - 1; cc >= 0; --cc) {
@@ -550,79 +552,82 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   }
   __syncthreads();
   {
-    C<R> cin = from_d<R>(sC2[tid]);
+    const D cin = sC2[tid];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
       if (i < len) x[i] = fma(sPow[len - i], cin, x[i]);
   }
-  // ---- e = rho x; sector: rank-one correction of the first row,
+  // ---- u = v + rho x; sector: rank-one correction of the first row,
   //      e_m -= K (rho^m - rho^{2N-m}),  K = rho^2 e_0 / (1 - rho^{2N+2})
-  C<R> u[MAXM];
-#pragma unroll
-  for (int i = 0; i < MAXM; ++i) u[i] = fma(rhoR, x[i], v[i]);
   if (!periodic) {
-    if (c == 0) sK[dl] = mul(rho, to_d(x[0]));
+    if (c == 0) sE2[dl] = mul(rho, x[0]);
     __syncthreads();
     if (act) {
-      C<double> e0 = sK[dl];
-      C<double> r2N2 = cpow(rho, 2 * (long long)NT + 2);
-      C<double> K = cdiv(mul(mul(rho, rho), e0), mk<double>(1.0 - r2N2.re, -r2N2.im));
-      C<double> pa = mul(K, cpow(rho, m0));                          // K rho^m at i = 0
-      C<double> pbk = mul(K, cpow(rho, 2 * (long long)NT - m0 - len + 1));  // K rho^{2N-m} at i = len-1
-      C<R> paR = from_d<R>(pa), pbR = from_d<R>(pbk);
+      const D e0 = sE2[dl];
+      const D r2N2 = cpow(rho, 2 * (long long)NT + 2);
+      const D K = cdiv(mul(mul(rho, rho), e0), mk<double>(1.0 - r2N2.re, -r2N2.im));
+      const D pa = mul(K, cpow(rho, m0));                                  // K rho^m at i = 0
+      const D pbk = mul(K, cpow(rho, 2 * (long long)NT - m0 - len + 1));   // K rho^{2N-m} at i = len-1
 #pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        if (i < len) {
-          C<R> corr = sub(mul(paR, sPow[i]), mul(pbR, sPow[len - 1 - i]));
-          u[i] = sub(u[i], corr);
-        }
-      }
+      for (int i = 0; i < MAXM; ++i)
+        if (i < len) x[i] = sub(fma(rho, x[i], to_d(v[i])), sub(mul(pa, sPow[i]), mul(pbk, sPow[len - 1 - i])));
     }
+  } else {
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) x[i] = fma(rho, x[i], to_d(v[i]));
   }
-  // ---- next step's azimuth factor w = u + s_{j+1} D_theta u, or store u
+  // x now holds u^{j+1}.  Next step's azimuth factor w = u + s_{j+1} D_theta u, or store u.
   if (!last) {
-    sUf[tid] = u[0];
-    sUl[tid] = zero<R>();
+    // start the next step from u^{j+1} as stored (rounded to S), exactly as a
+    // new march call would: an interrupted and resumed march is bitwise equal
+    // to an uninterrupted one
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) x[i] = to_d(from_d<S>(x[i]));
+    D* sUf = sE1;
+    D* sUl = sC1;
+    sUf[tid] = x[0];
+    D xl = zero<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-      if (i == len - 1) sUl[tid] = u[i];
+      if (i == len - 1) xl = x[i];
+    sUl[tid] = xl;
     __syncthreads();
     if (act) {
-      C<R> ul, ur;
+      D ul, ur;
       if (c > 0) ul = sUl[(c - 1) * TD + dl];
-      else ul = periodic ? sUl[(NC - 1) * TD + dl] : zero<R>();
+      else ul = periodic ? sUl[(NC - 1) * TD + dl] : zero<double>();
       if (c < NC - 1) ur = sUf[(c + 1) * TD + dl];
-      else ur = periodic ? sUf[dl] : zero<R>();
-      const R s1 = R(sigma_of(d, j + 1));
+      else ur = periodic ? sUf[dl] : zero<double>();
+      const double s1 = sigma_of(d, j + 1);
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (i < len) {
-          C<R> a = (i == 0) ? ul : u[i - 1];
-          C<R> b = (i + 1 < len) ? u[i + 1] : ur;
-          C<R> dd = sub(add(a, b), scl(R(2), u[i]));
-          dst[(size_t)(m0 + i) * N + z] = mk<R>(u[i].re - s1 * dd.im, u[i].im + s1 * dd.re);
+          D a = (i == 0) ? ul : x[i - 1];
+          D b = (i + 1 < len) ? x[i + 1] : ur;
+          D dd = sub(add(a, b), scl(2.0, x[i]));
+          dst[(size_t)(m0 + i) * N + z] = from_d<S>(mk<double>(x[i].re - s1 * dd.im, x[i].im + s1 * dd.re));
         }
       }
     }
   } else if (act) {
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-      if (i < len) dst[(size_t)(m0 + i) * N + z] = u[i];
+      if (i < len) dst[(size_t)(m0 + i) * N + z] = from_d<S>(x[i]);
   }
 }
 
-template <typename R, int MAXM>
+template <typename S, int MAXM>
 __global__ __launch_bounds__(kPassBThreads) void pass_b_single(ProbDesc d, int koff) {
-  pass_b_body<R, MAXM>(d, blockIdx.x, koff);
+  pass_b_body<S, MAXM>(d, blockIdx.x, koff);
 }
 
-template <typename R, int MAXM>
+template <typename S, int MAXM>
 __global__ __launch_bounds__(kPassBThreads) void pass_b_batch(const ProbDesc* __restrict__ descs,
                                                               const WorkItem* __restrict__ items,
                                                               int koff) {
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_b_body<R, MAXM>(d, it.tile, koff);
+  pass_b_body<S, MAXM>(d, it.tile, koff);
 }
 
 // ============================================================== small kernels
@@ -662,31 +667,26 @@ __global__ void tl_kernel(ProbDesc d, const C<R>* u, float* tl) {
 }
 
 // ============================================================== launchers
-int pass_a_lds_bytes(int prec, int maxm) {
-  size_t csz = prec ? 16 : 8;
-  return int(csz * (64 * (maxm + 1) + 4 * 64));
-}
-
-template <typename R, int MAXM>
+template <typename S, int MAXM>
 static hipError_t run_a(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                         int nitems, int koff, hipStream_t st) {
-  const int lds = int(sizeof(C<R>) * (64 * (MAXM + 1) + 4 * 64));
+  constexpr int lds = pass_a_lds<S, MAXM>();
   if (single) {
-    hipLaunchKernelGGL((pass_a_single<R, MAXM>), dim3(single->ntile_a), dim3(64), lds, st, *single, koff);
+    hipLaunchKernelGGL((pass_a_single<S, MAXM>), dim3(single->ntile_a), dim3(64), lds, st, *single, koff);
   } else {
-    hipLaunchKernelGGL((pass_a_batch<R, MAXM>), dim3(nitems), dim3(64), lds, st, d_descs, items, koff);
+    hipLaunchKernelGGL((pass_a_batch<S, MAXM>), dim3(nitems), dim3(64), lds, st, d_descs, items, koff);
   }
   return hipGetLastError();
 }
 
-template <typename R, int MAXM>
+template <typename S, int MAXM>
 static hipError_t run_b(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                         int nitems, int koff, hipStream_t st) {
   if (single) {
-    hipLaunchKernelGGL((pass_b_single<R, MAXM>), dim3(single->ntile_b), dim3(kPassBThreads), 0, st,
+    hipLaunchKernelGGL((pass_b_single<S, MAXM>), dim3(single->ntile_b), dim3(kPassBThreads), 0, st,
                        *single, koff);
   } else {
-    hipLaunchKernelGGL((pass_b_batch<R, MAXM>), dim3(nitems), dim3(kPassBThreads), 0, st, d_descs,
+    hipLaunchKernelGGL((pass_b_batch<S, MAXM>), dim3(nitems), dim3(kPassBThreads), 0, st, d_descs,
                        items, koff);
   }
   return hipGetLastError();
@@ -716,11 +716,9 @@ hipError_t launch_pass_b(int prec, int maxm, const ProbDesc* single, const ProbD
     switch (maxm) {
       case 8: return run_b<float, 8>(single, d_descs, items, nitems, koff, st);
       case 16: return run_b<float, 16>(single, d_descs, items, nitems, koff, st);
-      case 32: return run_b<float, 32>(single, d_descs, items, nitems, koff, st);
     }
   } else {
     switch (maxm) {
-      case 4: return run_b<double, 4>(single, d_descs, items, nitems, koff, st);
       case 8: return run_b<double, 8>(single, d_descs, items, nitems, koff, st);
       case 16: return run_b<double, 16>(single, d_descs, items, nitems, koff, st);
     }

@@ -37,7 +37,7 @@ PE3D_C128 = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_get_info",
-            "pe3d_strerror")
+            "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror")
 
 
 class pe3d_env(ct.Structure):
@@ -69,6 +69,11 @@ class pe3d_info(ct.Structure):
                 ("device_bytes", ct.c_size_t)]
 
 
+class pe3d_kernel_stat(ct.Structure):
+    _fields_ = [("name", ct.c_char * 48), ("launches", ct.c_int32), ("total_ms", ct.c_double),
+                ("algo_bytes", ct.c_double)]
+
+
 _H = ct.c_void_p
 _lib.pe3d_create.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), ct.POINTER(pe3d_freq),
                              ct.POINTER(_H)]
@@ -83,6 +88,10 @@ _lib.pe3d_march_batch.argtypes = [ct.POINTER(_H), ct.c_int32, ct.POINTER(ct.c_in
                                   ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p]
 _lib.pe3d_tl.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.pe3d_get_info.argtypes = [_H, ct.POINTER(pe3d_info)]
+_lib.pe3d_host_tables.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), ct.POINTER(pe3d_freq),
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_profile_enable.argtypes = [ct.c_int32]
+_lib.pe3d_profile_read.argtypes = [ct.POINTER(pe3d_kernel_stat), ct.c_int32, ct.POINTER(ct.c_int32)]
 _lib.pe3d_strerror.argtypes = [ct.c_int]
 _lib.pe3d_strerror.restype = ct.c_char_p
 for _n in EXPORTED[:-1]:
@@ -174,6 +183,25 @@ def pe3d_create_status(env, grid, f_hz: float) -> int:
     return st
 
 
+def pe3d_host_tables(env, grid, f_hz: float):
+    """FP64 host tables (host only): dict of numpy arrays qw, pw, pb (complex,
+    nz), kcol (int, ntheta), blk (complex, ntheta x 12)."""
+    import numpy as np
+    e, keep = make_env(env)
+    g = make_grid(grid)
+    nz, nth = int(grid.nz), int(grid.ntheta)
+    qw = np.zeros(2 * nz)
+    pw = np.zeros(2 * nz)
+    pb = np.zeros(2 * nz)
+    kc = np.zeros(nth, dtype=np.int32)
+    blk = np.zeros(24 * nth)
+    _check(_lib.pe3d_host_tables(ct.byref(e), ct.byref(g), ct.byref(pe3d_freq(f_hz)),
+                                 qw.ctypes.data, pw.ctypes.data, pb.ctypes.data, kc.ctypes.data,
+                                 blk.ctypes.data), "pe3d_host_tables")
+    c = lambda a: a[0::2] + 1j * a[1::2]
+    return dict(qw=c(qw), pw=c(pw), pb=c(pb), kcol=kc.astype(int), blk=c(blk).reshape(nth, 12))
+
+
 def pe3d_destroy(h) -> None:
     _check(_lib.pe3d_destroy(h), "pe3d_destroy")
 
@@ -216,6 +244,22 @@ def pe3d_march_batch(handles: Sequence[int], nsteps: Sequence[int], u_ptrs: Sequ
     us = (ct.c_void_p * n)(*u_ptrs)
     _check(_lib.pe3d_march_batch(hs, n, ns, us, int(bool(use_graph)), ct.c_void_p(stream_ptr)),
            "pe3d_march_batch")
+
+
+def pe3d_profile_enable(on: bool) -> None:
+    _check(_lib.pe3d_profile_enable(int(bool(on))), "pe3d_profile_enable")
+
+
+def pe3d_profile_read():
+    """Per-kernel aggregates since the last read: list of dicts with name,
+    launches, total_ms, algo_bytes."""
+    cap = 64
+    arr = (pe3d_kernel_stat * cap)()
+    n = ct.c_int32(0)
+    _check(_lib.pe3d_profile_read(arr, cap, ct.byref(n)), "pe3d_profile_read")
+    return [dict(name=arr[i].name.decode(), launches=int(arr[i].launches),
+                 total_ms=float(arr[i].total_ms), algo_bytes=float(arr[i].algo_bytes))
+            for i in range(min(n.value, cap))]
 
 
 # ----------------------------------------------------------------------- wrapper
