@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the 3D wide-angle PE range march on one MI355X.
+
+Default workload: the wide-band batch of 64 frequencies (20-500 Hz, dz =
+lambda/8, Ntheta growing with sqrt(f), Munk-like profile over a periodic
+wedge, 107.6 M grid points, 861 MB of complex64 field) advanced together by
+the batched march (one launch per pass and kernel class per range step,
+replayed from a captured hipGraph).  One bench "step" is one range step of
+every problem: pass A + pass B over the whole batch.
+
+Printed (one JSON line): throughput in grid-point * range-steps / s; the
+dominant kernel's achieved HBM bandwidth from HIP events (algorithmic bytes =
+the field read once and written once per pass); the plain per-frequency march
+(one problem at a time, per-step launches) on the same batch and the ratio;
+a parity sample against the complex128 oracle; the oracle's own CPU
+throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+METRIC = "grid-point·range-steps/s (batched vs plain) at ≤1e-5 rel L2; p50/p99 latency"
+UNIT = "grid-point·range-steps/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed range steps of the whole batch")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=10, help="range steps per batched call (one graph)")
+    ap.add_argument("--workload", choices=["config4", "config2"], default="config4")
+    ap.add_argument("--nfreq", type=int, default=64)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    return ap.parse_args()
+
+
+def problems_for(args):
+    if args.workload == "config4":
+        return W.config4_problems(nsteps=args.steps, nfreq=args.nfreq), (
+            f"config4: {args.nfreq} frequencies log-spaced 20-500 Hz, dz=lambda/8 (Nz 320-4096), "
+            "Ntheta 256-1024, Munk-like profile over a periodic 2000-200 m wedge, fluid bottom "
+            "1700 m/s rho 1.5 0.5 dB/lambda, complex64 field, FP64 arithmetic, batched")
+    p = W.config2(nsteps=args.steps)
+    return [p], ("config2: 100 Hz, Nz=2048, Ntheta=512, Munk-like profile over a periodic wedge, "
+                 "complex64 field, FP64 arithmetic")
+
+
+def march_steps(P, ms, us, nsteps, chunk, use_graph):
+    done = 0
+    while done < nsteps:
+        k = min(chunk, nsteps - done)
+        P.march_batch(ms, k, us, use_graph=use_graph)
+        done += k
+
+
+def cpu_baseline(probs, sample_every: int):
+    """The oracle (complex128 NumPy) on a bounded sample: one range step of
+    every `sample_every`-th problem from its starter."""
+    import oracle as O
+    sample = probs[::sample_every]
+    pts = sum(p.points for p in sample)
+    t0 = time.perf_counter()
+    outs = []
+    for p in sample:
+        st = O.setup(p.env, p.grid, p.f_hz)
+        u0 = O.starter(st, p.zs)
+        outs.append(O.step(st, u0, 0))
+    dt = time.perf_counter() - t0
+    return dict(value=pts / dt, unit=UNIT, cores=1, kind="oracle",
+                sample=f"1 range step of {len(sample)} of the {len(probs)} problems "
+                       f"(every {sample_every}th, {pts} points) from the starter, single thread"), \
+        sample, outs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every problem of the "
+              "batch is independent, so N GPUs would each run their own share with no exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1711_00005_amd import pe3d as P
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    torch.cuda.set_device(0)
+    probs, workload = problems_for(args)
+    npts = sum(p.points for p in probs)
+    log(f"workload: {len(probs)} problems, {npts} points")
+    ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
+    us = [m.starter(p.zs) for m, p in zip(ms, probs)]
+    torch.cuda.synchronize()
+    use_graph = not args.no_graph
+
+    # ---- warmup (captures the graphs of both chunk sizes used below)
+    log("warmup")
+    march_steps(P, ms, us, max(args.warmup, 1), args.chunk, use_graph)
+    if args.steps % args.chunk:
+        march_steps(P, ms, us, args.steps % args.chunk, args.chunk, use_graph)
+    torch.cuda.synchronize()
+
+    # ---- timed region
+    log("timed")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    march_steps(P, ms, us, args.steps, args.chunk, use_graph)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    value = npts * args.steps / elapsed
+    log(f"batched: {value:.4e} pt*steps/s, {1e3 * elapsed / args.steps:.3f} ms/step")
+
+    # ---- per-kernel durations (same workload, direct launches bracketed by HIP events)
+    log("profile")
+    P.pe3d_profile_enable(True)
+    march_steps(P, ms, us, args.profile_steps, args.chunk, False)
+    torch.cuda.synchronize()
+    stats = P.pe3d_profile_read()
+    P.pe3d_profile_enable(False)
+    prof_ms = sum(s["total_ms"] for s in stats)
+    kernels = []
+    for s in stats:
+        avg = s["total_ms"] / s["launches"]
+        gbs = (s["algo_bytes"] / s["launches"]) / (avg * 1e-3) / 1e9
+        kernels.append(dict(name=s["name"], launches=s["launches"], avg_ms=round(avg, 5),
+                            algo_bytes_per_launch=s["algo_bytes"] / s["launches"],
+                            achieved_gbs=round(gbs, 1)))
+    dom = max(stats, key=lambda s: s["total_ms"])
+    dom_avg = dom["total_ms"] / dom["launches"]
+    dom_gbs = (dom["algo_bytes"] / dom["launches"]) / (dom_avg * 1e-3) / 1e9
+    step_bytes = 32.0 * npts  # both passes, complex64
+    roofline = dict(bound="hbm", achieved=round(dom_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=dom["name"],
+                    step_achieved=round(step_bytes * args.steps / elapsed / 1e9, 1),
+                    step_frac=round(step_bytes * args.steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
+                    kernels=kernels, profiled_ms_per_step=round(prof_ms / args.profile_steps, 4))
+
+    out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "storage": "complex64", "data": "synthetic",
+           "config": {"workload": workload, "problems": len(probs), "grid_points": npts,
+                      "graph": use_graph, "chunk_steps": args.chunk},
+           "roofline": roofline}
+
+    # ---- plain per-frequency march on the same batch
+    if not args.no_plain and len(probs) > 1:
+        log("plain")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for m, u in zip(ms, us):
+            m.march(args.plain_steps, u)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        pv = npts * args.plain_steps / tp
+        out["plain"] = dict(value=pv, steps=args.plain_steps, ms_per_step=1e3 * tp / args.plain_steps,
+                            how="each problem alone, one launch per pass per step, no graph")
+        out["batched_over_plain"] = value / pv
+        log(f"plain: {pv:.4e} pt*steps/s -> batched/plain = {value / pv:.2f}")
+
+    # ---- oracle baseline and parity sample
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        every = 8 if len(probs) >= 8 else 1
+        cb, sample, outs = cpu_baseline(probs, every)
+        out["cpu_baseline"] = cb
+        errs = []
+        import oracle as O
+        for p, ref in zip(sample, outs):
+            m = P.Pe3d(p.env, p.grid, p.f_hz)
+            u = m.starter(p.zs)
+            m.march(1, u)
+            torch.cuda.synchronize()
+            errs.append(O.rel_l2(u.cpu().numpy().astype(np.complex128), ref))
+            m.close()
+        out["parity_sample"] = dict(max_rel_l2=max(errs), problems=len(errs), steps=1,
+                                    reference="complex128 oracle")
+        log(f"oracle {cb['value']:.3e} pt*steps/s; parity max rel L2 {max(errs):.2e}")
+
+    for m in ms:
+        m.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -69,7 +69,7 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (!is_fin(g->dr) || g->dr <= 0.0 || !is_fin(g->r0) || g->r0 < 0.0) return PE3D_EINVAL;
   if (g->precision != PE3D_C64 && g->precision != PE3D_C128) return PE3D_EINVAL;
   if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
-  if (g->precision == PE3D_C128 && (g->nz > 2048 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
+  if (g->precision == PE3D_C128 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   return PE3D_OK;
 }
 
@@ -118,6 +118,7 @@ struct Built {
   double k0 = 0, dz = 0, dth = 0, h = 0;
   cd qb, bp, bm;
   std::vector<cd> qw, pw, pb;
+  std::vector<cd> qwT, pwT, pbT, lane_tr;  // lane-major copies for the depth kernel
   std::vector<int> k;
   std::vector<std::array<cd, 12>> blk;
   int lpc = 0, ma = 0, maxm_a = 0, ntile_a = 0;
@@ -129,15 +130,12 @@ struct Built {
 // rows per lane; pass B uses nc azimuth chunks of mb nodes times td depths.
 pe3d_status choose_shapes(Built& b) {
   const int N = b.N, NT = b.NT;
-  const int cands_a64[3] = {16, 32, 64}, cands_a128[3] = {8, 16, 32};
-  const int* ca = b.prec ? cands_a128 : cands_a64;
-  b.maxm_a = 0;
-  for (int i = 0; i < 3; ++i)
-    if (64 * ca[i] >= N) { b.maxm_a = ca[i]; break; }
-  if (!b.maxm_a) return PE3D_EUNSUPPORTED;
-  b.lpc = std::min(64, next_pow2((N + b.maxm_a - 1) / b.maxm_a));
+  // pass A: at most 16 rows per lane, L = power of two in 4..256 lanes per column
+  b.maxm_a = 16;
+  b.lpc = std::max(4, next_pow2((N + 15) / 16));
+  if (b.lpc > 256) return PE3D_EUNSUPPORTED;
   b.ma = (N + b.lpc - 1) / b.lpc;
-  const int cpw = 64 / b.lpc;
+  const int cpw = 256 / b.lpc;
   b.ntile_a = (NT + cpw - 1) / cpw;
 
   // about 16 azimuth nodes per chunk, at most 64 chunks (8 depths per workgroup)
@@ -202,15 +200,21 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
       b.pw[l] = 1.0 / dw[l];
     }
   }
-  // bottom-up pivots of the all-bottom column
+  // bottom-up pivots of the all-bottom column; a rigid floor row is divided
+  // by 2 so that its lower coefficient is beta_- h like the other bottom rows
   b.pb.assign(N, 0.0);
   std::vector<cd> eb(N);
+  const double floor_scale = b.rigid ? 0.5 : 1.0;
   {
     cd anext = 0.0;
     for (int l = N - 1; l >= 0; --l) {
       cd xl, xd, xu;
       col_x(l, b.qb, xl, xd, xu);
       cd a = bm * xl, bb = 1.0 + bm * xd, c = bm * xu;
+      if (l == N - 1) {
+        a *= floor_scale;
+        bb *= floor_scale;
+      }
       eb[l] = (l == N - 1) ? bb : bb - c * anext / eb[l + 1];
       anext = a;
       b.pb[l] = 1.0 / eb[l];
@@ -261,7 +265,8 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     }
     if (k + 2 <= N - 1) {
       cd nxl, nxd, nxu;
-      xrow(k + 2, nxl, nxd, nxu);  // a bottom row
+      xrow(k + 2, nxl, nxd, nxu);  // a bottom row (scaled if it is the rigid floor)
+      if (k + 2 == N - 1) nxl *= floor_scale;
       gk1 = -(bm * xu1) / eb[k + 2];
       Q += gk1 * (bm * nxl);
     }
@@ -283,7 +288,38 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     maxb = std::max(maxb, std::abs(1.0 + bm * (b.qb - 2.0 * h)));
   }
   if (!(minpiv > 1e-10 * maxb)) return PE3D_EUNSUPPORTED;
-  return choose_shapes(b);
+  pe3d_status st = choose_shapes(b);
+  if (st != PE3D_OK) return st;
+  // lane-major copies: entry [i][t] holds the value for row t*M - 1 + i (pivots)
+  // or t*M + i (n^2 - 1), zero outside the column
+  const int L = b.lpc, M = b.ma;
+  const cd nbmh = -bm * h;
+  b.qwT.assign((size_t)M * L, 0.0);
+  b.pwT.assign((size_t)(M + 2) * L, 0.0);
+  b.pbT.assign((size_t)(M + 2) * L, 0.0);
+  b.lane_tr.assign((size_t)4 * L, 1.0);
+  auto at = [&](const std::vector<cd>& v, int r) { return (r >= 0 && r < N) ? v[r] : cd(0.0); };
+  for (int t = 0; t < L; ++t) {
+    const int r0 = t * M;
+    for (int i = 0; i < M; ++i) b.qwT[(size_t)i * L + t] = at(b.qw, r0 + i);
+    for (int i = 0; i < M + 2; ++i) {
+      b.pwT[(size_t)i * L + t] = at(b.pw, r0 - 1 + i);
+      b.pbT[(size_t)i * L + t] = at(b.pb, r0 - 1 + i);
+    }
+    // transfer products of a lane whose M rows are all top / all bottom rows
+    cd ft = 1.0, gb = 1.0, ht = 1.0, hb = 1.0;
+    for (int i = 0; i < M; ++i) {
+      ft *= nbmh * at(b.pw, r0 + i - 1);
+      gb *= nbmh * at(b.pb, r0 + i + 1);
+      ht *= nbmh * at(b.pw, r0 + i);
+      hb *= nbmh * at(b.pb, r0 + i);
+    }
+    b.lane_tr[0 * (size_t)L + t] = ft;
+    b.lane_tr[1 * (size_t)L + t] = gb;
+    b.lane_tr[2 * (size_t)L + t] = ht;
+    b.lane_tr[3 * (size_t)L + t] = hb;
+  }
+  return PE3D_OK;
 }
 
 size_t table_bytes(const Built& b) {
@@ -291,6 +327,7 @@ size_t table_bytes(const Built& b) {
   size_t n = 0;
   n += 3 * (size_t)b.N * csz;             // qw, pw, pb
   n += (size_t)b.NT * 12 * csz;           // column blocks
+  n += (size_t)(3 * b.ma + 4 + 4) * b.lpc * csz;  // qwT, pwT, pbT, lane transfer products
   n += (size_t)b.NT * sizeof(int);        // kcol
   n = (n + 255) & ~size_t(255);
   n += 256;                               // step counter
@@ -513,7 +550,12 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   const size_t tb = table_bytes(b);
   std::vector<unsigned char> img(tb, 0);
   const size_t o_qw = 0, o_pw = o_qw + b.N * csz, o_pb = o_pw + b.N * csz;
-  const size_t o_blk = o_pb + b.N * csz, o_k = o_blk + (size_t)b.NT * 12 * csz;
+  const size_t o_blk = o_pb + b.N * csz;
+  const size_t o_qwT = o_blk + (size_t)b.NT * 12 * csz;
+  const size_t o_pwT = o_qwT + (size_t)b.ma * b.lpc * csz;
+  const size_t o_pbT = o_pwT + (size_t)(b.ma + 2) * b.lpc * csz;
+  const size_t o_lt = o_pbT + (size_t)(b.ma + 2) * b.lpc * csz;
+  const size_t o_k = o_lt + (size_t)4 * b.lpc * csz;
   const size_t o_j = tb - 256;
   std::vector<cd> blkflat;
   blkflat.reserve((size_t)b.NT * 12);
@@ -523,6 +565,10 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   pack<double>(b.pw, img, o_pw);
   pack<double>(b.pb, img, o_pb);
   pack<double>(blkflat, img, o_blk);
+  pack<double>(b.qwT, img, o_qwT);
+  pack<double>(b.pwT, img, o_pwT);
+  pack<double>(b.pbT, img, o_pbT);
+  pack<double>(b.lane_tr, img, o_lt);
   std::memcpy(img.data() + o_k, b.k.data(), b.NT * sizeof(int));
 
   pe3d_handle h = new (std::nothrow) pe3d_handle_s();
@@ -567,9 +613,10 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.lpc = b.lpc;
   d.ma = b.ma;
   d.ntile_a = b.ntile_a;
-  d.qw = base + o_qw;
-  d.pw = base + o_pw;
-  d.pb = base + o_pb;
+  d.qwT = base + o_qwT;
+  d.pwT = base + o_pwT;
+  d.pbT = base + o_pbT;
+  d.lane_tr = base + o_lt;
   d.blk = base + o_blk;
   d.kcol = reinterpret_cast<const int*>(base + o_k);
   d.h = b.h;
@@ -708,7 +755,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     adds[p] = nsteps[order[p]];
     const ProbDesc& hd = h->desc;
     const double esz = h->prec ? 16.0 : 8.0;
-    const int cpw = 64 / hd.lpc;
+    const int cpw = 256 / hd.lpc;
     for (int t = 0; t < hd.ntile_a; ++t) {
       ia[h->maxm_a].push_back({p, t});
       ia_steps[h->maxm_a].push_back(nsteps[order[p]]);

@@ -17,6 +17,9 @@ struct alignas(2 * sizeof(R)) cplx {
 // rows use the shared all-water (above) or all-bottom (below) coefficients.
 // fk, gk1: elimination multipliers that bring the top and bottom
 // eliminations onto rows k and k+1; inv: inverse of the resulting 2x2 block.
+// A rigid floor row that belongs to the bottom region is divided by 2 in the
+// bottom system (its lower coefficient becomes beta_- h like every other
+// bottom row; its right-hand side is halved to match).
 template <typename R>
 struct ColBlock {
   cplx<R> xl0, xd0, xu0;  // X diagonals of row k
@@ -38,9 +41,12 @@ struct ProbDesc {
   int lpc;              // lanes per column (power of two, <= 64)
   int ma;               // rows per lane
   int ntile_a;          // number of 64-lane tiles = ceil(nth / (64/lpc))
-  const void* qw;       // [nz] cplx<double>: n^2-1 of the water column
-  const void* pw;       // [nz] cplx<double>: 1/pivot of the all-water column (top-down)
-  const void* pb;       // [nz] cplx<double>: 1/pivot of the all-bottom column (bottom-up)
+  // lane-major tables (entry [i][t] at i*lpc + t, t = lane in the column), FP64 complex:
+  const void* qwT;      // [ma][lpc]: n^2-1 of the water column at row t*ma + i
+  const void* pwT;      // [ma+2][lpc]: 1/pivot of the all-water column (top-down) at row t*ma - 1 + i
+  const void* pbT;      // [ma+2][lpc]: 1/pivot of the all-bottom column (bottom-up), same rows
+  const void* lane_tr;  // [4][lpc]: chunk transfer products of a lane whose rows are all top
+                        //   (elimination, back substitution) or all bottom
   const void* blk;      // [nth] ColBlock<double>
   const int* kcol;      // [nth] row k(m)
   double h;             // (k0 dz)^-2

@@ -4,8 +4,9 @@
 //
 //  pass A (depth pass, Eqs. (5)/(7)): per azimuth column, R = [I + beta_+ X] w
 //    with w = [I + s_j D_theta] u^j, then solve [I + beta_- X] v = R.
-//    One 64-lane wavefront owns 64/L columns; each column is split into L
-//    contiguous chunks of M rows, one per lane.  The column is staged through
+//    A 256-lane workgroup owns 256/L columns; each column is split into L
+//    contiguous chunks of M <= 16 rows, one per lane (L up to 256 lanes, so
+//    a column may span several wavefronts).  The column is staged through
 //    LDS so that global loads and stores are coalesced along depth.  The
 //    solve is a twisted factorisation: rows above the water/bottom interface
 //    are eliminated top-down with the shared pivots of the all-water column,
@@ -131,12 +132,95 @@ __device__ __forceinline__ C<double> rho_of(double sigma) {
   return cdiv(mk<double>(2.0 * s.re, 2.0 * s.im), den);
 }
 
+
+template <typename R>
+__device__ __forceinline__ C<R> shfl_idx(C<R> v, int src, int w) {
+  return mk<R>(__shfl(v.re, src, w), __shfl(v.im, src, w));
+}
+
+__device__ __forceinline__ int ncp_of(int nc) {
+  int p = 1;
+  while (p < nc) p <<= 1;
+  return p;
+}
+
 // ============================================================== pass A
+// Workgroup of 256 lanes; a depth column is split over L lanes (L a power of
+// two, 4..256), each lane holding M <= MAXM consecutive rows; 256/L <= 64
+// columns per workgroup.  Columns wider than a wavefront (L > 64) combine the
+// per-wavefront scan totals through LDS.
+//
+// A wavefront whose lanes all hold rows strictly above the interface rows of
+// their column (or all strictly below) runs a branch-free path; lanes holding
+// an interface row, or a partial chunk, run the general path.  With the
+// rigid floor row pre-scaled by 1/2 on the host, every row of the bottom
+// region has lower coefficient beta_- h.
+constexpr int kPassAThreads = 256;
+
+struct ChainPair {
+  D down, up;
+};
+// Exclusive carries of a downward chain (lane t's map applied after lanes
+// 0..t-1 of the column) and of an upward chain (after lanes t+1..L-1).  Each
+// lane passes its chunk map (A, B): x -> A x + B.  tot: LDS scratch, 4 complex
+// per wavefront.
+__device__ __forceinline__ ChainPair scan_pair(D Ad, D Bd, D init_d, D Au, D Bu, D init_u, int t, int L,
+                                               D* tot) {
+  const int w = L < 64 ? L : 64;  // segment width inside a wavefront
+  const int tw = t & (w - 1);     // lane within the segment
+  D ad = Ad, bd = Bd, au = Au, bu = Bu;
+  for (int dd = 1; dd < w; dd <<= 1) {
+    D ap = shfl_up(ad, dd, w), bp = shfl_up(bd, dd, w);
+    D aq = shfl_down(au, dd, w), bq = shfl_down(bu, dd, w);
+    if (tw >= dd) {
+      bd = fma(ad, bp, bd);
+      ad = mul(ad, ap);
+    }
+    if (tw + dd < w) {
+      bu = fma(au, bq, bu);
+      au = mul(au, aq);
+    }
+  }
+  D ade = shfl_up(ad, 1, w), bde = shfl_up(bd, 1, w);
+  D aue = shfl_down(au, 1, w), bue = shfl_down(bu, 1, w);
+  if (tw == 0) {
+    ade = one<double>();
+    bde = zero<double>();
+  }
+  if (tw == w - 1) {
+    aue = one<double>();
+    bue = zero<double>();
+  }
+  D xd = init_d, xu = init_u;
+  if (L > 64) {
+    const int wave = threadIdx.x >> 6;
+    if (tw == w - 1) {
+      tot[4 * wave + 0] = ad;
+      tot[4 * wave + 1] = bd;
+    }
+    if (tw == 0) {
+      tot[4 * wave + 2] = au;
+      tot[4 * wave + 3] = bu;
+    }
+    __syncthreads();
+    const int nw = L >> 6;
+    const int wc = (t >> 6);
+    const int w0 = wave - wc;
+    for (int q = 0; q < wc; ++q) xd = fma(tot[4 * (w0 + q) + 0], xd, tot[4 * (w0 + q) + 1]);
+    for (int q = nw - 1; q > wc; --q) xu = fma(tot[4 * (w0 + q) + 2], xu, tot[4 * (w0 + q) + 3]);
+    __syncthreads();
+  }
+  ChainPair r;
+  r.down = fma(ade, xd, bde);
+  r.up = fma(aue, xu, bue);
+  return r;
+}
+
 template <typename S, int MAXM>
 __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, C<S>* lds) {
   const int lane = threadIdx.x;
   const int L = d.lpc;
-  const int cpw = 64 / L;
+  const int cpw = kPassAThreads / L;  // columns per workgroup
   const int cw = lane / L;
   const int t = lane - cw * L;
   const int N = d.nz, NT = d.nth, M = d.ma;
@@ -148,16 +232,17 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   C<S>* __restrict__ dst = (C<S>*)d.scr;
   const int stride = L * (M + 1);
   const int ncols = min(cpw, NT - m0);
-  D* slots = reinterpret_cast<D*>(lds + 64 * (MAXM + 1));  // 4 per column
+  D* slots = reinterpret_cast<D*>(lds + kPassAThreads * (MAXM + 1));  // 4 per column
+  D* tot = slots + 4 * 64;                                              // 4 per wavefront
   const float invM = 1.0f / float(M);
 
   for (int q = t; q < 4; q += L) slots[cw * 4 + q] = zero<double>();
 
-  // ---- stage the columns into LDS; on the first step apply [I + s_0 D_theta]
+  // ---- stage the columns into LDS (coalesced); on the first step apply [I + s_0 D_theta]
   if (!first) {
     for (int c = 0; c < ncols; ++c) {
       const C<S>* col = src + (size_t)(m0 + c) * N;
-      for (int r = lane; r < N; r += 64) {
+      for (int r = lane; r < N; r += kPassAThreads) {
         int q = int((float(r) + 0.5f) * invM);
         lds[c * stride + r + q] = col[r];
       }
@@ -179,7 +264,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       }
       const C<S>* coll = src + (size_t)(hl ? ml : mm) * N;
       const C<S>* colr = src + (size_t)(hr ? mr : mm) * N;
-      for (int r = lane; r < N; r += 64) {
+      for (int r = lane; r < N; r += kPassAThreads) {
         D uc = to_d(col[r]);
         D ul = hl ? to_d(coll[r]) : zero<double>();
         D ur = hr ? to_d(colr[r]) : zero<double>();
@@ -190,208 +275,294 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       }
     }
   }
-  __syncthreads();
 
-  // ---- per-column constants (FP64)
+  // ---- constants (FP64), lane classification, the lane's pivots (loaded once, coalesced)
   const double h = d.h;
   const D qb = mk<double>(d.qb_re, d.qb_im);
   const D bp = mk<double>(d.bp_re, d.bp_im);
   const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
-  const D* __restrict__ qw = (const D*)d.qw;
-  const D* __restrict__ pw = (const D*)d.pw;
-  const D* __restrict__ pb = (const D*)d.pb;
-  int k = 0;
-  ColBlock<double> B;
-  if (colok) {
-    k = d.kcol[m];
-    B = ((const ColBlock<double>*)d.blk)[m];
-  } else {
-    B.xl0 = B.xd0 = B.xu0 = B.xl1 = B.xd1 = B.xu1 = zero<double>();
-    B.fk = B.gk1 = B.i00 = B.i01 = B.i10 = B.i11 = zero<double>();
-  }
+  const D* __restrict__ qwT = (const D*)d.qwT;
+  const D* __restrict__ pwT = (const D*)d.pwT;
+  const D* __restrict__ pbT = (const D*)d.pbT;
+  const D* __restrict__ lt = (const D*)d.lane_tr;  // [4][L]: Ft, Gb, Ht, Hb of full lanes
+  const int k = colok ? d.kcol[m] : 0;
+  const ColBlock<double>* Bp = colok ? ((const ColBlock<double>*)d.blk) + m : nullptr;
   const bool rigid = d.rigid != 0;
-  const D nbmh_floor = rigid ? scl(2.0, nbmh) : nbmh;  // lower coefficient of a rigid floor row
   const int r0 = t * M;
+  const bool full = colok && (r0 + M <= N);
+  const bool ftop = full && (r0 + M <= k);   // every row above the interface rows
+  const bool fbot = full && (r0 >= k + 2);   // every row below them
+  const bool wave_top = __all(ftop);
+  const bool wave_bot = __all(fbot);
+  // piv[i]: reciprocal pivot of row r0-1+i (top-down above the interface rows,
+  // bottom-up below them); zero outside the column
+  __syncthreads();
+  D piv[MAXM + 2];
+#pragma unroll
+  for (int i = 0; i < MAXM + 2; ++i) {
+    const int r = r0 - 1 + i;
+    piv[i] = (i < M + 2) ? (r < k ? pwT[i * L + t] : pbT[i * L + t]) : zero<double>();
+  }
   const C<S>* my = lds + cw * stride + t * (M + 1);
 
   // ---- RHS R = w + beta_+ X w over the lane's rows (sliding window)
-  C<S> Rv[MAXM];
+  D Rv[MAXM];
   {
     D wm = (r0 >= 1 && r0 - 1 < N) ? to_d(my[-2]) : zero<double>();
     D wc = (r0 < N) ? to_d(my[0]) : zero<double>();
+    const D dgb = mk<double>(qb.re - 2.0 * h, qb.im);
+    if (wave_top) {
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      const int r = r0 + i;
-      D wp = zero<double>();
-      if (i < M && r + 1 < N) wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
-      D X;
-      if (r < k) {
-        D qv = (i < M && r < N) ? qw[r] : zero<double>();
-        X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
-      } else if (r > k + 1) {
-        double hl = (rigid && r == N - 1) ? 2.0 * h : h;
-        X = fma(mk<double>(qb.re - 2.0 * h, qb.im), wc, add(scl(hl, wm), scl(h, wp)));
-      } else if (r == k) {
-        X = fma(B.xl0, wm, fma(B.xd0, wc, mul(B.xu0, wp)));
-      } else {
-        X = fma(B.xl1, wm, fma(B.xd1, wc, mul(B.xu1, wp)));
+      for (int i = 0; i < MAXM; ++i) {
+        if (i < M) {
+          const D wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
+          const D qv = qwT[i * L + t];
+          const D X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
+          Rv[i] = fma(bp, X, wc);
+          wm = wc;
+          wc = wp;
+        }
       }
-      Rv[i] = (i < M && r < N) ? from_d<S>(fma(bp, X, wc)) : zero<S>();
-      wm = wc;
-      wc = wp;
+    } else if (wave_bot) {
+      // a lane ending on a rigid floor: its last row has lower coefficient 2h
+      // and is scaled by 1/2 (the host scales the floor row of the bottom system)
+      const bool fl = rigid && (r0 + M == N);
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        if (i < M) {
+          const bool last = (i + 1 == M) && (r0 + M == N);
+          const D wp = last ? zero<double>() : to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
+          const D X = fma(dgb, wc, scl(h, add(wm, wp)));
+          D R = fma(bp, X, wc);
+          if (fl && i + 1 == M) R = scl(0.5, fma(bp, scl(h, wm), R));
+          Rv[i] = R;
+          wm = wc;
+          wc = wp;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        const int r = r0 + i;
+        D wp = zero<double>();
+        if (i < M && r + 1 < N) wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
+        D X;
+        D R;
+        if (r < k) {
+          const D qv = (i < M && r < N) ? qwT[i * L + t] : zero<double>();
+          X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
+          R = fma(bp, X, wc);
+        } else if (r > k + 1) {
+          const bool flr = rigid && (r == N - 1);
+          X = fma(dgb, wc, add(scl(flr ? 2.0 * h : h, wm), scl(h, wp)));
+          R = fma(bp, X, wc);
+          if (flr) R = scl(0.5, R);
+        } else if (Bp == nullptr) {
+          R = zero<double>();
+        } else if (r == k) {
+          X = fma(Bp->xl0, wm, fma(Bp->xd0, wc, mul(Bp->xu0, wp)));
+          R = fma(bp, X, wc);
+        } else {
+          X = fma(Bp->xl1, wm, fma(Bp->xd1, wc, mul(Bp->xu1, wp)));
+          R = fma(bp, X, wc);
+        }
+        Rv[i] = (i < M && r < N) ? R : zero<double>();
+        wm = wc;
+        wc = wp;
+      }
     }
   }
 
-  // ---- elimination: top rows r < k downward, bottom rows r > k+1 upward
+  // ---- elimination: top rows downward, y_r = R_r + (-beta_- h) pivot_{r-1} y_{r-1};
+  //      bottom rows upward, z_r = R_r + (-beta_- h) pivot_{r+1} z_{r+1}
   D Ft = one<double>(), Et = zero<double>(), Gb = one<double>(), Sb = zero<double>();
+  if (wave_top) {
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    const int r = r0 + i;
-    if (i < M && r < N && r < k) {
-      D f = (r == 0) ? zero<double>() : mul(nbmh, pw[r - 1]);
-      Et = fma(f, Et, to_d(Rv[i]));
-      Ft = mul(Ft, f);
-      Rv[i] = from_d<S>(Et);
-    }
-  }
+    for (int i = 0; i < MAXM; ++i)
+      if (i < M) {
+        Et = fma(nbmh, mul(piv[i], Et), Rv[i]);
+        Rv[i] = Et;
+      }
+    Ft = lt[0 * L + t];
+  } else if (wave_bot) {
 #pragma unroll
-  for (int i = MAXM - 1; i >= 0; --i) {
-    const int r = r0 + i;
-    if (i < M && r < N && r > k + 1) {
-      D g = (r == N - 1) ? zero<double>() : mul(nbmh, pb[r + 1]);
-      Sb = fma(g, Sb, to_d(Rv[i]));
-      Gb = mul(Gb, g);
-      Rv[i] = from_d<S>(Sb);
-    }
-  }
-  // segmented scans over the L lanes of the column (FP64)
-  {
-    D A = Ft, Bv = Et, A2 = Gb, B2 = Sb;
-    for (int dd = 1; dd < L; dd <<= 1) {
-      D Ap = shfl_up(A, dd, L), Bp = shfl_up(Bv, dd, L);
-      D A2p = shfl_down(A2, dd, L), B2p = shfl_down(B2, dd, L);
-      if (t >= dd) {
-        Bv = fma(A, Bp, Bv);
-        A = mul(A, Ap);
+    for (int i = MAXM - 1; i >= 0; --i)
+      if (i < M) {
+        Sb = fma(nbmh, mul(piv[i + 2], Sb), Rv[i]);
+        Rv[i] = Sb;
       }
-      if (t + dd < L) {
-        B2 = fma(A2, B2p, B2);
-        A2 = mul(A2, A2p);
-      }
-    }
-    D ctop = shfl_up(Bv, 1, L);
-    D cbot = shfl_down(B2, 1, L);
-    if (t == 0) ctop = zero<double>();
-    if (t == L - 1) cbot = zero<double>();
-    D P = one<double>();
+    Gb = lt[1 * L + t];
+  } else {
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       const int r = r0 + i;
       if (i < M && r < N && r < k) {
-        D f = (r == 0) ? zero<double>() : mul(nbmh, pw[r - 1]);
-        P = mul(P, f);
-        Rv[i] = from_d<S>(fma(P, ctop, to_d(Rv[i])));
+        const D f = mul(nbmh, piv[i]);
+        Et = fma(f, Et, Rv[i]);
+        Ft = mul(Ft, f);
+        Rv[i] = Et;
       }
     }
-    P = one<double>();
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
       const int r = r0 + i;
       if (i < M && r < N && r > k + 1) {
-        D g = (r == N - 1) ? zero<double>() : mul(nbmh, pb[r + 1]);
-        P = mul(P, g);
-        Rv[i] = from_d<S>(fma(P, cbot, to_d(Rv[i])));
+        const D g = mul(nbmh, piv[i + 2]);
+        Sb = fma(g, Sb, Rv[i]);
+        Gb = mul(Gb, g);
+        Rv[i] = Sb;
+      }
+    }
+  }
+  {
+    const ChainPair cc = scan_pair(Ft, Et, zero<double>(), Gb, Sb, zero<double>(), t, L, tot);
+    if (wave_top) {
+      D dl = cc.down;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        if (i < M) {
+          dl = mul(nbmh, mul(piv[i], dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+    } else if (wave_bot) {
+      D dl = cc.up;
+#pragma unroll
+      for (int i = MAXM - 1; i >= 0; --i)
+        if (i < M) {
+          dl = mul(nbmh, mul(piv[i + 2], dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+    } else {
+      D dl = cc.down;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        const int r = r0 + i;
+        if (i < M && r < N && r < k) {
+          dl = mul(nbmh, mul(piv[i], dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+      }
+      dl = cc.up;
+#pragma unroll
+      for (int i = MAXM - 1; i >= 0; --i) {
+        const int r = r0 + i;
+        if (i < M && r < N && r > k + 1) {
+          dl = mul(nbmh, mul(piv[i + 2], dl));
+          Rv[i] = add(Rv[i], dl);
+        }
       }
     }
   }
 
-  // ---- 2x2 interface block
+  // ---- 2x2 interface block (rows k, k+1): the lanes holding rows k-1..k+2 publish them
+  if (colok && r0 <= k + 2 && r0 + M > k - 1) {
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    const int r = r0 + i;
-    if (i < M && r < N) {
-      if (r == k - 1) slots[cw * 4 + 0] = to_d(Rv[i]);
-      if (r == k) slots[cw * 4 + 1] = to_d(Rv[i]);
-      if (r == k + 1) slots[cw * 4 + 2] = to_d(Rv[i]);
-      if (r == k + 2) slots[cw * 4 + 3] = to_d(Rv[i]);
+    for (int i = 0; i < MAXM; ++i) {
+      const int r = r0 + i;
+      if (i < M && r < N) {
+        if (r == k - 1) slots[cw * 4 + 0] = Rv[i];
+        if (r == k) slots[cw * 4 + 1] = Rv[i];
+        if (r == k + 1) slots[cw * 4 + 2] = Rv[i];
+        if (r == k + 2) slots[cw * 4 + 3] = Rv[i];
+      }
     }
   }
   __syncthreads();
-  D vk, vk1;
-  {
-    D ykm1 = slots[cw * 4 + 0], Rk = slots[cw * 4 + 1];
-    D Rk1 = slots[cw * 4 + 2], zk2 = slots[cw * 4 + 3];
-    D rk = fma(B.fk, ykm1, Rk);
-    D rk1 = fma(B.gk1, zk2, Rk1);
-    vk = fma(B.i00, rk, mul(B.i01, rk1));
-    vk1 = fma(B.i10, rk, mul(B.i11, rk1));
+  D vk = zero<double>(), vk1 = zero<double>();
+  if (Bp) {
+    const D ykm1 = slots[cw * 4 + 0], Rk = slots[cw * 4 + 1];
+    const D Rk1 = slots[cw * 4 + 2], zk2 = slots[cw * 4 + 3];
+    const D rk = fma(Bp->fk, ykm1, Rk);
+    const D rk1 = fma(Bp->gk1, zk2, Rk1);
+    vk = fma(Bp->i00, rk, mul(Bp->i01, rk1));
+    vk1 = fma(Bp->i10, rk, mul(Bp->i11, rk1));
   }
 
-  // ---- back substitution: top rows upward from v_k, bottom rows downward from v_{k+1}
+  // ---- back substitution: top rows upward, v_r = pivot_r (y_r + (-beta_- h) v_{r+1});
+  //      bottom rows downward, v_r = pivot_r (z_r + (-beta_- h) v_{r-1})
   D Ht = one<double>(), Eu = zero<double>(), Hb = one<double>(), Ed = zero<double>();
+  if (wave_top) {
 #pragma unroll
-  for (int i = MAXM - 1; i >= 0; --i) {
-    const int r = r0 + i;
-    if (i < M && r < N) {
-      if (r < k) {
-        D p = pw[r];
-        D hh = mul(nbmh, p);
-        Eu = fma(hh, Eu, mul(p, to_d(Rv[i])));
-        Ht = mul(Ht, hh);
-        Rv[i] = from_d<S>(Eu);
-      } else if (r == k) {
-        Rv[i] = from_d<S>(vk);
-      } else if (r == k + 1) {
-        Rv[i] = from_d<S>(vk1);
+    for (int i = MAXM - 1; i >= 0; --i)
+      if (i < M) {
+        Eu = mul(piv[i + 1], fma(nbmh, Eu, Rv[i]));
+        Rv[i] = Eu;
       }
-    }
-  }
+    Ht = lt[2 * L + t];
+  } else if (wave_bot) {
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    const int r = r0 + i;
-    if (i < M && r < N && r > k + 1) {
-      D p = pb[r];
-      D hh = mul((r == N - 1) ? nbmh_floor : nbmh, p);
-      Ed = fma(hh, Ed, mul(p, to_d(Rv[i])));
-      Hb = mul(Hb, hh);
-      Rv[i] = from_d<S>(Ed);
-    }
-  }
-  {
-    D A = Ht, Bv = Eu, A2 = Hb, B2 = Ed;
-    for (int dd = 1; dd < L; dd <<= 1) {
-      D Ap = shfl_down(A, dd, L), Bp = shfl_down(Bv, dd, L);
-      D A2p = shfl_up(A2, dd, L), B2p = shfl_up(B2, dd, L);
-      if (t + dd < L) {
-        Bv = fma(A, Bp, Bv);
-        A = mul(A, Ap);
+    for (int i = 0; i < MAXM; ++i)
+      if (i < M) {
+        Ed = mul(piv[i + 1], fma(nbmh, Ed, Rv[i]));
+        Rv[i] = Ed;
       }
-      if (t >= dd) {
-        B2 = fma(A2, B2p, B2);
-        A2 = mul(A2, A2p);
-      }
-    }
-    // carries: the top chain enters from below with v_k, the bottom chain from above with v_{k+1}
-    D An = shfl_down(A, 1, L), Bn = shfl_down(Bv, 1, L);
-    D A2n = shfl_up(A2, 1, L), B2n = shfl_up(B2, 1, L);
-    D cup = (t == L - 1) ? vk : fma(An, vk, Bn);
-    D cdn = (t == 0) ? vk1 : fma(A2n, vk1, B2n);
-    D P = one<double>();
+    Hb = lt[3 * L + t];
+  } else {
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
       const int r = r0 + i;
-      if (i < M && r < N && r < k) {
-        P = mul(P, mul(nbmh, pw[r]));
-        Rv[i] = from_d<S>(fma(P, cup, to_d(Rv[i])));
+      if (i < M && r < N) {
+        if (r < k) {
+          const D p = piv[i + 1];
+          Eu = mul(p, fma(nbmh, Eu, Rv[i]));
+          Ht = mul(Ht, mul(nbmh, p));
+          Rv[i] = Eu;
+        } else if (r == k) {
+          Rv[i] = vk;
+        } else if (r == k + 1) {
+          Rv[i] = vk1;
+        }
       }
     }
-    P = one<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
       const int r = r0 + i;
       if (i < M && r < N && r > k + 1) {
-        P = mul(P, mul((r == N - 1) ? nbmh_floor : nbmh, pb[r]));
-        Rv[i] = from_d<S>(fma(P, cdn, to_d(Rv[i])));
+        const D p = piv[i + 1];
+        Ed = mul(p, fma(nbmh, Ed, Rv[i]));
+        Hb = mul(Hb, mul(nbmh, p));
+        Rv[i] = Ed;
+      }
+    }
+  }
+  {
+    // the top chain runs upward and enters from below with v_k; the bottom
+    // chain runs downward and enters from above with v_{k+1}
+    const ChainPair cc = scan_pair(Hb, Ed, vk1, Ht, Eu, vk, t, L, tot);
+    if (wave_top) {
+      D dl = cc.up;
+#pragma unroll
+      for (int i = MAXM - 1; i >= 0; --i)
+        if (i < M) {
+          dl = mul(piv[i + 1], mul(nbmh, dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+    } else if (wave_bot) {
+      D dl = cc.down;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i)
+        if (i < M) {
+          dl = mul(piv[i + 1], mul(nbmh, dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+    } else {
+      D dl = cc.up;
+#pragma unroll
+      for (int i = MAXM - 1; i >= 0; --i) {
+        const int r = r0 + i;
+        if (i < M && r < N && r < k) {
+          dl = mul(piv[i + 1], mul(nbmh, dl));
+          Rv[i] = add(Rv[i], dl);
+        }
+      }
+      dl = cc.down;
+#pragma unroll
+      for (int i = 0; i < MAXM; ++i) {
+        const int r = r0 + i;
+        if (i < M && r < N && r > k + 1) {
+          dl = mul(piv[i + 1], mul(nbmh, dl));
+          Rv[i] = add(Rv[i], dl);
+        }
       }
     }
   }
@@ -401,12 +572,12 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   C<S>* myw = lds + cw * stride + t * (M + 1);
 #pragma unroll
   for (int i = 0; i < MAXM; ++i) {
-    if (i < M && r0 + i < N) myw[i] = Rv[i];
+    if (i < M && r0 + i < N) myw[i] = from_d<S>(Rv[i]);
   }
   __syncthreads();
   for (int c = 0; c < ncols; ++c) {
     C<S>* col = dst + (size_t)(m0 + c) * N;
-    for (int r = lane; r < N; r += 64) {
+    for (int r = lane; r < N; r += kPassAThreads) {
       int q = int((float(r) + 0.5f) * invM);
       col[r] = lds[c * stride + r + q];
     }
@@ -415,18 +586,22 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 
 template <typename S, int MAXM>
 constexpr int pass_a_lds() {
-  return int(sizeof(C<S>) * 64 * (MAXM + 1) + sizeof(D) * 4 * 64);
+  return int(sizeof(C<S>) * kPassAThreads * (MAXM + 1) + sizeof(D) * (4 * 64 + 16));
 }
 
+// two workgroups per CU: staging and compute of one overlap the other's memory traffic
+#define PE3D_PASS_A_ATTR __launch_bounds__(kPassAThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+
 template <typename S, int MAXM>
-__global__ __launch_bounds__(64) void pass_a_single(ProbDesc d, int koff) {
+__global__ PE3D_PASS_A_ATTR void pass_a_single(ProbDesc d, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   pass_a_body<S, MAXM>(d, blockIdx.x, koff, (C<S>*)smem_a);
 }
 
 template <typename S, int MAXM>
-__global__ __launch_bounds__(64) void pass_a_batch(const ProbDesc* __restrict__ descs,
-                                                   const WorkItem* __restrict__ items, int koff) {
+__global__ PE3D_PASS_A_ATTR void pass_a_batch(const ProbDesc* __restrict__ descs,
+                                                              const WorkItem* __restrict__ items,
+                                                              int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
@@ -434,13 +609,27 @@ __global__ __launch_bounds__(64) void pass_a_batch(const ProbDesc* __restrict__ 
 }
 
 // ============================================================== pass B
+// Per-workgroup FP64 constants of the azimuth solve for one range step.
+struct BConst {
+  D rho;     // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle
+  D rM;      // rho^M
+  D rL;      // rho^lastlen
+  D winv;    // 1 / (1 - rho^N)   (periodic closure)
+  D sinv;    // 1 / (1 - rho^(2N+2))  (sector first-row correction)
+  D lev[6];  // rho^(M 2^l), multipliers of the chunk scan
+  double s1; // sigma of the next step (its azimuth factor is applied on store)
+};
+
 template <typename S, int MAXM>
 __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int koff) {
   constexpr int NTHR = kPassBThreads;
   // sE1/sC1: forward chunk ends and carries, reused for the edge exchange;
   // sE2/sC2: backward chunk starts and carries, sE2 reused for the sector term
   __shared__ D sE1[NTHR], sC1[NTHR], sE2[NTHR], sC2[NTHR];
-  __shared__ D sPow[MAXM + 2];
+  __shared__ D sPow[MAXM + 2];   // rho^i
+  __shared__ D sPowC[64];        // rho^(M c), chunk c
+  __shared__ D sPowS[64];        // rho^(2N - m0 - len + 1), chunk c (sector)
+  __shared__ BConst K;
 
   const int tid = threadIdx.x;
   const int TD = d.td, NC = d.nc, M = d.mb;
@@ -455,67 +644,93 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   const long long j = *d.jdev + koff;
   const bool last = (koff == d.nsteps - 1);
   const bool periodic = d.periodic != 0;
-
-  const double sig = sigma_of(d, j);
-  const D rho = rho_of(sig);
-  if (tid <= MAXM + 1) sPow[tid] = cpow(rho, tid);
+  const int lastlen = NT - (NC - 1) * M;
 
   const C<S>* __restrict__ src = (const C<S>*)d.scr;
   C<S>* __restrict__ dst = (C<S>*)(last ? d.u : d.scr);
 
-  // ---- load the chunk and its two azimuth neighbours
+  // ---- load the chunk and its two azimuth neighbours (issued before the prologue)
   C<S> v[MAXM];
-  D x[MAXM];
-  D vl = zero<double>(), vr = zero<double>();
+  C<S> vl = zero<S>(), vr = zero<S>();
   if (act) {
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-      v[i] = (i < len) ? src[(size_t)(m0 + i) * N + z] : zero<S>();
+      if (i < len) v[i] = src[(size_t)(m0 + i) * N + z];
     int ml = m0 - 1, mr = m0 + len;
     if (periodic) {
       if (ml < 0) ml = NT - 1;
       if (mr >= NT) mr = 0;
-      vl = to_d(src[(size_t)ml * N + z]);
-      vr = to_d(src[(size_t)mr * N + z]);
+      vl = src[(size_t)ml * N + z];
+      vr = src[(size_t)mr * N + z];
     } else {
-      if (ml >= 0) vl = to_d(src[(size_t)ml * N + z]);
-      if (mr < NT) vr = to_d(src[(size_t)mr * N + z]);
+      if (ml >= 0) vl = src[(size_t)ml * N + z];
+      if (mr < NT) vr = src[(size_t)mr * N + z];
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) v[i] = zero<S>();
   }
+
+  // ---- FP64 step constants, once per workgroup
+  if (tid == 0) {
+    const D rho = rho_of(sigma_of(d, j));
+    K.rho = rho;
+    K.rM = cpow(rho, M);
+    K.rL = cpow(rho, lastlen);
+    const D rN = cpow(rho, NT);
+    K.winv = cdiv(one<double>(), mk<double>(1.0 - rN.re, -rN.im));
+    const D r2 = cpow(rho, 2 * (long long)NT + 2);
+    K.sinv = cdiv(one<double>(), mk<double>(1.0 - r2.re, -r2.im));
+    D lv = K.rM;
+    for (int l = 0; l < 6; ++l) {
+      K.lev[l] = lv;
+      lv = mul(lv, lv);
+    }
+    K.s1 = sigma_of(d, j + 1);
+  }
+  __syncthreads();
+  const D rho = K.rho;
+  if (tid <= MAXM + 1) sPow[tid] = cpow(rho, tid);
+  if (tid >= 64 && tid < 128 && tid - 64 < NC) sPowC[tid - 64] = cpow(K.rM, tid - 64);
+  if (!periodic && tid >= 128 && tid < 192 && tid - 128 < NC) {
+    const int cc = tid - 128;
+    const int ln = min(M, NT - cc * M);
+    sPowS[cc] = cpow(rho, 2 * (long long)NT - cc * M - ln + 1);
+  }
+
   // ---- D_theta v, forward recurrence y_m = t_m + rho y_{m-1} with zero carry
+  D x[MAXM];
   D E = zero<double>();
+  {
+    D a = to_d(vl), b = (len > 0) ? to_d(v[0]) : zero<double>();
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    if (i < len) {
-      D a = (i == 0) ? vl : to_d(v[i - 1]);
-      D b = (i + 1 < len) ? to_d(v[i + 1]) : vr;
-      D tt = sub(add(a, b), scl(2.0, to_d(v[i])));
-      E = fma(rho, E, tt);
-      x[i] = E;
-    } else {
-      x[i] = zero<double>();
+    for (int i = 0; i < MAXM; ++i) {
+      if (i < len) {
+        const D cdn = (i + 1 < len) ? to_d(v[i + 1]) : to_d(vr);
+        const D tt = sub(add(a, cdn), scl(2.0, b));
+        E = fma(rho, E, tt);
+        x[i] = E;
+        a = b;
+        b = cdn;
+      }
     }
   }
   sE1[tid] = E;
   __syncthreads();
-  // ---- carries across chunks; periodic closure y_{-1} = y_{N-1}
-  if (c == 0) {
-    const D rM = cpow(rho, M);
-    const D rL = cpow(rho, NT - (NC - 1) * M);
-    D carry = zero<double>();
-    if (periodic) {
-      D tot = zero<double>();
-      for (int cc = 0; cc < NC; ++cc) tot = add(mul(cc == NC - 1 ? rL : rM, tot), sE1[cc * TD + dl]);
-      D rN = cpow(rho, NT);
-      carry = cdiv(tot, mk<double>(1.0 - rN.re, -rN.im));
+  // ---- carries across chunks (FP64 segmented scan over the chunks of a depth)
+  const int NCp = ncp_of(NC);
+  if (tid < TD * NCp) {
+    const int sd = tid / NCp, sc = tid - sd * NCp;
+    const D e = (sc < NC) ? sE1[sc * TD + sd] : zero<double>();
+    // inclusive scan over chunks 0..NC-2 (length M each)
+    D Sv = (sc < NC - 1) ? e : zero<double>();
+    for (int l = 0, dd = 1; dd < NCp; ++l, dd <<= 1) {
+      const D up = shfl_up(Sv, dd, NCp);
+      if (sc >= dd) Sv = fma(K.lev[l], up, Sv);
     }
-    for (int cc = 0; cc < NC; ++cc) {
-      sC1[cc * TD + dl] = carry;
-      carry = add(mul(cc == NC - 1 ? rL : rM, carry), sE1[cc * TD + dl]);
-    }
+    const D Slast = (NC >= 2) ? shfl_idx(Sv, NC - 2, NCp) : zero<double>();
+    const D Elast = shfl_idx(e, NC - 1, NCp);
+    const D c0 = periodic ? mul(fma(K.rL, Slast, Elast), K.winv) : zero<double>();
+    D prev = shfl_up(Sv, 1, NCp);
+    if (sc == 0) prev = zero<double>();
+    if (sc < NC) sC1[sc * TD + sd] = fma(sPowC[sc], c0, prev);
   }
   __syncthreads();
   {
@@ -525,30 +740,30 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       if (i < len) x[i] = fma(sPow[i + 1], cin, x[i]);
   }
   // ---- backward recurrence x_m = y_m + rho x_{m+1} with zero carry
-  D Sv = zero<double>();
+  D Sb = zero<double>();
 #pragma unroll
   for (int i = MAXM - 1; i >= 0; --i) {
     if (i < len) {
-      Sv = fma(rho, Sv, x[i]);
-      x[i] = Sv;
+      Sb = fma(rho, Sb, x[i]);
+      x[i] = Sb;
     }
   }
-  sE2[tid] = Sv;
+  sE2[tid] = Sb;
   __syncthreads();
-  if (c == 0) {
-    const D rM = cpow(rho, M);
-    const D rL = cpow(rho, NT - (NC - 1) * M);
-    D carry = zero<double>();
-    if (periodic) {
-      D tot = zero<double>();
-      for (int cc = NC - 1; cc >= 0; --cc) tot = add(mul(cc == NC - 1 ? rL : rM, tot), sE2[cc * TD + dl]);
-      D rN = cpow(rho, NT);
-      carry = cdiv(tot, mk<double>(1.0 - rN.re, -rN.im));
+  // backward chain scanned in reversed chunk order (chunk NC-1 first): the
+  // chunk of length lastlen comes first, so only the wrap value sees rho^lastlen
+  if (tid < TD * NCp) {
+    const int sd = tid / NCp, sr = tid - sd * NCp;
+    const D e = (sr < NC) ? sE2[(NC - 1 - sr) * TD + sd] : zero<double>();
+    D Sv = e;
+    for (int l = 0, dd = 1; dd < NCp; ++l, dd <<= 1) {
+      const D up = shfl_up(Sv, dd, NCp);
+      if (sr >= dd) Sv = fma(K.lev[l], up, Sv);
     }
-    for (int cc = NC - 1; cc >= 0; --cc) {
-      sC2[cc * TD + dl] = carry;
-      carry = add(mul(cc == NC - 1 ? rL : rM, carry), sE2[cc * TD + dl]);
-    }
+    const D c0 = periodic ? mul(shfl_idx(Sv, NC - 1, NCp), K.winv) : zero<double>();
+    D prev = shfl_up(Sv, 1, NCp);
+    const D cin = (sr == 0) ? c0 : fma(mul(K.rL, sPowC[sr > 0 ? sr - 1 : 0]), c0, prev);
+    if (sr < NC) sC2[(NC - 1 - sr) * TD + sd] = cin;
   }
   __syncthreads();
   {
@@ -563,18 +778,18 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     if (c == 0) sE2[dl] = mul(rho, x[0]);
     __syncthreads();
     if (act) {
-      const D e0 = sE2[dl];
-      const D r2N2 = cpow(rho, 2 * (long long)NT + 2);
-      const D K = cdiv(mul(mul(rho, rho), e0), mk<double>(1.0 - r2N2.re, -r2N2.im));
-      const D pa = mul(K, cpow(rho, m0));                                  // K rho^m at i = 0
-      const D pbk = mul(K, cpow(rho, 2 * (long long)NT - m0 - len + 1));   // K rho^{2N-m} at i = len-1
+      const D Kc = mul(mul(mul(rho, rho), sE2[dl]), K.sinv);
+      const D pa = mul(Kc, sPowC[c]);   // K rho^m at i = 0
+      const D pbk = mul(Kc, sPowS[c]);  // K rho^{2N-m} at i = len-1
 #pragma unroll
       for (int i = 0; i < MAXM; ++i)
-        if (i < len) x[i] = sub(fma(rho, x[i], to_d(v[i])), sub(mul(pa, sPow[i]), mul(pbk, sPow[len - 1 - i])));
+        if (i < len)
+          x[i] = sub(fma(rho, x[i], to_d(v[i])), sub(mul(pa, sPow[i]), mul(pbk, sPow[len - 1 - i])));
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) x[i] = fma(rho, x[i], to_d(v[i]));
+    for (int i = 0; i < MAXM; ++i)
+      if (i < len) x[i] = fma(rho, x[i], to_d(v[i]));
   }
   // x now holds u^{j+1}.  Next step's azimuth factor w = u + s_{j+1} D_theta u, or store u.
   if (!last) {
@@ -582,10 +797,11 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     // new march call would: an interrupted and resumed march is bitwise equal
     // to an uninterrupted one
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) x[i] = to_d(from_d<S>(x[i]));
+    for (int i = 0; i < MAXM; ++i)
+      if (i < len) x[i] = to_d(from_d<S>(x[i]));
     D* sUf = sE1;
     D* sUl = sC1;
-    sUf[tid] = x[0];
+    sUf[tid] = (len > 0) ? x[0] : zero<double>();
     D xl = zero<double>();
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
@@ -598,14 +814,15 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       else ul = periodic ? sUl[(NC - 1) * TD + dl] : zero<double>();
       if (c < NC - 1) ur = sUf[(c + 1) * TD + dl];
       else ur = periodic ? sUf[dl] : zero<double>();
-      const double s1 = sigma_of(d, j + 1);
+      const double s1 = K.s1;
+      D a = ul;
 #pragma unroll
       for (int i = 0; i < MAXM; ++i) {
         if (i < len) {
-          D a = (i == 0) ? ul : x[i - 1];
-          D b = (i + 1 < len) ? x[i + 1] : ur;
-          D dd = sub(add(a, b), scl(2.0, x[i]));
+          const D b = (i + 1 < len) ? x[i + 1] : ur;
+          const D dd = sub(add(a, b), scl(2.0, x[i]));
           dst[(size_t)(m0 + i) * N + z] = from_d<S>(mk<double>(x[i].re - s1 * dd.im, x[i].im + s1 * dd.re));
+          a = x[i];
         }
       }
     }
@@ -671,10 +888,21 @@ template <typename S, int MAXM>
 static hipError_t run_a(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                         int nitems, int koff, hipStream_t st) {
   constexpr int lds = pass_a_lds<S, MAXM>();
+  static bool attr = false;  // allow more than the default dynamic LDS once per kernel
+  if (!attr) {
+    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, MAXM>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S, MAXM>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e1 != hipSuccess || e2 != hipSuccess) return e1 != hipSuccess ? e1 : e2;
+    attr = true;
+  }
   if (single) {
-    hipLaunchKernelGGL((pass_a_single<S, MAXM>), dim3(single->ntile_a), dim3(64), lds, st, *single, koff);
+    hipLaunchKernelGGL((pass_a_single<S, MAXM>), dim3(single->ntile_a), dim3(kPassAThreads), lds, st,
+                       *single, koff);
   } else {
-    hipLaunchKernelGGL((pass_a_batch<S, MAXM>), dim3(nitems), dim3(64), lds, st, d_descs, items, koff);
+    hipLaunchKernelGGL((pass_a_batch<S, MAXM>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs,
+                       items, koff);
   }
   return hipGetLastError();
 }
@@ -694,18 +922,9 @@ static hipError_t run_b(const ProbDesc* single, const ProbDesc* d_descs, const W
 
 hipError_t launch_pass_a(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
                          const WorkItem* items, int nitems, int koff, hipStream_t st) {
-  if (prec == 0) {
-    switch (maxm) {
-      case 16: return run_a<float, 16>(single, d_descs, items, nitems, koff, st);
-      case 32: return run_a<float, 32>(single, d_descs, items, nitems, koff, st);
-      case 64: return run_a<float, 64>(single, d_descs, items, nitems, koff, st);
-    }
-  } else {
-    switch (maxm) {
-      case 8: return run_a<double, 8>(single, d_descs, items, nitems, koff, st);
-      case 16: return run_a<double, 16>(single, d_descs, items, nitems, koff, st);
-      case 32: return run_a<double, 32>(single, d_descs, items, nitems, koff, st);
-    }
+  if (maxm == 16) {
+    if (prec == 0) return run_a<float, 16>(single, d_descs, items, nitems, koff, st);
+    return run_a<double, 16>(single, d_descs, items, nitems, koff, st);
   }
   return hipErrorInvalidValue;
 }

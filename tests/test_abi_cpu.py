@@ -84,7 +84,7 @@ def test_create_reports_unsupported_sizes(P):
     env = W.wedge_env()
     assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED
     assert _status(P, env, W.Grid(nz=64, ntheta=1025, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED
-    assert _status(P, env, W.Grid(nz=2049, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0,
+    assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0,
                                   precision=W.PREC_C128)) == P.PE3D_EUNSUPPORTED
 
 
