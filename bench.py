@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-range-scale", type=float, default=0.25)
     return ap.parse_args()
 
 
@@ -205,6 +208,29 @@ def main():
 
     for m in ms:
         m.close()
+    del us
+
+    # ---- served stream (Poisson arrivals at 200/s, continuous batching)
+    if not args.no_serve:
+        from paper_1711_00005_amd.serve import Pe3dBackend, Scheduler, report
+        tr = W.config5_trace(n=args.serve_requests, rate_hz=200.0, seed=0)
+        tr = [W.Request(r.rid, r.arrival_s, W.Problem(r.problem.env, r.problem.grid, r.problem.f_hz,
+                                                      r.problem.zs,
+                                                      max(1, int(math.ceil(r.problem.nsteps * args.serve_range_scale))),
+                                                      r.problem.name)) for r in tr]
+        log(f"serve: {len(tr)} requests")
+        sch = Scheduler(Pe3dBackend(), 1 << 30, 20)
+        t0 = time.perf_counter()
+        recs = sch.run(tr)
+        rep = report(recs, time.perf_counter() - t0)
+        rep.update(rate_hz=200.0, budget_bytes=1 << 30, chunk_steps=20, max_resident=sch.max_resident,
+                   range_scale=args.serve_range_scale,
+                   trace="config5 seed 0: f~U(20,400) Hz, zs~U(10,500) m, width in {30,90,360} deg, "
+                         "range~U(2,20) km scaled by range_scale, Nz=clamp(ceil64(6.4 f),128,4096), "
+                         "Ntheta by sqrt(f) and width, dr=clamp(1500/f,2,75) m")
+        out["serving"] = rep
+        log(f"serve: p50 {rep['p50_latency_s']:.3f} s, p99 {rep['p99_latency_s']:.3f} s, "
+            f"{rep['throughput_pt_steps_per_s']:.3e} pt*steps/s")
     print(json.dumps(out), flush=True)
 
 
