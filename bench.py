@@ -70,6 +70,27 @@ def problems_for(args):
                  "complex64 field, FP64 arithmetic")
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of a kernel from the committed counter summary,
+    or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "config4_batch_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_1711_00005_amd", "csrc", "pe3d_kernels.hip")
+    try:
+        txt = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    rec = dict(l.split()[0:2] for l in txt.splitlines() if l.startswith("kernel_sha256"))
+    if rec.get("kernel_sha256") != sha:
+        return None
+    for l in txt.splitlines():
+        f = l.split()
+        if len(f) == 3 and f[0] == "traffic_bytes" and kernel_name.startswith(f[1]):
+            return int(f[2])
+    return None
+
+
 def march_steps(P, ms, us, nsteps, chunk, use_graph):
     done = 0
     while done < nsteps:
@@ -159,7 +180,9 @@ def main():
     dom_gbs = (dom["algo_bytes"] / dom["launches"]) / (dom_avg * 1e-3) / 1e9
     step_bytes = 32.0 * npts  # both passes, complex64
     roofline = dict(bound="hbm", achieved=round(dom_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=None, kernel=dom["name"],
+                    frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom["name"]),
+                    traffic_unit="bytes per launch",
+                    algo_bytes_per_launch=dom["algo_bytes"] / dom["launches"], kernel=dom["name"],
                     step_achieved=round(step_bytes * args.steps / elapsed / 1e9, 1),
                     step_frac=round(step_bytes * args.steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
                     kernels=kernels, profiled_ms_per_step=round(prof_ms / args.profile_steps, 4))
