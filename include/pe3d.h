@@ -107,7 +107,7 @@ typedef struct { double f_hz; } pe3d_freq;
  * once (the medium depends on (theta, z) only, so it is range invariant),
  * and allocates the handle's device buffers (coefficient tables and one
  * scratch field).  The range counter starts at step j = 0 (range r0).
- * Limits of the built kernels: complex64 nz <= 4096, complex128 nz <= 2048,
+ * Limits of the built kernels: nz <= 4096 in both precisions,
  * ntheta <= 1024; nz >= 2; ntheta >= 3 (periodic) or >= 1 (sector).
  * Precision: in both modes every coefficient and every arithmetic operation
  * is FP64; PE3D_C64 stores the field (and values held between sweeps) in
@@ -208,8 +208,12 @@ pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, int32_t* n);
  *             all-water column, pb[2*nz] reciprocal bottom-up pivots for the
  *             all-bottom column,
  *   kcol[ntheta]   interface row k(m) of each column,
- *   blk[24*ntheta] per column: X diagonals (lower, diag, upper) of rows k and
- *             k+1, the two elimination multipliers and the inverse 2x2 block.
+ *   blk[24*ntheta] per column, 6 complex for row k then 6 for row k+1:
+ *             diagonal of [1 + (1/4 + d/4) X], its coefficients on the
+ *             previous and next row of the row's elimination order (row k:
+ *             k-1 and k+1; row k+1: k+2 and k), the multiplier that
+ *             eliminates that previous row, and the two entries of the
+ *             inverse interface 2x2 block giving the row's value (own, other).
  * Same validation and errors as pe3d_create (minus device errors). */
 pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
                              double* qw, double* pw, double* pb, int32_t* kcol, double* blk);

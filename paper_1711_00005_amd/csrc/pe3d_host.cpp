@@ -118,10 +118,10 @@ struct Built {
   double k0 = 0, dz = 0, dth = 0, h = 0;
   cd qb, bp, bm;
   std::vector<cd> qw, pw, pb;
-  std::vector<cd> qwT, pwT, pbT, lane_tr;  // lane-major copies for the depth kernel
+  std::vector<cd> tabG, tabC, tabP;  // depth-kernel chain tables and lane products
   std::vector<int> k;
-  std::vector<std::array<cd, 12>> blk;
-  int lpc = 0, ma = 0, maxm_a = 0, ntile_a = 0;
+  std::vector<std::array<cd, 12>> rec;  // interface rows of each column
+  int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
   int nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
 };
 
@@ -130,12 +130,22 @@ struct Built {
 // rows per lane; pass B uses nc azimuth chunks of mb nodes times td depths.
 pe3d_status choose_shapes(Built& b) {
   const int N = b.N, NT = b.NT;
-  // pass A: at most 16 rows per lane, L = power of two in 4..256 lanes per column
-  b.maxm_a = 16;
-  b.lpc = std::max(4, next_pow2((N + 15) / 16));
-  if (b.lpc > 256) return PE3D_EUNSUPPORTED;
-  b.ma = (N + b.lpc - 1) / b.lpc;
-  const int cpw = 256 / b.lpc;
+  // pass A: the fewest lanes L (power of two, 4..256) with M = ceil((nz+1)/(L-1))
+  // rows per lane, rounded up to an odd number (conflict-free LDS strides),
+  // at most 17; nz <= (L-1) M - 1 leaves room for the two chains' leading
+  // zero slots in every column
+  int L = 4, M = 0;
+  for (;; L *= 2) {
+    if (L > 256) return PE3D_EUNSUPPORTED;
+    M = (N + 1 + L - 2) / (L - 1);
+    if (M % 2 == 0) ++M;
+    if (M < 3) M = 3;
+    if (M <= 17) break;
+  }
+  b.lpc = L;
+  b.ma = M;
+  b.lt = (N + 3 * M - 1) / M;
+  const int cpw = 256 / L;
   b.ntile_a = (NT + cpw - 1) / cpw;
 
   // about 16 azimuth nodes per chunk, at most 64 chunks (8 depths per workgroup)
@@ -222,10 +232,10 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   }
   // per-column interface rows
   b.k.resize(NT);
-  b.blk.resize(NT);
+  b.rec.resize(NT);
   double maxb = 0.0, minpiv = 1e300;
   int kmin = N, kmax = 0;
-  std::vector<double> rho(N);
+  const cd bp = b.bp;
   for (int m = 0; m < NT; ++m) {
     double th = b.periodic ? g.theta0 + m * b.dth : g.theta0 - 0.5 * g.width + (m + 1) * b.dth;
     double D = interp_bathy(e, th);
@@ -255,20 +265,20 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     cd xl0, xd0, xu0, xl1, xd1, xu1;
     xrow(k, xl0, xd0, xu0);
     xrow(k + 1, xl1, xd1, xu1);
-    cd fk = 0.0, gk1 = 0.0;
+    // eliminating row k-1 (top chain) into row k and row k+2 (bottom chain)
+    // into row k+1 leaves the 2x2 block [[P, c01], [c10, Q]]
+    const cd cft = -(bm * xl0), cfb = -(bm * xu1);
     cd P = 1.0 + bm * xd0, Q = 1.0 + bm * xd1;
     if (k >= 1) {
       cd pxl, pxd, pxu;
       xrow(k - 1, pxl, pxd, pxu);  // a water row: its upper coefficient is h
-      fk = -(bm * xl0) / dw[k - 1];
-      P += fk * (bm * pxu);
+      P += cft * b.pw[k - 1] * (bm * pxu);
     }
     if (k + 2 <= N - 1) {
       cd nxl, nxd, nxu;
-      xrow(k + 2, nxl, nxd, nxu);  // a bottom row (scaled if it is the rigid floor)
+      xrow(k + 2, nxl, nxd, nxu);  // a bottom row (halved if it is the rigid floor)
       if (k + 2 == N - 1) nxl *= floor_scale;
-      gk1 = -(bm * xu1) / eb[k + 2];
-      Q += gk1 * (bm * nxl);
+      Q += cfb * b.pb[k + 2] * (bm * nxl);
     }
     cd c01 = bm * xu0, c10 = bm * xl1;
     cd det = P * Q - c01 * c10;
@@ -276,7 +286,10 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     minpiv = std::min(minpiv, std::abs(det) / std::max(std::abs(P), std::abs(Q)));
     if (det == 0.0 || !std::isfinite(std::abs(det))) return PE3D_EUNSUPPORTED;
     cd id = 1.0 / det;
-    b.blk[m] = {xl0, xd0, xu0, xl1, xd1, xu1, fk, gk1, Q * id, -c01 * id, -c10 * id, P * id};
+    // row k (top chain: previous row k-1, next row k+1), then row k+1
+    // (bottom chain, reversed: previous row k+2, next row k)
+    b.rec[m] = {1.0 + bp * xd0, bp * xl0, bp * xu0, cft, Q * id, -c01 * id,
+                1.0 + bp * xd1, bp * xu1, bp * xl1, cfb, P * id, -c10 * id};
   }
   // pivots actually used: water rows < kmax, bottom rows > kmin + 1
   for (int l = 0; l < kmax; ++l) {
@@ -290,47 +303,52 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   if (!(minpiv > 1e-10 * maxb)) return PE3D_EUNSUPPORTED;
   pe3d_status st = choose_shapes(b);
   if (st != PE3D_OK) return st;
-  // lane-major copies: entry [i][t] holds the value for row t*M - 1 + i (pivots)
-  // or t*M + i (n^2 - 1), zero outside the column
-  const int L = b.lpc, M = b.ma;
+
+  // chain tables: chain 0 = rows 0..N-2 of the all-water column (top-down
+  // pivots), chain 1 = rows N-1..1 of the all-bottom column (bottom-up
+  // pivots, chain row bb = N-1-l); chain row r at [(r+M) % M][(r+M) / M]
+  const int L = b.lpc, M = b.ma, LT = b.lt;
+  const size_t MLT = (size_t)M * LT;
   const cd nbmh = -bm * h;
-  b.qwT.assign((size_t)M * L, 0.0);
-  b.pwT.assign((size_t)(M + 2) * L, 0.0);
-  b.pbT.assign((size_t)(M + 2) * L, 0.0);
-  b.lane_tr.assign((size_t)4 * L, 1.0);
-  auto at = [&](const std::vector<cd>& v, int r) { return (r >= 0 && r < N) ? v[r] : cd(0.0); };
-  for (int t = 0; t < L; ++t) {
-    const int r0 = t * M;
-    for (int i = 0; i < M; ++i) b.qwT[(size_t)i * L + t] = at(b.qw, r0 + i);
-    for (int i = 0; i < M + 2; ++i) {
-      b.pwT[(size_t)i * L + t] = at(b.pw, r0 - 1 + i);
-      b.pbT[(size_t)i * L + t] = at(b.pb, r0 - 1 + i);
-    }
-    // transfer products of a lane whose M rows are all top / all bottom rows
-    cd ft = 1.0, gb = 1.0, ht = 1.0, hb = 1.0;
-    for (int i = 0; i < M; ++i) {
-      ft *= nbmh * at(b.pw, r0 + i - 1);
-      gb *= nbmh * at(b.pb, r0 + i + 1);
-      ht *= nbmh * at(b.pw, r0 + i);
-      hb *= nbmh * at(b.pb, r0 + i);
-    }
-    b.lane_tr[0 * (size_t)L + t] = ft;
-    b.lane_tr[1 * (size_t)L + t] = gb;
-    b.lane_tr[2 * (size_t)L + t] = ht;
-    b.lane_tr[3 * (size_t)L + t] = hb;
+  b.tabG.assign(2 * MLT, 0.0);
+  b.tabC.assign(2 * MLT, 0.0);
+  auto tix = [&](int r) { const int rp = r + M; return (size_t)(rp % M) * LT + rp / M; };
+  for (int r = 0; r <= N - 2; ++r) {
+    b.tabG[tix(r)] = b.pw[r];
+    b.tabC[tix(r)] = 1.0 + bp * (b.qw[r] - 2.0 * h);
   }
+  for (int bb = 0; bb <= N - 2; ++bb) {
+    b.tabG[MLT + tix(bb)] = b.pb[N - 1 - bb];
+    cd c = 1.0 + bp * (b.qb - 2.0 * h);
+    if (bb == 0) c *= floor_scale;
+    b.tabC[MLT + tix(bb)] = c;
+  }
+  // lane products by (chain, leading zero slots sc = 1..M, lane in chain tc):
+  // slot j of the lane holds chain row tc*M + j - sc
+  b.tabP.assign((size_t)2 * (M + 1) * L, 0.0);
+  for (int ch = 0; ch < 2; ++ch)
+    for (int sc = 1; sc <= M; ++sc)
+      for (int tc = 0; tc < L; ++tc) {
+        cd p = 1.0;
+        for (int j = 0; j < M; ++j) {
+          const int r = tc * M + j - sc;
+          const cd gv = (r + M < (int)MLT) ? b.tabG[ch * MLT + tix(r)] : cd(0.0);
+          p *= nbmh * gv;
+        }
+        b.tabP[((size_t)ch * (M + 1) + sc) * L + tc] = p;
+      }
   return PE3D_OK;
 }
 
 size_t table_bytes(const Built& b) {
   const size_t csz = 16;  // coefficient tables are FP64 in both precisions
   size_t n = 0;
-  n += 3 * (size_t)b.N * csz;             // qw, pw, pb
-  n += (size_t)b.NT * 12 * csz;           // column blocks
-  n += (size_t)(3 * b.ma + 4 + 4) * b.lpc * csz;  // qwT, pwT, pbT, lane transfer products
-  n += (size_t)b.NT * sizeof(int);        // kcol
+  n += 2 * 2 * (size_t)b.ma * b.lt * csz;        // tabG, tabC
+  n += 2 * (size_t)(b.ma + 1) * b.lpc * csz;    // tabP
+  n += (size_t)b.NT * 12 * csz;                 // rec
+  n += (size_t)b.NT * sizeof(int);              // kcol
   n = (n + 255) & ~size_t(255);
-  n += 256;                               // step counter
+  n += 256;                                     // step counter
   return n;
 }
 size_t field_bytes(const Built& b) { return (size_t)b.N * b.NT * (b.prec ? 16 : 8); }
@@ -352,6 +370,7 @@ void pack(const std::vector<cd>& v, std::vector<unsigned char>& out, size_t off)
 struct pe3d_handle_s {
   int prec = 0;
   int maxm_a = 0, maxm_b = 0;
+  int lds_a = 0;  // dynamic LDS of a pass A workgroup
   ProbDesc desc{};
   void* d_tables = nullptr;
   void* d_scr = nullptr;
@@ -376,6 +395,7 @@ struct BatchPlan {
   int n = 0;
   struct Class {
     int maxm;
+    int lds = 0;                       // pass A: dynamic LDS (largest of the class)
     WorkItem* d_items;
     std::vector<int> nitems_at;        // active items at step k (problems sorted by steps)
     std::vector<double> bytes_prefix;  // algorithmic bytes of the first i items
@@ -528,8 +548,8 @@ pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const p
   for (int m = 0; m < b.NT; ++m) {
     kcol[m] = b.k[m];
     for (int q = 0; q < 12; ++q) {
-      blk[24 * m + 2 * q] = b.blk[m][q].real();
-      blk[24 * m + 2 * q + 1] = b.blk[m][q].imag();
+      blk[24 * m + 2 * q] = b.rec[m][q].real();
+      blk[24 * m + 2 * q + 1] = b.rec[m][q].imag();
     }
   }
   return PE3D_OK;
@@ -549,33 +569,26 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   const size_t csz = 16;
   const size_t tb = table_bytes(b);
   std::vector<unsigned char> img(tb, 0);
-  const size_t o_qw = 0, o_pw = o_qw + b.N * csz, o_pb = o_pw + b.N * csz;
-  const size_t o_blk = o_pb + b.N * csz;
-  const size_t o_qwT = o_blk + (size_t)b.NT * 12 * csz;
-  const size_t o_pwT = o_qwT + (size_t)b.ma * b.lpc * csz;
-  const size_t o_pbT = o_pwT + (size_t)(b.ma + 2) * b.lpc * csz;
-  const size_t o_lt = o_pbT + (size_t)(b.ma + 2) * b.lpc * csz;
-  const size_t o_k = o_lt + (size_t)4 * b.lpc * csz;
+  const size_t o_G = 0, o_C = o_G + b.tabG.size() * csz, o_P = o_C + b.tabC.size() * csz;
+  const size_t o_rec = o_P + b.tabP.size() * csz;
+  const size_t o_k = o_rec + (size_t)b.NT * 12 * csz;
   const size_t o_j = tb - 256;
-  std::vector<cd> blkflat;
-  blkflat.reserve((size_t)b.NT * 12);
-  for (auto& a : b.blk)
-    for (auto& z : a) blkflat.push_back(z);
-  pack<double>(b.qw, img, o_qw);
-  pack<double>(b.pw, img, o_pw);
-  pack<double>(b.pb, img, o_pb);
-  pack<double>(blkflat, img, o_blk);
-  pack<double>(b.qwT, img, o_qwT);
-  pack<double>(b.pwT, img, o_pwT);
-  pack<double>(b.pbT, img, o_pbT);
-  pack<double>(b.lane_tr, img, o_lt);
+  std::vector<cd> recflat;
+  recflat.reserve((size_t)b.NT * 12);
+  for (auto& a : b.rec)
+    for (auto& z : a) recflat.push_back(z);
+  pack<double>(b.tabG, img, o_G);
+  pack<double>(b.tabC, img, o_C);
+  pack<double>(b.tabP, img, o_P);
+  pack<double>(recflat, img, o_rec);
   std::memcpy(img.data() + o_k, b.k.data(), b.NT * sizeof(int));
 
   pe3d_handle h = new (std::nothrow) pe3d_handle_s();
   if (!h) return PE3D_ENOMEM;
   h->prec = b.prec;
-  h->maxm_a = b.maxm_a;
+  h->maxm_a = b.ma;
   h->maxm_b = b.maxm_b;
+  h->lds_a = pass_a_lds(b.prec, b.lpc, b.N, b.ma);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return PE3D_EDEVICE;
@@ -613,11 +626,11 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.lpc = b.lpc;
   d.ma = b.ma;
   d.ntile_a = b.ntile_a;
-  d.qwT = base + o_qwT;
-  d.pwT = base + o_pwT;
-  d.pbT = base + o_pbT;
-  d.lane_tr = base + o_lt;
-  d.blk = base + o_blk;
+  d.lt = b.lt;
+  d.tabG = base + o_G;
+  d.tabC = base + o_C;
+  d.tabP = base + o_P;
+  d.rec = base + o_rec;
   d.kcol = reinterpret_cast<const int*>(base + o_k);
   d.h = b.h;
   d.qb_re = b.qb.real();
@@ -696,7 +709,7 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
-          return launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, st);
+          return launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, h->lds_a, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
     if (prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
@@ -746,6 +759,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::map<int, std::vector<WorkItem>> ia, ib;
   std::map<int, std::vector<int>> ia_steps, ib_steps;  // steps of the problem of each item
   std::map<int, std::vector<double>> ia_bytes, ib_bytes;
+  std::map<int, int> ia_lds;
   for (int p = 0; p < np; ++p) {
     pe3d_handle h = hs[order[p]];
     descs[p] = h->desc;
@@ -756,6 +770,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     const ProbDesc& hd = h->desc;
     const double esz = h->prec ? 16.0 : 8.0;
     const int cpw = 256 / hd.lpc;
+    ia_lds[h->maxm_a] = std::max(ia_lds[h->maxm_a], h->lds_a);
     for (int t = 0; t < hd.ntile_a; ++t) {
       ia[h->maxm_a].push_back({p, t});
       ia_steps[h->maxm_a].push_back(nsteps[order[p]]);
@@ -809,6 +824,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     }
   };
   emit(ia, ia_steps, ia_bytes, P.a);
+  for (auto& c : P.a) c.lds = ia_lds[c.maxm];
   emit(ib, ib_steps, ib_bytes, P.b);
   if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
@@ -819,7 +835,7 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
     for (auto& c : P.a) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st);
+            return launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
           }) != hipSuccess)
         return PE3D_EDEVICE;
     }

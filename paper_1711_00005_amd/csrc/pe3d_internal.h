@@ -11,23 +11,6 @@ struct alignas(2 * sizeof(R)) cplx {
   R re, im;
 };
 
-// Per-column data of the depth pass.  Row k(m) is the last water node of
-// column m (clamped to 0..nz-2); rows k and k+1 hold the column's own depth
-// operator coefficients (they straddle the water/bottom interface), all other
-// rows use the shared all-water (above) or all-bottom (below) coefficients.
-// fk, gk1: elimination multipliers that bring the top and bottom
-// eliminations onto rows k and k+1; inv: inverse of the resulting 2x2 block.
-// A rigid floor row that belongs to the bottom region is divided by 2 in the
-// bottom system (its lower coefficient becomes beta_- h like every other
-// bottom row; its right-hand side is halved to match).
-template <typename R>
-struct ColBlock {
-  cplx<R> xl0, xd0, xu0;  // X diagonals of row k
-  cplx<R> xl1, xd1, xu1;  // X diagonals of row k+1
-  cplx<R> fk, gk1;
-  cplx<R> i00, i01, i10, i11;
-};
-
 // Everything a kernel needs to march one problem.  Plain data; passed by
 // value as a kernel argument (single-problem launches) or stored in a device
 // array (batched launches).
@@ -37,17 +20,22 @@ struct ProbDesc {
   long long* jdev;      // device step counter (j of u on entry of the call)
   int nsteps;           // steps of the current call
   int nz, nth, periodic, rigid;
-  // depth pass (pass A)
-  int lpc;              // lanes per column (power of two, <= 64)
-  int ma;               // rows per lane
-  int ntile_a;          // number of 64-lane tiles = ceil(nth / (64/lpc))
-  // lane-major tables (entry [i][t] at i*lpc + t, t = lane in the column), FP64 complex:
-  const void* qwT;      // [ma][lpc]: n^2-1 of the water column at row t*ma + i
-  const void* pwT;      // [ma+2][lpc]: 1/pivot of the all-water column (top-down) at row t*ma - 1 + i
-  const void* pbT;      // [ma+2][lpc]: 1/pivot of the all-bottom column (bottom-up), same rows
-  const void* lane_tr;  // [4][lpc]: chunk transfer products of a lane whose rows are all top
-                        //   (elimination, back substitution) or all bottom
-  const void* blk;      // [nth] ColBlock<double>
+  // depth pass (pass A): L lanes per column, M rows per lane; see pe3d_kernels.hip
+  int lpc;              // L, lanes per column (power of two, 4..256)
+  int ma;               // M, rows per lane (odd, <= 17), nz <= (L-1) M - 1
+  int ntile_a;          // workgroups = ceil(nth / (256 / L))
+  int lt;               // LT, columns of the lane-major chain tables
+  // chain tables, FP64 complex, [2][M][LT] (chain 0: all-water column top-down,
+  // chain 1: all-bottom column bottom-up), chain row r at [(r+M) % M][(r+M) / M],
+  // zero outside rows 0..nz-2:
+  const void* tabG;     // 1 / pivot of the chain row
+  const void* tabC;     // diagonal of [I + beta_+ X] of the chain row
+  const void* tabP;     // [2][M+1][L]: product of -beta_- h G over a lane's M slots,
+                        //   by (chain, leading zero slots sc, lane in chain)
+  const void* rec;      // [nth][12] interface rows of each column: for row k then
+                        //   row k+1: RHS diagonal, previous and next coefficient
+                        //   along the chain, elimination multiplier, and the two
+                        //   entries of the 2x2 block inverse that give its value
   const int* kcol;      // [nth] row k(m)
   double h;             // (k0 dz)^-2
   double qb_re, qb_im;  // n^2-1 of the bottom half-space
@@ -72,8 +60,9 @@ constexpr int kPassBThreads = 512;
 // kernel launchers (pe3d_kernels.hip); all return a hipError_t
 // single != nullptr: one problem, grid from single->ntile_a / ntile_b, the
 // descriptor passed by value.  Otherwise a batched launch over nitems items.
-hipError_t launch_pass_a(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, hipStream_t st);
+hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc* d_descs,
+                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st);
+int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pass A workgroup
 hipError_t launch_pass_b(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
                          const WorkItem* items, int nitems, int koff, hipStream_t st);
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n,

@@ -145,114 +145,126 @@ __device__ __forceinline__ int ncp_of(int nc) {
 }
 
 // ============================================================== pass A
-// Workgroup of 256 lanes; a depth column is split over L lanes (L a power of
-// two, 4..256), each lane holding M <= MAXM consecutive rows; 256/L <= 64
-// columns per workgroup.  Columns wider than a wavefront (L > 64) combine the
-// per-wavefront scan totals through LDS.
+// Workgroup of 256 lanes; a depth column uses L lanes (a power of two,
+// 4..256; columns wider than a wavefront combine per-wavefront scan totals
+// through LDS), 256/L columns per workgroup.  M (odd, <= 17) rows per lane.
 //
-// A wavefront whose lanes all hold rows strictly above the interface rows of
-// their column (or all strictly below) runs a branch-free path; lanes holding
-// an interface row, or a partial chunk, run the general path.  With the
-// rigid floor row pre-scaled by 1/2 on the host, every row of the bottom
-// region has lower coefficient beta_- h.
+// Lane layout of a column with interface rows k, k+1 (twisted factorisation):
+//   top chain    rows 0..k in natural order, preceded by s >= 1 zero slots
+//                so that row k is the last slot of lane a-1;
+//   bottom chain rows N-1..k+1 (reversed), preceded by sb >= 1 zero slots
+//                so that row k+1 is the last slot of lane a+nbl-1;
+//   idle lanes   after the bottom chain.
+// Both chains are eliminated in increasing lane order and back-substituted
+// in decreasing lane order, so every lane runs the same code; the two
+// interface rows sit in the last slot of their chain's last lane (the
+// "head" lanes).  The leading zero slots have zero table entries, so a
+// chain's first lane has a zero transfer product and no carry crosses from
+// one chain into the next.
+//
+// Recurrences (G = 1/pivot, nbmh = -beta_- h the off-diagonal of every
+// non-interface row of [I + beta_- X] with the rigid floor row halved):
+//   elimination     yh_j = G_j (R_j + nbmh yh_{j-1})
+//   back substitution x_j = yh_j + nbmh G_j x_{j+1}
+// Both have the per-slot multiplier nbmh G_j, so one table of lane transfer
+// products serves the two scans.
 constexpr int kPassAThreads = 256;
 
-struct ChainPair {
-  D down, up;
-};
-// Exclusive carries of a downward chain (lane t's map applied after lanes
-// 0..t-1 of the column) and of an upward chain (after lanes t+1..L-1).  Each
-// lane passes its chunk map (A, B): x -> A x + B.  tot: LDS scratch, 4 complex
-// per wavefront.
-__device__ __forceinline__ ChainPair scan_pair(D Ad, D Bd, D init_d, D Au, D Bu, D init_u, int t, int L,
-                                               D* tot) {
-  const int w = L < 64 ? L : 64;  // segment width inside a wavefront
-  const int tw = t & (w - 1);     // lane within the segment
-  D ad = Ad, bd = Bd, au = Au, bu = Bu;
-  for (int dd = 1; dd < w; dd <<= 1) {
-    D ap = shfl_up(ad, dd, w), bp = shfl_up(bd, dd, w);
-    D aq = shfl_down(au, dd, w), bq = shfl_down(bu, dd, w);
-    if (tw >= dd) {
-      bd = fma(ad, bp, bd);
-      ad = mul(ad, ap);
-    }
-    if (tw + dd < w) {
-      bu = fma(au, bq, bu);
-      au = mul(au, aq);
+// Exclusive scan of the affine lane maps x -> A x + B within a column:
+// UP: lane t receives the composition of lanes 0..t-1 applied to 0; DOWN:
+// of lanes L-1..t+1.  tot: LDS scratch, 2 complex per wavefront.
+template <bool UP>
+__device__ __forceinline__ D scan_excl(D A, D B, int t, int L, D* tot) {
+  const int w = L < 64 ? L : 64;
+  const int tw = t & (w - 1);
+#pragma unroll
+  for (int dd = 1; dd < 64; dd <<= 1) {
+    if (dd < w) {
+      const D ap = UP ? shfl_up(A, dd, w) : shfl_down(A, dd, w);
+      const D bq = UP ? shfl_up(B, dd, w) : shfl_down(B, dd, w);
+      if (UP ? (tw >= dd) : (tw + dd < w)) {
+        B = fma(A, bq, B);
+        A = mul(A, ap);
+      }
     }
   }
-  D ade = shfl_up(ad, 1, w), bde = shfl_up(bd, 1, w);
-  D aue = shfl_down(au, 1, w), bue = shfl_down(bu, 1, w);
-  if (tw == 0) {
-    ade = one<double>();
-    bde = zero<double>();
+  D ea = UP ? shfl_up(A, 1, w) : shfl_down(A, 1, w);
+  D eb = UP ? shfl_up(B, 1, w) : shfl_down(B, 1, w);
+  if (UP ? (tw == 0) : (tw == w - 1)) {
+    ea = one<double>();
+    eb = zero<double>();
   }
-  if (tw == w - 1) {
-    aue = one<double>();
-    bue = zero<double>();
-  }
-  D xd = init_d, xu = init_u;
+  D x = zero<double>();
   if (L > 64) {
     const int wave = threadIdx.x >> 6;
-    if (tw == w - 1) {
-      tot[4 * wave + 0] = ad;
-      tot[4 * wave + 1] = bd;
-    }
-    if (tw == 0) {
-      tot[4 * wave + 2] = au;
-      tot[4 * wave + 3] = bu;
+    if (UP ? (tw == 63) : (tw == 0)) {
+      tot[2 * wave + 0] = A;
+      tot[2 * wave + 1] = B;
     }
     __syncthreads();
-    const int nw = L >> 6;
-    const int wc = (t >> 6);
+    const int nwv = L >> 6;
+    const int wc = t >> 6;
     const int w0 = wave - wc;
-    for (int q = 0; q < wc; ++q) xd = fma(tot[4 * (w0 + q) + 0], xd, tot[4 * (w0 + q) + 1]);
-    for (int q = nw - 1; q > wc; --q) xu = fma(tot[4 * (w0 + q) + 2], xu, tot[4 * (w0 + q) + 3]);
+    if (UP) {
+      for (int q = 0; q < wc; ++q) x = fma(tot[2 * (w0 + q)], x, tot[2 * (w0 + q) + 1]);
+    } else {
+      for (int q = nwv - 1; q > wc; --q) x = fma(tot[2 * (w0 + q)], x, tot[2 * (w0 + q) + 1]);
+    }
     __syncthreads();
   }
-  ChainPair r;
-  r.down = fma(ade, xd, bde);
-  r.up = fma(aue, xu, bue);
-  return r;
+  return fma(ea, x, eb);
 }
 
-template <typename S, int MAXM>
-__device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, C<S>* lds) {
+__host__ __device__ constexpr int pass_a_align(int b) { return (b + 15) & ~15; }
+
+// LDS of one workgroup: 256/L column buffers of N + 2(M+1) entries (rows
+// -(M+1)..N+M, zero outside the column), the interface exchange (2 complex
+// per column) and the scan totals (2 complex per wavefront).
+__host__ __device__ constexpr int pass_a_lds_bytes(int esz, int L, int N, int M) {
+  return pass_a_align((kPassAThreads / L) * (N + 2 * (M + 1)) * esz) + (kPassAThreads / L) * 2 * 16 +
+         8 * 16;
+}
+
+template <typename S, int M>
+__device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
   const int lane = threadIdx.x;
   const int L = d.lpc;
-  const int cpw = kPassAThreads / L;  // columns per workgroup
-  const int cw = lane / L;
-  const int t = lane - cw * L;
-  const int N = d.nz, NT = d.nth, M = d.ma;
+  const int lgL = 31 - __clz(L);
+  const int cpw = kPassAThreads >> lgL;
+  const int cw = lane >> lgL;
+  const int t = lane & (L - 1);
+  const int N = d.nz, NT = d.nth;
   const int m0 = tile * cpw;
   const int m = m0 + cw;
   const bool colok = m < NT;
+  const int ncols = min(cpw, NT - m0);
+  constexpr int GA = M + 1;
+  const int CS = N + 2 * GA;
+  C<S>* buf = reinterpret_cast<C<S>*>(smem);
+  D* xch = reinterpret_cast<D*>(smem + pass_a_align(cpw * CS * int(sizeof(C<S>))));
+  D* tot = xch + 2 * cpw;
   const bool first = (koff == 0);
   const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
   C<S>* __restrict__ dst = (C<S>*)d.scr;
-  const int stride = L * (M + 1);
-  const int ncols = min(cpw, NT - m0);
-  D* slots = reinterpret_cast<D*>(lds + kPassAThreads * (MAXM + 1));  // 4 per column
-  D* tot = slots + 4 * 64;                                              // 4 per wavefront
-  const float invM = 1.0f / float(M);
 
-  for (int q = t; q < 4; q += L) slots[cw * 4 + q] = zero<double>();
-
-  // ---- stage the columns into LDS (coalesced); on the first step apply [I + s_0 D_theta]
+  // ---- zero the guard rows of every column buffer, stage the columns (coalesced);
+  //      on the first step apply [I + s_0 D_theta] from the neighbouring columns
+  for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
+    const int c = i / (2 * GA);
+    const int g = i - c * 2 * GA;
+    buf[c * CS + (g < GA ? g : N + g)] = zero<S>();
+  }
   if (!first) {
     for (int c = 0; c < ncols; ++c) {
       const C<S>* col = src + (size_t)(m0 + c) * N;
-      for (int r = lane; r < N; r += kPassAThreads) {
-        int q = int((float(r) + 0.5f) * invM);
-        lds[c * stride + r + q] = col[r];
-      }
+      C<S>* b = buf + c * CS + GA;
+      for (int r = lane; r < N; r += kPassAThreads) b[r] = col[r];
     }
   } else {
     const long long j = *d.jdev + koff;
     const double s0 = sigma_of(d, j);  // s_0 = i * s0
     for (int c = 0; c < ncols; ++c) {
       const int mm = m0 + c;
-      const C<S>* col = src + (size_t)mm * N;
       int ml = mm - 1, mr = mm + 1;
       bool hl = true, hr = true;
       if (d.periodic) {
@@ -262,350 +274,167 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         hl = ml >= 0;
         hr = mr < NT;
       }
+      const C<S>* col = src + (size_t)mm * N;
       const C<S>* coll = src + (size_t)(hl ? ml : mm) * N;
       const C<S>* colr = src + (size_t)(hr ? mr : mm) * N;
+      C<S>* b = buf + c * CS + GA;
       for (int r = lane; r < N; r += kPassAThreads) {
-        D uc = to_d(col[r]);
-        D ul = hl ? to_d(coll[r]) : zero<double>();
-        D ur = hr ? to_d(colr[r]) : zero<double>();
-        D dd = sub(add(ul, ur), scl(2.0, uc));
-        D w = mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re);  // u + i s0 dd
-        int q = int((float(r) + 0.5f) * invM);
-        lds[c * stride + r + q] = from_d<S>(w);
+        const D uc = to_d(col[r]);
+        const D ul = hl ? to_d(coll[r]) : zero<double>();
+        const D ur = hr ? to_d(colr[r]) : zero<double>();
+        const D dd = sub(add(ul, ur), scl(2.0, uc));
+        b[r] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));  // u + i s0 dd
       }
     }
   }
 
-  // ---- constants (FP64), lane classification, the lane's pivots (loaded once, coalesced)
-  const double h = d.h;
-  const D qb = mk<double>(d.qb_re, d.qb_im);
-  const D bp = mk<double>(d.bp_re, d.bp_im);
-  const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
-  const D* __restrict__ qwT = (const D*)d.qwT;
-  const D* __restrict__ pwT = (const D*)d.pwT;
-  const D* __restrict__ pbT = (const D*)d.pbT;
-  const D* __restrict__ lt = (const D*)d.lane_tr;  // [4][L]: Ft, Gb, Ht, Hb of full lanes
+  // ---- lane role
   const int k = colok ? d.kcol[m] : 0;
-  const ColBlock<double>* Bp = colok ? ((const ColBlock<double>*)d.blk) + m : nullptr;
-  const bool rigid = d.rigid != 0;
-  const int r0 = t * M;
-  const bool full = colok && (r0 + M <= N);
-  const bool ftop = full && (r0 + M <= k);   // every row above the interface rows
-  const bool fbot = full && (r0 >= k + 2);   // every row below them
-  const bool wave_top = __all(ftop);
-  const bool wave_bot = __all(fbot);
-  // piv[i]: reciprocal pivot of row r0-1+i (top-down above the interface rows,
-  // bottom-up below them); zero outside the column
-  __syncthreads();
-  D piv[MAXM + 2];
-#pragma unroll
-  for (int i = 0; i < MAXM + 2; ++i) {
-    const int r = r0 - 1 + i;
-    piv[i] = (i < M + 2) ? (r < k ? pwT[i * L + t] : pbT[i * L + t]) : zero<double>();
-  }
-  const C<S>* my = lds + cw * stride + t * (M + 1);
+  const int a = (k + 1) / M + 1;
+  const int s = a * M - (k + 1);
+  const int nbl = (N - k - 1) / M + 1;
+  const int sb = nbl * M - (N - k - 1);
+  const bool top = colok && t < a;
+  const bool bot = colok && !top && t < a + nbl;
+  const bool head = colok && (t == a - 1 || t == a + nbl - 1);
+  const int tc = top ? t : (bot ? t - a : 0);
+  const int sc = top ? s : (bot ? sb : M);
+  const int tb = bot ? 1 : 0;
+  const int row0 = top ? t * M - s : (bot ? N - 1 - (tc * M - sb) : -1);
+  const int dir = top ? 1 : (bot ? -1 : 0);
 
-  // ---- RHS R = w + beta_+ X w over the lane's rows (sliding window)
-  D Rv[MAXM];
+  // table byte offsets of the lane's slots (lane-major, padded by M zero rows)
+  const int LT = d.lt;
+  unsigned offb[M];
   {
-    D wm = (r0 >= 1 && r0 - 1 < N) ? to_d(my[-2]) : zero<double>();
-    D wc = (r0 < N) ? to_d(my[0]) : zero<double>();
-    const D dgb = mk<double>(qb.re - 2.0 * h, qb.im);
-    if (wave_top) {
+    const int lo = tb * M * LT + (M - sc) * LT + tc;  // slot j < sc
+    const int hi = tb * M * LT + tc + 1 - sc * LT;    // slot j >= sc
 #pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        if (i < M) {
-          const D wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
-          const D qv = qwT[i * L + t];
-          const D X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
-          Rv[i] = fma(bp, X, wc);
-          wm = wc;
-          wc = wp;
-        }
-      }
-    } else if (wave_bot) {
-      // a lane ending on a rigid floor: its last row has lower coefficient 2h
-      // and is scaled by 1/2 (the host scales the floor row of the bottom system)
-      const bool fl = rigid && (r0 + M == N);
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        if (i < M) {
-          const bool last = (i + 1 == M) && (r0 + M == N);
-          const D wp = last ? zero<double>() : to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
-          const D X = fma(dgb, wc, scl(h, add(wm, wp)));
-          D R = fma(bp, X, wc);
-          if (fl && i + 1 == M) R = scl(0.5, fma(bp, scl(h, wm), R));
-          Rv[i] = R;
-          wm = wc;
-          wc = wp;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        const int r = r0 + i;
-        D wp = zero<double>();
-        if (i < M && r + 1 < N) wp = to_d((i + 1 < M) ? my[i + 1] : my[M + 1]);
-        D X;
-        D R;
-        if (r < k) {
-          const D qv = (i < M && r < N) ? qwT[i * L + t] : zero<double>();
-          X = fma(mk<double>(qv.re - 2.0 * h, qv.im), wc, scl(h, add(wm, wp)));
-          R = fma(bp, X, wc);
-        } else if (r > k + 1) {
-          const bool flr = rigid && (r == N - 1);
-          X = fma(dgb, wc, add(scl(flr ? 2.0 * h : h, wm), scl(h, wp)));
-          R = fma(bp, X, wc);
-          if (flr) R = scl(0.5, R);
-        } else if (Bp == nullptr) {
-          R = zero<double>();
-        } else if (r == k) {
-          X = fma(Bp->xl0, wm, fma(Bp->xd0, wc, mul(Bp->xu0, wp)));
-          R = fma(bp, X, wc);
-        } else {
-          X = fma(Bp->xl1, wm, fma(Bp->xd1, wc, mul(Bp->xu1, wp)));
-          R = fma(bp, X, wc);
-        }
-        Rv[i] = (i < M && r < N) ? R : zero<double>();
-        wm = wc;
-        wc = wp;
-      }
-    }
+    for (int j = 0; j < M; ++j) offb[j] = unsigned((j < sc ? lo : hi) + j * LT) * 16u;
   }
+  const unsigned char* __restrict__ Gt = (const unsigned char*)d.tabG;
+  const unsigned char* __restrict__ Ct = (const unsigned char*)d.tabC;
+  auto G_at = [&](int j) { return *reinterpret_cast<const D*>(Gt + offb[j]); };
+  auto C_at = [&](int j) { return *reinterpret_cast<const D*>(Ct + offb[j]); };
 
-  // ---- elimination: top rows downward, y_r = R_r + (-beta_- h) pivot_{r-1} y_{r-1};
-  //      bottom rows upward, z_r = R_r + (-beta_- h) pivot_{r+1} z_{r+1}
-  D Ft = one<double>(), Et = zero<double>(), Gb = one<double>(), Sb = zero<double>();
-  if (wave_top) {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < M) {
-        Et = fma(nbmh, mul(piv[i], Et), Rv[i]);
-        Rv[i] = Et;
-      }
-    Ft = lt[0 * L + t];
-  } else if (wave_bot) {
-#pragma unroll
-    for (int i = MAXM - 1; i >= 0; --i)
-      if (i < M) {
-        Sb = fma(nbmh, mul(piv[i + 2], Sb), Rv[i]);
-        Rv[i] = Sb;
-      }
-    Gb = lt[1 * L + t];
-  } else {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      const int r = r0 + i;
-      if (i < M && r < N && r < k) {
-        const D f = mul(nbmh, piv[i]);
-        Et = fma(f, Et, Rv[i]);
-        Ft = mul(Ft, f);
-        Rv[i] = Et;
-      }
-    }
-#pragma unroll
-    for (int i = MAXM - 1; i >= 0; --i) {
-      const int r = r0 + i;
-      if (i < M && r < N && r > k + 1) {
-        const D g = mul(nbmh, piv[i + 2]);
-        Sb = fma(g, Sb, Rv[i]);
-        Gb = mul(Gb, g);
-        Rv[i] = Sb;
-      }
-    }
-  }
-  {
-    const ChainPair cc = scan_pair(Ft, Et, zero<double>(), Gb, Sb, zero<double>(), t, L, tot);
-    if (wave_top) {
-      D dl = cc.down;
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i)
-        if (i < M) {
-          dl = mul(nbmh, mul(piv[i], dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-    } else if (wave_bot) {
-      D dl = cc.up;
-#pragma unroll
-      for (int i = MAXM - 1; i >= 0; --i)
-        if (i < M) {
-          dl = mul(nbmh, mul(piv[i + 2], dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-    } else {
-      D dl = cc.down;
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        const int r = r0 + i;
-        if (i < M && r < N && r < k) {
-          dl = mul(nbmh, mul(piv[i], dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-      }
-      dl = cc.up;
-#pragma unroll
-      for (int i = MAXM - 1; i >= 0; --i) {
-        const int r = r0 + i;
-        if (i < M && r < N && r > k + 1) {
-          dl = mul(nbmh, mul(piv[i + 2], dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-      }
-    }
-  }
-
-  // ---- 2x2 interface block (rows k, k+1): the lanes holding rows k-1..k+2 publish them
-  if (colok && r0 <= k + 2 && r0 + M > k - 1) {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      const int r = r0 + i;
-      if (i < M && r < N) {
-        if (r == k - 1) slots[cw * 4 + 0] = Rv[i];
-        if (r == k) slots[cw * 4 + 1] = Rv[i];
-        if (r == k + 1) slots[cw * 4 + 2] = Rv[i];
-        if (r == k + 2) slots[cw * 4 + 3] = Rv[i];
-      }
-    }
+  const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
+  const D cb = mk<double>(d.bp_re * d.h, d.bp_im * d.h);
+  D tp = zero<double>();
+  if (top || bot) tp = ((const D*)d.tabP)[(tb * (M + 1) + sc) * L + tc];
+  D hc0 = zero<double>(), hcp = zero<double>(), hcn = zero<double>(), hcF = zero<double>();
+  D hia = zero<double>(), hib = zero<double>();
+  if (head) {
+    const D* hr = ((const D*)d.rec) + (size_t)m * 12 + (bot ? 6 : 0);
+    hc0 = hr[0];
+    hcp = hr[1];
+    hcn = hr[2];
+    hcF = hr[3];
+    hia = hr[4];
+    hib = hr[5];
   }
   __syncthreads();
-  D vk = zero<double>(), vk1 = zero<double>();
-  if (Bp) {
-    const D ykm1 = slots[cw * 4 + 0], Rk = slots[cw * 4 + 1];
-    const D Rk1 = slots[cw * 4 + 2], zk2 = slots[cw * 4 + 3];
-    const D rk = fma(Bp->fk, ykm1, Rk);
-    const D rk1 = fma(Bp->gk1, zk2, Rk1);
-    vk = fma(Bp->i00, rk, mul(Bp->i01, rk1));
-    vk1 = fma(Bp->i10, rk, mul(Bp->i11, rk1));
-  }
 
-  // ---- back substitution: top rows upward, v_r = pivot_r (y_r + (-beta_- h) v_{r+1});
-  //      bottom rows downward, v_r = pivot_r (z_r + (-beta_- h) v_{r-1})
-  D Ht = one<double>(), Eu = zero<double>(), Hb = one<double>(), Ed = zero<double>();
-  if (wave_top) {
-#pragma unroll
-    for (int i = MAXM - 1; i >= 0; --i)
-      if (i < M) {
-        Eu = mul(piv[i + 1], fma(nbmh, Eu, Rv[i]));
-        Rv[i] = Eu;
-      }
-    Ht = lt[2 * L + t];
-  } else if (wave_bot) {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < M) {
-        Ed = mul(piv[i + 1], fma(nbmh, Ed, Rv[i]));
-        Rv[i] = Ed;
-      }
-    Hb = lt[3 * L + t];
-  } else {
-#pragma unroll
-    for (int i = MAXM - 1; i >= 0; --i) {
-      const int r = r0 + i;
-      if (i < M && r < N) {
-        if (r < k) {
-          const D p = piv[i + 1];
-          Eu = mul(p, fma(nbmh, Eu, Rv[i]));
-          Ht = mul(Ht, mul(nbmh, p));
-          Rv[i] = Eu;
-        } else if (r == k) {
-          Rv[i] = vk;
-        } else if (r == k + 1) {
-          Rv[i] = vk1;
-        }
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      const int r = r0 + i;
-      if (i < M && r < N && r > k + 1) {
-        const D p = piv[i + 1];
-        Ed = mul(p, fma(nbmh, Ed, Rv[i]));
-        Hb = mul(Hb, mul(nbmh, p));
-        Rv[i] = Ed;
-      }
-    }
-  }
+  // ---- phase 1: R = [I + beta_+ X] w along the chain (sliding window), local
+  //      elimination with zero carry -> the lane's map yh_out = tp yh_in + E
+  const C<S>* col = buf + cw * CS + GA;
+  D Rv[M];
+  D E = zero<double>();
   {
-    // the top chain runs upward and enters from below with v_k; the bottom
-    // chain runs downward and enters from above with v_{k+1}
-    const ChainPair cc = scan_pair(Hb, Ed, vk1, Ht, Eu, vk, t, L, tot);
-    if (wave_top) {
-      D dl = cc.up;
+    const C<S>* p = col + row0;
+    D wp = to_d(p[-dir]);
+    D wc = to_d(p[0]);
 #pragma unroll
-      for (int i = MAXM - 1; i >= 0; --i)
-        if (i < M) {
-          dl = mul(piv[i + 1], mul(nbmh, dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-    } else if (wave_bot) {
-      D dl = cc.down;
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i)
-        if (i < M) {
-          dl = mul(piv[i + 1], mul(nbmh, dl));
-          Rv[i] = add(Rv[i], dl);
-        }
-    } else {
-      D dl = cc.up;
-#pragma unroll
-      for (int i = MAXM - 1; i >= 0; --i) {
-        const int r = r0 + i;
-        if (i < M && r < N && r < k) {
-          dl = mul(piv[i + 1], mul(nbmh, dl));
-          Rv[i] = add(Rv[i], dl);
-        }
+    for (int j = 0; j < M; ++j) {
+      const D wn = to_d(p[dir * (j + 1)]);
+      const D g = G_at(j);
+      const D cdv = C_at(j);
+      D R;
+      if (j == M - 1) {
+        const D c0 = head ? hc0 : cdv;
+        const D cp = head ? hcp : cb;
+        const D cn = head ? hcn : cb;
+        R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
+        const D y = fma(head ? hcF : nbmh, E, R);
+        E = head ? y : mul(g, y);
+      } else {
+        R = fma(cdv, wc, mul(cb, add(wp, wn)));
+        E = mul(g, fma(nbmh, E, R));
       }
-      dl = cc.down;
+      Rv[j] = R;
+      wp = wc;
+      wc = wn;
+    }
+  }
+  const D cin = scan_excl<true>(tp, E, t, L, tot);
+
+  // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
+  //      reduced interface right-hand side r_k or r_{k+1})
+  {
+    D yh = cin;
 #pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        const int r = r0 + i;
-        if (i < M && r < N && r > k + 1) {
-          dl = mul(piv[i + 1], mul(nbmh, dl));
-          Rv[i] = add(Rv[i], dl);
-        }
+    for (int j = 0; j < M; ++j) {
+      const D g = G_at(j);
+      if (j == M - 1) {
+        const D y = fma(head ? hcF : nbmh, yh, Rv[j]);
+        Rv[j] = head ? y : mul(g, y);
+      } else {
+        yh = mul(g, fma(nbmh, yh, Rv[j]));
+        Rv[j] = yh;
       }
     }
   }
-
-  // ---- write back through LDS, coalesced store
+  // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
+  if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
   __syncthreads();
-  C<S>* myw = lds + cw * stride + t * (M + 1);
+  if (head) Rv[M - 1] = fma(hia, Rv[M - 1], mul(hib, xch[2 * cw + (bot ? 0 : 1)]));
+
+  // ---- phase 3: local back substitution with zero carry -> x_out = tpb x_in + X
+  D X = zero<double>();
 #pragma unroll
-  for (int i = 0; i < MAXM; ++i) {
-    if (i < M && r0 + i < N) myw[i] = from_d<S>(Rv[i]);
+  for (int j = M - 1; j >= 0; --j) {
+    const D g = G_at(j);
+    if (j == M - 1 && head) X = Rv[j];
+    else X = fma(nbmh, mul(g, X), Rv[j]);
+  }
+  const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
+
+  // ---- phase 4: back substitution with the exact carry, written to the column
+  //      buffer (the input was last read before the interface barrier; zero
+  //      slots and idle lanes write guard rows only)
+  {
+    C<S>* p = buf + cw * CS + GA + row0;
+    D x = xin;
+#pragma unroll
+    for (int j = M - 1; j >= 0; --j) {
+      const D g = G_at(j);
+      if (j == M - 1 && head) x = Rv[j];
+      else x = fma(nbmh, mul(g, x), Rv[j]);
+      p[dir * j] = from_d<S>(x);
+    }
   }
   __syncthreads();
   for (int c = 0; c < ncols; ++c) {
-    C<S>* col = dst + (size_t)(m0 + c) * N;
-    for (int r = lane; r < N; r += kPassAThreads) {
-      int q = int((float(r) + 0.5f) * invM);
-      col[r] = lds[c * stride + r + q];
-    }
+    C<S>* out = dst + (size_t)(m0 + c) * N;
+    const C<S>* b = buf + c * CS + GA;
+    for (int r = lane; r < N; r += kPassAThreads) out[r] = b[r];
   }
 }
 
-template <typename S, int MAXM>
-constexpr int pass_a_lds() {
-  return int(sizeof(C<S>) * kPassAThreads * (MAXM + 1) + sizeof(D) * (4 * 64 + 16));
-}
+#define PE3D_PASS_A_ATTR __launch_bounds__(kPassAThreads)
 
-// two workgroups per CU: staging and compute of one overlap the other's memory traffic
-#define PE3D_PASS_A_ATTR __launch_bounds__(kPassAThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
-
-template <typename S, int MAXM>
+template <typename S, int M>
 __global__ PE3D_PASS_A_ATTR void pass_a_single(ProbDesc d, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
-  pass_a_body<S, MAXM>(d, blockIdx.x, koff, (C<S>*)smem_a);
+  pass_a_body<S, M>(d, blockIdx.x, koff, smem_a);
 }
 
-template <typename S, int MAXM>
+template <typename S, int M>
 __global__ PE3D_PASS_A_ATTR void pass_a_batch(const ProbDesc* __restrict__ descs,
-                                                              const WorkItem* __restrict__ items,
-                                                              int koff) {
+                                              const WorkItem* __restrict__ items, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_a_body<S, MAXM>(d, it.tile, koff, (C<S>*)smem_a);
+  pass_a_body<S, M>(d, it.tile, koff, smem_a);
 }
 
 // ============================================================== pass B
@@ -884,24 +713,27 @@ __global__ void tl_kernel(ProbDesc d, const C<R>* u, float* tl) {
 }
 
 // ============================================================== launchers
-template <typename S, int MAXM>
+template <typename S, int M>
 static hipError_t run_a(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
-                        int nitems, int koff, hipStream_t st) {
-  constexpr int lds = pass_a_lds<S, MAXM>();
+                        int nitems, int koff, int lds, hipStream_t st) {
+  // largest LDS any shape with this M can ask for: L = 4 lanes and nz = 3M - 1
+  // (the host keeps nz <= (L-1) M - 1)
+  constexpr int lds_max = pass_a_lds_bytes(int(sizeof(C<S>)), 4, 3 * M - 1, M);
+  if (lds > lds_max) return hipErrorInvalidValue;
   static bool attr = false;  // allow more than the default dynamic LDS once per kernel
   if (!attr) {
-    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, MAXM>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S, MAXM>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, M>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S, M>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
     if (e1 != hipSuccess || e2 != hipSuccess) return e1 != hipSuccess ? e1 : e2;
     attr = true;
   }
   if (single) {
-    hipLaunchKernelGGL((pass_a_single<S, MAXM>), dim3(single->ntile_a), dim3(kPassAThreads), lds, st,
+    hipLaunchKernelGGL((pass_a_single<S, M>), dim3(single->ntile_a), dim3(kPassAThreads), lds, st,
                        *single, koff);
   } else {
-    hipLaunchKernelGGL((pass_a_batch<S, MAXM>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs,
+    hipLaunchKernelGGL((pass_a_batch<S, M>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs,
                        items, koff);
   }
   return hipGetLastError();
@@ -920,13 +752,30 @@ static hipError_t run_b(const ProbDesc* single, const ProbDesc* d_descs, const W
   return hipGetLastError();
 }
 
-hipError_t launch_pass_a(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, hipStream_t st) {
-  if (maxm == 16) {
-    if (prec == 0) return run_a<float, 16>(single, d_descs, items, nitems, koff, st);
-    return run_a<double, 16>(single, d_descs, items, nitems, koff, st);
+int pass_a_lds(int prec, int L, int nz, int M) {
+  return pass_a_lds_bytes(prec ? 16 : 8, L, nz, M);
+}
+
+template <typename S>
+static hipError_t run_a_m(int M, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                          int nitems, int koff, int lds, hipStream_t st) {
+  switch (M) {
+    case 3: return run_a<S, 3>(single, d_descs, items, nitems, koff, lds, st);
+    case 5: return run_a<S, 5>(single, d_descs, items, nitems, koff, lds, st);
+    case 7: return run_a<S, 7>(single, d_descs, items, nitems, koff, lds, st);
+    case 9: return run_a<S, 9>(single, d_descs, items, nitems, koff, lds, st);
+    case 11: return run_a<S, 11>(single, d_descs, items, nitems, koff, lds, st);
+    case 13: return run_a<S, 13>(single, d_descs, items, nitems, koff, lds, st);
+    case 15: return run_a<S, 15>(single, d_descs, items, nitems, koff, lds, st);
+    case 17: return run_a<S, 17>(single, d_descs, items, nitems, koff, lds, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc* d_descs,
+                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
+  if (prec == 0) return run_a_m<float>(M, single, d_descs, items, nitems, koff, lds, st);
+  return run_a_m<double>(M, single, d_descs, items, nitems, koff, lds, st);
 }
 
 hipError_t launch_pass_b(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
