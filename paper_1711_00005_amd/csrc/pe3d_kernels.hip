@@ -247,43 +247,68 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
   C<S>* __restrict__ dst = (C<S>*)d.scr;
 
-  // ---- zero the guard rows of every column buffer, stage the columns (coalesced);
-  //      on the first step apply [I + s_0 D_theta] from the neighbouring columns
+  // ---- zero the guard rows of every column buffer, stage the columns.  The
+  //      workgroup's columns are one contiguous span of ncols*N values;
+  //      thread `lane` takes entries lane + 256 q, q < M (ncols*N < 256 M),
+  //      all loads issued before the first LDS write.  On the first step
+  //      apply [I + s_0 D_theta] from the neighbouring columns.
   for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
     const int c = i / (2 * GA);
     const int g = i - c * 2 * GA;
     buf[c * CS + (g < GA ? g : N + g)] = zero<S>();
   }
+  const int span = ncols * N;
+  const float invN = 1.0f / float(N);
+  const C<S>* __restrict__ base = src + (size_t)m0 * N;
   if (!first) {
-    for (int c = 0; c < ncols; ++c) {
-      const C<S>* col = src + (size_t)(m0 + c) * N;
-      C<S>* b = buf + c * CS + GA;
-      for (int r = lane; r < N; r += kPassAThreads) b[r] = col[r];
+    C<S> v[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + q * kPassAThreads;
+      if (e < span) v[q] = base[e];
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + q * kPassAThreads;
+      if (e < span) {
+        const int c = int((float(e) + 0.5f) * invN);
+        buf[c * CS + GA + (e - c * N)] = v[q];
+      }
     }
   } else {
     const long long j = *d.jdev + koff;
     const double s0 = sigma_of(d, j);  // s_0 = i * s0
-    for (int c = 0; c < ncols; ++c) {
-      const int mm = m0 + c;
-      int ml = mm - 1, mr = mm + 1;
-      bool hl = true, hr = true;
-      if (d.periodic) {
-        if (ml < 0) ml = NT - 1;
-        if (mr >= NT) mr = 0;
-      } else {
-        hl = ml >= 0;
-        hr = mr < NT;
+    C<S> vc[M], vl[M], vr[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + q * kPassAThreads;
+      if (e < span) {
+        const int c = int((float(e) + 0.5f) * invN);
+        const int r = e - c * N;
+        const int mm = m0 + c;
+        int ml = mm - 1, mr = mm + 1;
+        if (d.periodic) {
+          if (ml < 0) ml = NT - 1;
+          if (mr >= NT) mr = 0;
+        }
+        // sector edges: load an in-range column, zero it below
+        vc[q] = base[e];
+        vl[q] = src[(size_t)max(ml, 0) * N + r];
+        vr[q] = src[(size_t)min(mr, NT - 1) * N + r];
       }
-      const C<S>* col = src + (size_t)mm * N;
-      const C<S>* coll = src + (size_t)(hl ? ml : mm) * N;
-      const C<S>* colr = src + (size_t)(hr ? mr : mm) * N;
-      C<S>* b = buf + c * CS + GA;
-      for (int r = lane; r < N; r += kPassAThreads) {
-        const D uc = to_d(col[r]);
-        const D ul = hl ? to_d(coll[r]) : zero<double>();
-        const D ur = hr ? to_d(colr[r]) : zero<double>();
+    }
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + q * kPassAThreads;
+      if (e < span) {
+        const int c = int((float(e) + 0.5f) * invN);
+        const int mm = m0 + c;
+        const bool hl = d.periodic || mm > 0, hr = d.periodic || mm < NT - 1;
+        const D uc = to_d(vc[q]);
+        const D ul = hl ? to_d(vl[q]) : zero<double>();
+        const D ur = hr ? to_d(vr[q]) : zero<double>();
         const D dd = sub(add(ul, ur), scl(2.0, uc));
-        b[r] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));  // u + i s0 dd
+        buf[c * CS + GA + (e - c * N)] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));
       }
     }
   }
@@ -413,10 +438,16 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     }
   }
   __syncthreads();
-  for (int c = 0; c < ncols; ++c) {
-    C<S>* out = dst + (size_t)(m0 + c) * N;
-    const C<S>* b = buf + c * CS + GA;
-    for (int r = lane; r < N; r += kPassAThreads) out[r] = b[r];
+  {
+    C<S>* __restrict__ out = dst + (size_t)m0 * N;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + q * kPassAThreads;
+      if (e < span) {
+        const int c = int((float(e) + 0.5f) * invN);
+        out[e] = buf[c * CS + GA + (e - c * N)];
+      }
+    }
   }
 }
 
