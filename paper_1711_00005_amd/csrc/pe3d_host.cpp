@@ -122,7 +122,7 @@ struct Built {
   std::vector<int> k;
   std::vector<std::array<cd, 12>> rec;  // interface rows of each column
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
-  int nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
+  int wb = 0, nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
 };
 
 
@@ -148,14 +148,19 @@ pe3d_status choose_shapes(Built& b) {
   const int cpw = 256 / L;
   b.ntile_a = (NT + cpw - 1) / cpw;
 
-  // about 16 azimuth nodes per chunk, at most 64 chunks (8 depths per workgroup)
-  const int nc = std::min(64, next_pow2((NT + 15) / 16));
-  const int mb = (NT + nc - 1) / nc;
-  if (mb > 16) return PE3D_EUNSUPPORTED;
-  b.td = kPassBThreads / nc;
-  b.nc = (NT + mb - 1) / mb;  // every chunk non-empty
+  // pass B: the fewest lanes W per depth line (power of two, 1..64) with chunks
+  // of M = ceil(nth / W) <= 16 azimuths; lines of exactly W*M azimuths with
+  // M >= 9 use the kernel specialised for M (class M), others the general
+  // kernel (class 0)
+  int W = 1;
+  while ((NT + W - 1) / W > 16) W *= 2;
+  if (W > 64) return PE3D_EUNSUPPORTED;
+  const int mb = (NT + W - 1) / W;
+  b.wb = W;
   b.mb = mb;
-  b.maxm_b = mb <= 8 ? 8 : 16;
+  b.nc = (NT + mb - 1) / mb;
+  b.td = kPassBThreads / W;
+  b.maxm_b = (NT == W * mb && mb >= 9) ? mb : 0;
   b.ntile_b = (N + b.td - 1) / b.td;
   return PE3D_OK;
 }
@@ -370,7 +375,7 @@ void pack(const std::vector<cd>& v, std::vector<unsigned char>& out, size_t off)
 struct pe3d_handle_s {
   int prec = 0;
   int maxm_a = 0, maxm_b = 0;
-  int lds_a = 0;  // dynamic LDS of a pass A workgroup
+  int lds_a = 0, lds_b = 0;  // dynamic LDS of a pass A / pass B workgroup
   ProbDesc desc{};
   void* d_tables = nullptr;
   void* d_scr = nullptr;
@@ -589,6 +594,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   h->maxm_a = b.ma;
   h->maxm_b = b.maxm_b;
   h->lds_a = pass_a_lds(b.prec, b.lpc, b.N, b.ma);
+  h->lds_b = pass_b_lds(b.prec, b.wb, b.mb);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return PE3D_EDEVICE;
@@ -639,6 +645,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.bp_im = b.bp.imag();
   d.bm_re = b.bm.real();
   d.bm_im = b.bm.imag();
+  d.wb = b.wb;
   d.nc = b.nc;
   d.td = b.td;
   d.mb = b.mb;
@@ -713,7 +720,7 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
         }) != hipSuccess)
       return PE3D_EDEVICE;
     if (prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
-          return launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, st);
+          return launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, h->lds_b, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
   }
@@ -759,7 +766,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::map<int, std::vector<WorkItem>> ia, ib;
   std::map<int, std::vector<int>> ia_steps, ib_steps;  // steps of the problem of each item
   std::map<int, std::vector<double>> ia_bytes, ib_bytes;
-  std::map<int, int> ia_lds;
+  std::map<int, int> ia_lds, ib_lds;
   for (int p = 0; p < np; ++p) {
     pe3d_handle h = hs[order[p]];
     descs[p] = h->desc;
@@ -777,6 +784,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
       const int ncol = std::min(cpw, hd.nth - t * cpw);
       ia_bytes[h->maxm_a].push_back(2.0 * esz * ncol * hd.nz);
     }
+    ib_lds[h->maxm_b] = std::max(ib_lds[h->maxm_b], h->lds_b);
     for (int t = 0; t < hd.ntile_b; ++t) {
       ib[h->maxm_b].push_back({p, t});
       ib_steps[h->maxm_b].push_back(nsteps[order[p]]);
@@ -826,6 +834,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   emit(ia, ia_steps, ia_bytes, P.a);
   for (auto& c : P.a) c.lds = ia_lds[c.maxm];
   emit(ib, ib_steps, ib_bytes, P.b);
+  for (auto& c : P.b) c.lds = ib_lds[c.maxm];
   if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
 }
@@ -842,7 +851,7 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
     for (auto& c : P.b) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, st);
+            return launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
           }) != hipSuccess)
         return PE3D_EDEVICE;
     }

@@ -41,10 +41,11 @@ struct ProbDesc {
   double qb_re, qb_im;  // n^2-1 of the bottom half-space
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
-  // azimuth pass (pass B)
-  int nc;               // chunks per depth line
-  int td;               // depths per workgroup (nc * td == kPassBThreads)
-  int mb;               // azimuth nodes per chunk (nc * mb >= nth, all chunks non-empty)
+  // azimuth pass (pass B): W lanes per depth line, NC <= W chunks of M azimuths
+  int wb;               // W, lanes per depth line (power of two, 1..64)
+  int nc;               // NC = ceil(nth / M)
+  int td;               // depths per workgroup = kPassBThreads / W
+  int mb;               // M, azimuth nodes per chunk (<= 16)
   int ntile_b;          // ceil(nz / td)
   double k0, dr, r0, dth;
   double dz;            // starter / TL only
@@ -63,8 +64,9 @@ constexpr int kPassBThreads = 512;
 hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc* d_descs,
                          const WorkItem* items, int nitems, int koff, int lds, hipStream_t st);
 int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pass A workgroup
-hipError_t launch_pass_b(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, hipStream_t st);
+hipError_t launch_pass_b(int prec, int cls, const ProbDesc* single, const ProbDesc* d_descs,
+                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st);
+int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n,
                           long long* jsingle, int add, hipStream_t st);
 hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipStream_t st);

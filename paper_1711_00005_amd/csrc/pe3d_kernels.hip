@@ -89,6 +89,35 @@ __device__ __forceinline__ C<double> to_d(C<R> z) { return mk<double>(double(z.r
 using D = C<double>;
 
 // ---------------------------------------------------------------- FP64 helpers
+// Field loads and stores through a pointer in the global address space:
+// a uniform (scalar) base plus a 32-bit per-lane element offset.
+template <typename S>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename S>
+__device__ __forceinline__ C<S> gload(const C<S>* base, unsigned off) {
+  using V = typename Vec2<S>::type;
+  const __attribute__((address_space(1))) V* p = (const __attribute__((address_space(1))) V*)base;
+  const V v = p[off];
+  return mk<S>(v.x, v.y);
+}
+template <typename S>
+__device__ __forceinline__ void gstore(C<S>* base, unsigned off, C<S> val) {
+  using V = typename Vec2<S>::type;
+  __attribute__((address_space(1))) V* p = (__attribute__((address_space(1))) V*)base;
+  V v;
+  v.x = val.re;
+  v.y = val.im;
+  p[off] = v;
+}
+
 __device__ __forceinline__ C<double> cdiv(C<double> a, C<double> b) {
   // Smith's algorithm
   if (fabs(b.re) >= fabs(b.im)) {
@@ -439,10 +468,13 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   }
   __syncthreads();
   {
+    // the staging addresses are recomputed here rather than kept live
+    int lane_r = lane;
+    asm volatile("" : "+v"(lane_r));
     C<S>* __restrict__ out = dst + (size_t)m0 * N;
 #pragma unroll
     for (int q = 0; q < M; ++q) {
-      const int e = lane + q * kPassAThreads;
+      const int e = lane_r + q * kPassAThreads;
       if (e < span) {
         const int c = int((float(e) + 0.5f) * invN);
         out[e] = buf[c * CS + GA + (e - c * N)];
@@ -469,242 +501,284 @@ __global__ PE3D_PASS_A_ATTR void pass_a_batch(const ProbDesc* __restrict__ descs
 }
 
 // ============================================================== pass B
-// Per-workgroup FP64 constants of the azimuth solve for one range step.
+// A workgroup of 512 lanes owns TD = 512/W consecutive depths of one problem.
+// Every depth line of NT azimuths is cut into NC <= W chunks of M nodes (the
+// last one may be shorter); lane = depth * W + chunk, so the chunks of one
+// line are W consecutive lanes of one wavefront and every chunk scan is a
+// wavefront shuffle scan.  The tile is staged through LDS (global loads and
+// stores coalesced along depth); in LDS a chunk of one depth is contiguous,
+// at c * CST + dl * DS with odd strides DS >= M and CST = TD DS + 1, so the
+// lanes of a line read distinct banks and slot offsets are immediates.
 struct BConst {
-  D rho;     // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle
-  D rM;      // rho^M
-  D rL;      // rho^lastlen
-  D winv;    // 1 / (1 - rho^N)   (periodic closure)
-  D sinv;    // 1 / (1 - rho^(2N+2))  (sector first-row correction)
-  D lev[6];  // rho^(M 2^l), multipliers of the chunk scan
-  double s1; // sigma of the next step (its azimuth factor is applied on store)
+  D rho;      // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle
+  D rinv;     // 1 / rho (sector)
+  D rL;       // rho^lastlen
+  D winv;     // 1 / (1 - rho^NT)      (periodic closure)
+  D sinv;     // 1 / (1 - rho^(2NT+2)) (sector first-row correction)
+  D rM;       // rho^M, chunk multiplier of the scans
+  double s1;  // sigma of the next step (its azimuth factor is applied on store)
 };
 
-template <typename S, int MAXM>
-__device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int koff) {
-  constexpr int NTHR = kPassBThreads;
-  // sE1/sC1: forward chunk ends and carries, reused for the edge exchange;
-  // sE2/sC2: backward chunk starts and carries, sE2 reused for the sector term
-  __shared__ D sE1[NTHR], sC1[NTHR], sE2[NTHR], sC2[NTHR];
-  __shared__ D sPow[MAXM + 2];   // rho^i
-  __shared__ D sPowC[64];        // rho^(M c), chunk c
-  __shared__ D sPowS[64];        // rho^(2N - m0 - len + 1), chunk c (sector)
-  __shared__ BConst K;
+constexpr int kPassBPow = 64;  // sPowC / sPowS entries: chunks <= 64
 
+__host__ __device__ constexpr int pass_b_ds(int M) { return M | 1; }
+__host__ __device__ constexpr int pass_b_tile_elems(int W, int M) {
+  return W * ((kPassBThreads / W) * pass_b_ds(M) + 1);
+}
+__host__ __device__ constexpr int pass_b_lds_bytes(int esz, int W, int M) {
+  return ((pass_b_tile_elems(W, M) * esz + 15) & ~15) + int(sizeof(BConst)) + 2 * kPassBPow * 16;
+}
+
+// EQ: every chunk holds exactly M nodes (NT = W*M, M = MM); otherwise M =
+// d.mb <= MM at run time and the last chunk holds NT - (NC-1) M nodes.
+template <typename S, int MM, bool EQ>
+__device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
+  constexpr int NTHR = kPassBThreads;
   const int tid = threadIdx.x;
-  const int TD = d.td, NC = d.nc, M = d.mb;
-  const int c = tid / TD;
-  const int dl = tid - c * TD;
+  const int W = d.wb;
+  const int lgW = 31 - __clz(W);
+  const int TD = NTHR >> lgW;
+  const int lgTD = 9 - lgW;
+  const int M = EQ ? MM : d.mb;
+  const int DS = EQ ? pass_b_ds(MM) : pass_b_ds(M);
   const int N = d.nz, NT = d.nth;
-  const int z = tile * TD + dl;
-  const bool zok = z < N;
-  const int m0 = c * M;
-  const int len = (c < NC) ? min(M, NT - m0) : 0;
-  const bool act = zok && len > 0;
+  const int NC = EQ ? W : d.nc;
+  const int CST = TD * DS + 1;
+  const int z0 = tile * TD;
+  C<S>* tl = reinterpret_cast<C<S>*>(smem);
+  BConst* K = reinterpret_cast<BConst*>(smem + ((W * CST * int(sizeof(C<S>)) + 15) & ~15));
+  D* sPowC = reinterpret_cast<D*>(K + 1);  // rho^(M c)
+  D* sPowS = sPowC + kPassBPow;            // rho^(2 NT - M c) (sector)
   const long long j = *d.jdev + koff;
   const bool last = (koff == d.nsteps - 1);
   const bool periodic = d.periodic != 0;
-  const int lastlen = NT - (NC - 1) * M;
-
   const C<S>* __restrict__ src = (const C<S>*)d.scr;
   C<S>* __restrict__ dst = (C<S>*)(last ? d.u : d.scr);
+  const float invM = 1.0f / float(M);
+  auto lidx = [&](int m, int dl) {  // LDS index of azimuth m, depth dl
+    const int c = EQ ? m / MM : int((float(m) + 0.5f) * invM);
+    return c * CST + dl * DS + (m - c * M);
+  };
 
-  // ---- load the chunk and its two azimuth neighbours (issued before the prologue)
-  C<S> v[MAXM];
-  C<S> vl = zero<S>(), vr = zero<S>();
-  if (act) {
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) v[i] = src[(size_t)(m0 + i) * N + z];
-    int ml = m0 - 1, mr = m0 + len;
-    if (periodic) {
-      if (ml < 0) ml = NT - 1;
-      if (mr >= NT) mr = 0;
-      vl = src[(size_t)ml * N + z];
-      vr = src[(size_t)mr * N + z];
-    } else {
-      if (ml >= 0) vl = src[(size_t)ml * N + z];
-      if (mr < NT) vr = src[(size_t)mr * N + z];
+  // ---- step constants (wavefront 0; read by all after the staging barrier)
+  if (tid < 64) {
+    const D rho = rho_of(sigma_of(d, j));
+    const int lastlen = NT - (NC - 1) * M;
+    const D rM = cpow(rho, M);
+    sPowC[tid] = cpow(rM, tid);
+    if (!periodic) sPowS[tid] = cpow(rho, 2 * (long long)NT - (long long)M * tid);
+    if (tid == 0) {
+      K->rho = rho;
+      K->rinv = cdiv(one<double>(), rho);
+      K->rL = cpow(rho, lastlen);
+      const D rN = cpow(rho, NT);
+      K->winv = cdiv(one<double>(), mk<double>(1.0 - rN.re, -rN.im));
+      const D r2 = cpow(rho, 2 * (long long)NT + 2);
+      K->sinv = cdiv(one<double>(), mk<double>(1.0 - r2.re, -r2.im));
+      K->rM = rM;
+      K->s1 = sigma_of(d, j + 1);
     }
   }
-
-  // ---- FP64 step constants, once per workgroup
-  if (tid == 0) {
-    const D rho = rho_of(sigma_of(d, j));
-    K.rho = rho;
-    K.rM = cpow(rho, M);
-    K.rL = cpow(rho, lastlen);
-    const D rN = cpow(rho, NT);
-    K.winv = cdiv(one<double>(), mk<double>(1.0 - rN.re, -rN.im));
-    const D r2 = cpow(rho, 2 * (long long)NT + 2);
-    K.sinv = cdiv(one<double>(), mk<double>(1.0 - r2.re, -r2.im));
-    D lv = K.rM;
-    for (int l = 0; l < 6; ++l) {
-      K.lev[l] = lv;
-      lv = mul(lv, lv);
+  // ---- stage the tile: thread tid loads depth z0 + tid % TD of azimuths
+  //      tid / TD + q W, q < M (NT <= W M); all loads issued before the
+  //      first LDS write
+  const int sdl = tid & (TD - 1);
+  const int sm0 = tid >> lgTD;
+  const int szc = min(z0 + sdl, N - 1);
+  const bool szok = z0 + sdl < N;
+  {
+    const unsigned o0 = unsigned(sm0 * N + szc), dq = unsigned(W * N);
+    C<S> v[MM];
+#pragma unroll
+    for (int q = 0; q < MM; ++q) {
+      const int m = sm0 + q * W;
+      if ((EQ || q < M) && (EQ || m < NT)) v[q] = gload(src, o0 + unsigned(q) * dq);
     }
-    K.s1 = sigma_of(d, j + 1);
+#pragma unroll
+    for (int q = 0; q < MM; ++q) {
+      const int m = sm0 + q * W;
+      if ((EQ || q < M) && (EQ || m < NT)) tl[lidx(m, sdl)] = szok ? v[q] : zero<S>();
+    }
   }
   __syncthreads();
-  const D rho = K.rho;
-  if (tid <= MAXM + 1) sPow[tid] = cpow(rho, tid);
-  if (tid >= 64 && tid < 128 && tid - 64 < NC) sPowC[tid - 64] = cpow(K.rM, tid - 64);
-  if (!periodic && tid >= 128 && tid < 192 && tid - 128 < NC) {
-    const int cc = tid - 128;
-    const int ln = min(M, NT - cc * M);
-    sPowS[cc] = cpow(rho, 2 * (long long)NT - cc * M - ln + 1);
-  }
 
-  // ---- D_theta v, forward recurrence y_m = t_m + rho y_{m-1} with zero carry
-  D x[MAXM];
+  // ---- lane role
+  const int c = tid & (W - 1);
+  const int dl = tid >> lgW;
+  const int seg = tid & ~(W - 1) & 63;  // first lane of this line within the wavefront
+  const int len = EQ ? MM : (c < NC - 1 ? M : (c == NC - 1 ? NT - (NC - 1) * M : 0));
+  const D rho = K->rho;
+  C<S>* T = tl + c * CST + dl * DS;
+  auto vat = [&](int i) { return to_d(T[i]); };
+
+  // ---- t = D_theta v, forward recurrence y_m = t_m + rho y_{m-1}: end value
+  //      with zero carry
+  D xr[MM];
   D E = zero<double>();
   {
-    D a = to_d(vl), b = (len > 0) ? to_d(v[0]) : zero<double>();
+    D a;  // v_{m0-1}
+    if (c > 0) a = to_d(T[M - 1 - CST]);
+    else if (periodic) a = to_d(tl[lidx(NT - 1, dl)]);
+    else a = zero<double>();
+    D nxe;  // v_{m0+len}
+    if (c < NC - 1) nxe = to_d(T[CST]);
+    else nxe = periodic ? to_d(tl[dl * DS]) : zero<double>();
+    D b = vat(0);
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-      if (i < len) {
-        const D cdn = (i + 1 < len) ? to_d(v[i + 1]) : to_d(vr);
-        const D tt = sub(add(a, cdn), scl(2.0, b));
+    for (int i = 0; i < MM; ++i) {
+      if (EQ || i < len) {
+        const D nx = (EQ ? (i + 1 < MM) : (i + 1 < len)) ? vat(i + 1 < MM ? i + 1 : i) : nxe;
+        const D tt = sub(add(a, nx), scl(2.0, b));
         E = fma(rho, E, tt);
-        x[i] = E;
+        xr[i] = tt;
         a = b;
-        b = cdn;
+        b = nx;
+        __builtin_amdgcn_sched_barrier(0);  // keep each LDS read next to its use
       }
     }
   }
-  sE1[tid] = E;
-  __syncthreads();
-  // ---- carries across chunks (FP64 segmented scan over the chunks of a depth)
-  const int NCp = ncp_of(NC);
-  if (tid < TD * NCp) {
-    const int sd = tid / NCp, sc = tid - sd * NCp;
-    const D e = (sc < NC) ? sE1[sc * TD + sd] : zero<double>();
-    // inclusive scan over chunks 0..NC-2 (length M each)
-    D Sv = (sc < NC - 1) ? e : zero<double>();
-    for (int l = 0, dd = 1; dd < NCp; ++l, dd <<= 1) {
-      const D up = shfl_up(Sv, dd, NCp);
-      if (sc >= dd) Sv = fma(K.lev[l], up, Sv);
-    }
-    const D Slast = (NC >= 2) ? shfl_idx(Sv, NC - 2, NCp) : zero<double>();
-    const D Elast = shfl_idx(e, NC - 1, NCp);
-    const D c0 = periodic ? mul(fma(K.rL, Slast, Elast), K.winv) : zero<double>();
-    D prev = shfl_up(Sv, 1, NCp);
-    if (sc == 0) prev = zero<double>();
-    if (sc < NC) sC1[sc * TD + sd] = fma(sPowC[sc], c0, prev);
-  }
-  __syncthreads();
+  // ---- forward chunk carries: inclusive scan over chunks 0..NC-2 (length M)
   {
-    const D cin = sC1[tid];
+    D Sv = (c < NC - 1) ? E : zero<double>();
+    D lv = K->rM;  // rho^(M dd)
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) x[i] = fma(sPow[i + 1], cin, x[i]);
-  }
-  // ---- backward recurrence x_m = y_m + rho x_{m+1} with zero carry
-  D Sb = zero<double>();
+    for (int l = 0; l < 6; ++l) {
+      const int dd = 1 << l;
+      if (dd < W) {
+        const D up = shfl_up(Sv, dd, W);
+        if (c >= dd) Sv = fma(lv, up, Sv);
+        lv = mul(lv, lv);
+      }
+    }
+    D y0 = zero<double>();  // y_{-1} = y_{NT-1} (periodic)
+    if (periodic) {
+      const D Sl = (NC >= 2) ? shfl_idx(Sv, seg + NC - 2, 64) : zero<double>();
+      const D El = shfl_idx(E, seg + NC - 1, 64);
+      y0 = mul(fma(K->rL, Sl, El), K->winv);
+    }
+    D prev = shfl_up(Sv, 1, W);
+    if (c == 0) prev = zero<double>();
+    D y = fma(sPowC[c < kPassBPow ? c : 0], y0, prev);
 #pragma unroll
-  for (int i = MAXM - 1; i >= 0; --i) {
-    if (i < len) {
-      Sb = fma(rho, Sb, x[i]);
-      x[i] = Sb;
-    }
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < len) {
+        y = fma(rho, y, xr[i]);
+        xr[i] = y;
+      }
   }
-  sE2[tid] = Sb;
-  __syncthreads();
-  // backward chain scanned in reversed chunk order (chunk NC-1 first): the
-  // chunk of length lastlen comes first, so only the wrap value sees rho^lastlen
-  if (tid < TD * NCp) {
-    const int sd = tid / NCp, sr = tid - sd * NCp;
-    const D e = (sr < NC) ? sE2[(NC - 1 - sr) * TD + sd] : zero<double>();
-    D Sv = e;
-    for (int l = 0, dd = 1; dd < NCp; ++l, dd <<= 1) {
-      const D up = shfl_up(Sv, dd, NCp);
-      if (sr >= dd) Sv = fma(K.lev[l], up, Sv);
-    }
-    const D c0 = periodic ? mul(shfl_idx(Sv, NC - 1, NCp), K.winv) : zero<double>();
-    D prev = shfl_up(Sv, 1, NCp);
-    const D cin = (sr == 0) ? c0 : fma(mul(K.rL, sPowC[sr > 0 ? sr - 1 : 0]), c0, prev);
-    if (sr < NC) sC2[(NC - 1 - sr) * TD + sd] = cin;
-  }
-  __syncthreads();
+  // ---- backward recurrence x_m = y_m + rho x_{m+1}: end value with zero carry,
+  //      carries scanned downward over the chunks
   {
-    const D cin = sC2[tid];
+    D X = zero<double>();
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) x[i] = fma(sPow[len - i], cin, x[i]);
-  }
-  // ---- u = v + rho x; sector: rank-one correction of the first row,
-  //      e_m -= K (rho^m - rho^{2N-m}),  K = rho^2 e_0 / (1 - rho^{2N+2})
-  if (!periodic) {
-    if (c == 0) sE2[dl] = mul(rho, x[0]);
-    __syncthreads();
-    if (act) {
-      const D Kc = mul(mul(mul(rho, rho), sE2[dl]), K.sinv);
-      const D pa = mul(Kc, sPowC[c]);   // K rho^m at i = 0
-      const D pbk = mul(Kc, sPowS[c]);  // K rho^{2N-m} at i = len-1
+    for (int i = MM - 1; i >= 0; --i)
+      if (EQ || i < len) X = fma(rho, X, xr[i]);
+    D Sv = (c < NC) ? X : zero<double>();
+    D lv = K->rM;
 #pragma unroll
-      for (int i = 0; i < MAXM; ++i)
-        if (i < len)
-          x[i] = sub(fma(rho, x[i], to_d(v[i])), sub(mul(pa, sPow[i]), mul(pbk, sPow[len - 1 - i])));
+    for (int l = 0; l < 6; ++l) {
+      const int dd = 1 << l;
+      if (dd < W) {
+        const D dn = shfl_down(Sv, dd, W);
+        if (c + dd < W) Sv = fma(lv, dn, Sv);
+        lv = mul(lv, lv);
+      }
     }
+    const D xN = periodic ? mul(shfl_idx(Sv, seg, 64), K->winv) : zero<double>();  // x_NT = x_0
+    D nxt = shfl_down(Sv, 1, W);
+    D x;
+    if (c >= NC - 1) x = xN;
+    else x = fma(mul(sPowC[NC - 2 - c], K->rL), xN, nxt);
+#pragma unroll
+    for (int i = MM - 1; i >= 0; --i)
+      if (EQ || i < len) {
+        x = fma(rho, x, xr[i]);
+        xr[i] = x;
+      }
+  }
+  // ---- u = v + e, e = rho x, written to the tile rounded to S (the next step
+  //      starts from u as stored, exactly as a new march call would); sector:
+  //      rank-one correction of the first row,
+  //      e_m -= Kc (rho^m - rho^{2NT-m}),  Kc = rho^3 x_0 / (1 - rho^{2NT+2})
+  if (periodic) {
+#pragma unroll
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < len) {
+        T[i] = from_d<S>(fma(rho, xr[i], vat(i)));
+        __builtin_amdgcn_sched_barrier(0);
+      }
   } else {
+    const D x0 = shfl_idx(xr[0], seg, 64);
+    const D Kc = mul(mul(mul(rho, rho), mul(rho, x0)), K->sinv);
+    D pa = mul(Kc, sPowC[c < kPassBPow ? c : 0]);
+    D pb = mul(Kc, sPowS[c < kPassBPow ? c : 0]);
+    const D rinv = K->rinv;
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) x[i] = fma(rho, x[i], to_d(v[i]));
-  }
-  // x now holds u^{j+1}.  Next step's azimuth factor w = u + s_{j+1} D_theta u, or store u.
-  if (!last) {
-    // start the next step from u^{j+1} as stored (rounded to S), exactly as a
-    // new march call would: an interrupted and resumed march is bitwise equal
-    // to an uninterrupted one
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) x[i] = to_d(from_d<S>(x[i]));
-    D* sUf = sE1;
-    D* sUl = sC1;
-    sUf[tid] = (len > 0) ? x[0] : zero<double>();
-    D xl = zero<double>();
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i == len - 1) xl = x[i];
-    sUl[tid] = xl;
-    __syncthreads();
-    if (act) {
-      D ul, ur;
-      if (c > 0) ul = sUl[(c - 1) * TD + dl];
-      else ul = periodic ? sUl[(NC - 1) * TD + dl] : zero<double>();
-      if (c < NC - 1) ur = sUf[(c + 1) * TD + dl];
-      else ur = periodic ? sUf[dl] : zero<double>();
-      const double s1 = K.s1;
-      D a = ul;
-#pragma unroll
-      for (int i = 0; i < MAXM; ++i) {
-        if (i < len) {
-          const D b = (i + 1 < len) ? x[i + 1] : ur;
-          const D dd = sub(add(a, b), scl(2.0, x[i]));
-          dst[(size_t)(m0 + i) * N + z] = from_d<S>(mk<double>(x[i].re - s1 * dd.im, x[i].im + s1 * dd.re));
-          a = x[i];
-        }
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < len) {
+        const D e = sub(mul(rho, xr[i]), sub(pa, pb));
+        pa = mul(pa, rho);
+        pb = mul(pb, rinv);
+        T[i] = from_d<S>(add(vat(i), e));
+        __builtin_amdgcn_sched_barrier(0);
       }
-    }
-  } else if (act) {
+  }
+  // ---- next step's azimuth factor w = u + s_{j+1} D_theta u over the tile.
+  //      All lanes of a line are in one wavefront: the chunk-edge neighbours
+  //      are read before any lane of the line writes, and each lane then
+  //      reads slot i+1 before writing slot i.
+  if (!last) {
+    D ul, ur;
+    if (c > 0) ul = to_d(T[M - 1 - CST]);
+    else if (periodic) ul = to_d(tl[lidx(NT - 1, dl)]);
+    else ul = zero<double>();
+    if (c < NC - 1) ur = to_d(T[CST]);
+    else ur = periodic ? to_d(tl[dl * DS]) : zero<double>();
+    const double s1 = K->s1;
+    D a = ul, b = vat(0);
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i)
-      if (i < len) dst[(size_t)(m0 + i) * N + z] = from_d<S>(x[i]);
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < len) {
+        const D nx = (EQ ? (i + 1 < MM) : (i + 1 < len)) ? vat(i + 1 < MM ? i + 1 : i) : ur;
+        const D dd = sub(add(a, nx), scl(2.0, b));
+        T[i] = from_d<S>(mk<double>(b.re - s1 * dd.im, b.im + s1 * dd.re));
+        a = b;
+        b = nx;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+  __syncthreads();
+  // ---- store the tile (coalesced along depth).  The staging addresses are
+  //      recomputed here rather than kept live through the solve.
+  if (szok) {
+    int sm0r = sm0, sdlr = sdl;
+    asm volatile("" : "+v"(sm0r), "+v"(sdlr));
+    const unsigned o0 = unsigned(sm0r * N + szc), dq = unsigned(W * N);
+#pragma unroll
+    for (int q = 0; q < MM; ++q) {
+      const int m = sm0r + q * W;
+      if ((EQ || q < M) && (EQ || m < NT)) gstore(dst, o0 + unsigned(q) * dq, tl[lidx(m, sdlr)]);
+    }
   }
 }
 
-template <typename S, int MAXM>
-__global__ __launch_bounds__(kPassBThreads) void pass_b_single(ProbDesc d, int koff) {
-  pass_b_body<S, MAXM>(d, blockIdx.x, koff);
+// two workgroups per CU: one stages or stores its tile while the other computes
+#define PE3D_PASS_B_OCC __attribute__((amdgpu_waves_per_eu(4, 4)))
+
+template <typename S, int MM, bool EQ>
+__global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_single(ProbDesc d, int koff) {
+  extern __shared__ __align__(16) unsigned char smem_b[];
+  pass_b_body<S, MM, EQ>(d, blockIdx.x, koff, smem_b);
 }
 
-template <typename S, int MAXM>
-__global__ __launch_bounds__(kPassBThreads) void pass_b_batch(const ProbDesc* __restrict__ descs,
+template <typename S, int MM, bool EQ>
+__global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_batch(const ProbDesc* __restrict__ descs,
                                                               const WorkItem* __restrict__ items,
                                                               int koff) {
+  extern __shared__ __align__(16) unsigned char smem_b[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_b_body<S, MAXM>(d, it.tile, koff);
+  pass_b_body<S, MM, EQ>(d, it.tile, koff, smem_b);
 }
 
 // ============================================================== small kernels
@@ -770,14 +844,25 @@ static hipError_t run_a(const ProbDesc* single, const ProbDesc* d_descs, const W
   return hipGetLastError();
 }
 
-template <typename S, int MAXM>
+template <typename S, int MM, bool EQ>
 static hipError_t run_b(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
-                        int nitems, int koff, hipStream_t st) {
+                        int nitems, int koff, int lds, hipStream_t st) {
+  constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, MM);  // W = 64 is the largest tile
+  if (lds > lds_max) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_single<S, MM, EQ>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_batch<S, MM, EQ>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e1 != hipSuccess || e2 != hipSuccess) return e1 != hipSuccess ? e1 : e2;
+    attr = true;
+  }
   if (single) {
-    hipLaunchKernelGGL((pass_b_single<S, MAXM>), dim3(single->ntile_b), dim3(kPassBThreads), 0, st,
+    hipLaunchKernelGGL((pass_b_single<S, MM, EQ>), dim3(single->ntile_b), dim3(kPassBThreads), lds, st,
                        *single, koff);
   } else {
-    hipLaunchKernelGGL((pass_b_batch<S, MAXM>), dim3(nitems), dim3(kPassBThreads), 0, st, d_descs,
+    hipLaunchKernelGGL((pass_b_batch<S, MM, EQ>), dim3(nitems), dim3(kPassBThreads), lds, st, d_descs,
                        items, koff);
   }
   return hipGetLastError();
@@ -809,20 +894,30 @@ hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc
   return run_a_m<double>(M, single, d_descs, items, nitems, koff, lds, st);
 }
 
-hipError_t launch_pass_b(int prec, int maxm, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, hipStream_t st) {
-  if (prec == 0) {
-    switch (maxm) {
-      case 8: return run_b<float, 8>(single, d_descs, items, nitems, koff, st);
-      case 16: return run_b<float, 16>(single, d_descs, items, nitems, koff, st);
-    }
-  } else {
-    switch (maxm) {
-      case 8: return run_b<double, 8>(single, d_descs, items, nitems, koff, st);
-      case 16: return run_b<double, 16>(single, d_descs, items, nitems, koff, st);
-    }
+int pass_b_lds(int prec, int W, int M) { return pass_b_lds_bytes(prec ? 16 : 8, W, M); }
+
+// cls: M in 9..16 for lines of exactly W*M azimuths, 0 for the general kernel
+template <typename S>
+static hipError_t run_b_cls(int cls, const ProbDesc* single, const ProbDesc* d_descs,
+                            const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
+  switch (cls) {
+    case 0: return run_b<S, 16, false>(single, d_descs, items, nitems, koff, lds, st);
+    case 9: return run_b<S, 9, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 10: return run_b<S, 10, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 11: return run_b<S, 11, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 12: return run_b<S, 12, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 13: return run_b<S, 13, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 14: return run_b<S, 14, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 15: return run_b<S, 15, true>(single, d_descs, items, nitems, koff, lds, st);
+    case 16: return run_b<S, 16, true>(single, d_descs, items, nitems, koff, lds, st);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass_b(int prec, int cls, const ProbDesc* single, const ProbDesc* d_descs,
+                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
+  if (prec == 0) return run_b_cls<float>(cls, single, d_descs, items, nitems, koff, lds, st);
+  return run_b_cls<double>(cls, single, d_descs, items, nitems, koff, lds, st);
 }
 
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n, long long* jsingle,
