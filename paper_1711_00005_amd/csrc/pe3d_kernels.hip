@@ -108,6 +108,13 @@ __device__ __forceinline__ C<S> gload(const C<S>* base, unsigned off) {
   const V v = p[off];
   return mk<S>(v.x, v.y);
 }
+// FP64 complex table entry at a 32-bit byte offset from a uniform base
+__device__ __forceinline__ C<double> gload_b(const void* base, unsigned boff) {
+  using V = Vec2<double>::type;
+  const __attribute__((address_space(1))) char* p = (const __attribute__((address_space(1))) char*)base;
+  const V v = *(const __attribute__((address_space(1))) V*)(p + boff);
+  return mk<double>(v.x, v.y);
+}
 template <typename S>
 __device__ __forceinline__ void gstore(C<S>* base, unsigned off, C<S> val) {
   using V = typename Vec2<S>::type;
@@ -198,6 +205,7 @@ __device__ __forceinline__ int ncp_of(int nc) {
 // Both have the per-slot multiplier nbmh G_j, so one table of lane transfer
 // products serves the two scans.
 constexpr int kPassAThreads = 256;
+
 
 // Exclusive scan of the affine lane maps x -> A x + B within a column:
 // UP: lane t receives the composition of lanes 0..t-1 applied to 0; DOWN:
@@ -305,39 +313,45 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       }
     }
   } else {
+    // first step of a march call only: groups of 4 entries (a rolled loop), so
+    // that its three loads per entry do not set the kernel's register count
     const long long j = *d.jdev + koff;
     const double s0 = sigma_of(d, j);  // s_0 = i * s0
-    C<S> vc[M], vl[M], vr[M];
+    constexpr int QG = 4;
+#pragma unroll 1
+    for (int q0 = 0; q0 < M; q0 += QG) {
+      C<S> vc[QG], vl[QG], vr[QG];
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = lane + q * kPassAThreads;
-      if (e < span) {
-        const int c = int((float(e) + 0.5f) * invN);
-        const int r = e - c * N;
-        const int mm = m0 + c;
-        int ml = mm - 1, mr = mm + 1;
-        if (d.periodic) {
-          if (ml < 0) ml = NT - 1;
-          if (mr >= NT) mr = 0;
+      for (int qq = 0; qq < QG; ++qq) {
+        const int e = lane + (q0 + qq) * kPassAThreads;
+        if (q0 + qq < M && e < span) {
+          const int c = int((float(e) + 0.5f) * invN);
+          const int r = e - c * N;
+          const int mm = m0 + c;
+          int ml = mm - 1, mr = mm + 1;
+          if (d.periodic) {
+            if (ml < 0) ml = NT - 1;
+            if (mr >= NT) mr = 0;
+          }
+          // sector edges: load an in-range column, zero it below
+          vc[qq] = base[e];
+          vl[qq] = src[(size_t)max(ml, 0) * N + r];
+          vr[qq] = src[(size_t)min(mr, NT - 1) * N + r];
         }
-        // sector edges: load an in-range column, zero it below
-        vc[q] = base[e];
-        vl[q] = src[(size_t)max(ml, 0) * N + r];
-        vr[q] = src[(size_t)min(mr, NT - 1) * N + r];
       }
-    }
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = lane + q * kPassAThreads;
-      if (e < span) {
-        const int c = int((float(e) + 0.5f) * invN);
-        const int mm = m0 + c;
-        const bool hl = d.periodic || mm > 0, hr = d.periodic || mm < NT - 1;
-        const D uc = to_d(vc[q]);
-        const D ul = hl ? to_d(vl[q]) : zero<double>();
-        const D ur = hr ? to_d(vr[q]) : zero<double>();
-        const D dd = sub(add(ul, ur), scl(2.0, uc));
-        buf[c * CS + GA + (e - c * N)] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));
+      for (int qq = 0; qq < QG; ++qq) {
+        const int e = lane + (q0 + qq) * kPassAThreads;
+        if (q0 + qq < M && e < span) {
+          const int c = int((float(e) + 0.5f) * invN);
+          const int mm = m0 + c;
+          const bool hl = d.periodic || mm > 0, hr = d.periodic || mm < NT - 1;
+          const D uc = to_d(vc[qq]);
+          const D ul = hl ? to_d(vl[qq]) : zero<double>();
+          const D ur = hr ? to_d(vr[qq]) : zero<double>();
+          const D dd = sub(add(ul, ur), scl(2.0, uc));
+          buf[c * CS + GA + (e - c * N)] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));
+        }
       }
     }
   }
@@ -366,27 +380,36 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 #pragma unroll
     for (int j = 0; j < M; ++j) offb[j] = unsigned((j < sc ? lo : hi) + j * LT) * 16u;
   }
-  const unsigned char* __restrict__ Gt = (const unsigned char*)d.tabG;
-  const unsigned char* __restrict__ Ct = (const unsigned char*)d.tabC;
-  auto G_at = [&](int j) { return *reinterpret_cast<const D*>(Gt + offb[j]); };
-  auto C_at = [&](int j) { return *reinterpret_cast<const D*>(Ct + offb[j]); };
+  // the offset passes through an empty volatile asm so that the load is issued
+  // where it is written (in its prefetch slot), not hoisted to the phase start
+  // A prefetch is issued only after the current slot's value `after` exists:
+  // its offset passes through an empty volatile asm that also reads that
+  // value, so the compiler can neither hoist the load to the phase start nor
+  // sink the slot's arithmetic below it.
+  auto G_at = [&](int j, const D& after) {
+    unsigned o = offb[j];
+    asm volatile("" : "+v"(o) : "v"(after.re));
+    return gload_b(d.tabG, o);
+  };
+  auto C_at = [&](int j, const D& after) {
+    unsigned o = offb[j];
+    asm volatile("" : "+v"(o) : "v"(after.re));
+    return gload_b(d.tabC, o);
+  };
+  // the head lanes' interface coefficients: RHS diagonal, previous and next
+  // coefficient, elimination multiplier, then the two inverse entries
+  const D* hrec = ((const D*)d.rec) + (size_t)(colok ? m : 0) * 12 + (bot ? 6 : 0);
 
   const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
   const D cb = mk<double>(d.bp_re * d.h, d.bp_im * d.h);
   D tp = zero<double>();
   if (top || bot) tp = ((const D*)d.tabP)[(tb * (M + 1) + sc) * L + tc];
-  D hc0 = zero<double>(), hcp = zero<double>(), hcn = zero<double>(), hcF = zero<double>();
-  D hia = zero<double>(), hib = zero<double>();
-  if (head) {
-    const D* hr = ((const D*)d.rec) + (size_t)m * 12 + (bot ? 6 : 0);
-    hc0 = hr[0];
-    hcp = hr[1];
-    hcn = hr[2];
-    hcF = hr[3];
-    hia = hr[4];
-    hib = hr[5];
-  }
   __syncthreads();
+
+  // Table values are prefetched PF slots ahead; the scheduling barrier at the
+  // end of each slot keeps the compiler from hoisting all M loads (and their
+  // registers) to the start of a phase.
+  constexpr int PF = 4;
 
   // ---- phase 1: R = [I + beta_+ X] w along the chain (sliding window), local
   //      elimination with zero carry -> the lane's map yh_out = tp yh_in + E
@@ -394,25 +417,42 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   D Rv[M];
   D E = zero<double>();
   {
+    D gq[PF], cq[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+      if (j < M) {
+        gq[j] = G_at(j, E);
+        cq[j] = C_at(j, E);
+      }
     const C<S>* p = col + row0;
     D wp = to_d(p[-dir]);
     D wc = to_d(p[0]);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const D wn = to_d(p[dir * (j + 1)]);
-      const D g = G_at(j);
-      const D cdv = C_at(j);
+      const D g = gq[j % PF];
+      const D cdv = cq[j % PF];
+      int wi = dir * (j + 1);
+      asm volatile("" : "+v"(wi) : "v"(E.re));
+      const D wn = to_d(p[wi]);
       D R;
       if (j == M - 1) {
-        const D c0 = head ? hc0 : cdv;
-        const D cp = head ? hcp : cb;
-        const D cn = head ? hcn : cb;
+        D c0 = cdv, cp = cb, cn = cb, cf = nbmh;
+        if (head) {
+          c0 = hrec[0];
+          cp = hrec[1];
+          cn = hrec[2];
+          cf = hrec[3];
+        }
         R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
-        const D y = fma(head ? hcF : nbmh, E, R);
+        const D y = fma(cf, E, R);
         E = head ? y : mul(g, y);
       } else {
         R = fma(cdv, wc, mul(cb, add(wp, wn)));
         E = mul(g, fma(nbmh, E, R));
+      }
+      if (j + PF < M) {
+        gq[j % PF] = G_at(j + PF, E);
+        cq[j % PF] = C_at(j + PF, E);
       }
       Rv[j] = R;
       wp = wc;
@@ -425,30 +465,45 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      reduced interface right-hand side r_k or r_{k+1})
   {
     D yh = cin;
+    D gq[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j)
+      if (j < M) gq[j] = G_at(j, yh);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const D g = G_at(j);
+      const D g = gq[j % PF];
       if (j == M - 1) {
-        const D y = fma(head ? hcF : nbmh, yh, Rv[j]);
+        D cf = nbmh;
+        if (head) cf = hrec[3];
+        const D y = fma(cf, yh, Rv[j]);
         Rv[j] = head ? y : mul(g, y);
       } else {
         yh = mul(g, fma(nbmh, yh, Rv[j]));
         Rv[j] = yh;
       }
+      if (j + PF < M) gq[j % PF] = G_at(j + PF, yh);
     }
   }
   // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
   __syncthreads();
-  if (head) Rv[M - 1] = fma(hia, Rv[M - 1], mul(hib, xch[2 * cw + (bot ? 0 : 1)]));
+  if (head) Rv[M - 1] = fma(hrec[4], Rv[M - 1], mul(hrec[5], xch[2 * cw + (bot ? 0 : 1)]));
 
   // ---- phase 3: local back substitution with zero carry -> x_out = tpb x_in + X
   D X = zero<double>();
+  {
+    D gq[PF];
 #pragma unroll
-  for (int j = M - 1; j >= 0; --j) {
-    const D g = G_at(j);
-    if (j == M - 1 && head) X = Rv[j];
-    else X = fma(nbmh, mul(g, X), Rv[j]);
+    for (int jj = 0; jj < PF; ++jj)
+      if (jj < M) gq[jj] = G_at(M - 1 - jj, X);
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) {
+      const int j = M - 1 - jj;
+      const D g = gq[jj % PF];
+      if (j == M - 1 && head) X = Rv[j];
+      else X = fma(nbmh, mul(g, X), Rv[j]);
+      if (jj + PF < M) gq[jj % PF] = G_at(j - PF, X);
+    }
   }
   const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
 
@@ -456,14 +511,20 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      buffer (the input was last read before the interface barrier; zero
   //      slots and idle lanes write guard rows only)
   {
-    C<S>* p = buf + cw * CS + GA + row0;
     D x = xin;
+    D gq[PF];
 #pragma unroll
-    for (int j = M - 1; j >= 0; --j) {
-      const D g = G_at(j);
+    for (int jj = 0; jj < PF; ++jj)
+      if (jj < M) gq[jj] = G_at(M - 1 - jj, x);
+    C<S>* p = buf + cw * CS + GA + row0;
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) {
+      const int j = M - 1 - jj;
+      const D g = gq[jj % PF];
       if (j == M - 1 && head) x = Rv[j];
       else x = fma(nbmh, mul(g, x), Rv[j]);
       p[dir * j] = from_d<S>(x);
+      if (jj + PF < M) gq[jj % PF] = G_at(j - PF, x);
     }
   }
   __syncthreads();
