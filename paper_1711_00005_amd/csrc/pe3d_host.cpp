@@ -117,6 +117,7 @@ struct Built {
   int N = 0, NT = 0, prec = 0, periodic = 0, rigid = 0;
   double k0 = 0, dz = 0, dth = 0, h = 0;
   cd qb, bp, bm;
+  cd cbs;  // beta_+ h / (-beta_- h): off-diagonal of the scaled depth RHS
   std::vector<cd> qw, pw, pb;
   std::vector<cd> tabG, tabC, tabP;  // depth-kernel chain tables and lane products
   std::vector<int> k;
@@ -292,9 +293,13 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     if (det == 0.0 || !std::isfinite(std::abs(det))) return PE3D_EUNSUPPORTED;
     cd id = 1.0 / det;
     // row k (top chain: previous row k-1, next row k+1), then row k+1
-    // (bottom chain, reversed: previous row k+2, next row k)
-    b.rec[m] = {1.0 + bp * xd0, bp * xl0, bp * xu0, cft, Q * id, -c01 * id,
-                1.0 + bp * xd1, bp * xu1, bp * xl1, cfb, P * id, -c10 * id};
+    // (bottom chain, reversed: previous row k+2, next row k).  The kernel
+    // carries right-hand sides divided by nbmh = -beta_- h (see below), so
+    // the RHS and elimination coefficients are divided by nbmh and the
+    // inverse entries multiplied by it.
+    const cd nb = -bm * h, inb = 1.0 / nb;
+    b.rec[m] = {(1.0 + bp * xd0) * inb, bp * xl0 * inb, bp * xu0 * inb, cft * inb, Q * id * nb, -c01 * id * nb,
+                (1.0 + bp * xd1) * inb, bp * xu1 * inb, bp * xl1 * inb, cfb * inb, P * id * nb, -c10 * id * nb};
   }
   // pivots actually used: water rows < kmax, bottom rows > kmin + 1
   for (int l = 0; l < kmax; ++l) {
@@ -311,22 +316,28 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
 
   // chain tables: chain 0 = rows 0..N-2 of the all-water column (top-down
   // pivots), chain 1 = rows N-1..1 of the all-bottom column (bottom-up
-  // pivots, chain row bb = N-1-l); chain row r at [(r+M) % M][(r+M) / M]
+  // pivots, chain row bb = N-1-l); chain row r at [(r+M) % M][(r+M) / M].
+  // With nbmh = -beta_- h (the off-diagonal of every non-interface row) and
+  // right-hand sides carried divided by nbmh, the elimination is
+  // yh_r = Gh_r (Rt_r + yh_{r-1}) and the back substitution
+  // x_r = yh_r + Gh_r x_{r+1}, Gh_r = nbmh / pivot_r: tabG holds Gh and tabC
+  // the diagonal of [I + beta_+ X] divided by nbmh.
   const int L = b.lpc, M = b.ma, LT = b.lt;
   const size_t MLT = (size_t)M * LT;
-  const cd nbmh = -bm * h;
+  const cd nbmh = -bm * h, inb = 1.0 / nbmh;
+  b.cbs = bp * h * inb;
   b.tabG.assign(2 * MLT, 0.0);
   b.tabC.assign(2 * MLT, 0.0);
   auto tix = [&](int r) { const int rp = r + M; return (size_t)(rp % M) * LT + rp / M; };
   for (int r = 0; r <= N - 2; ++r) {
-    b.tabG[tix(r)] = b.pw[r];
-    b.tabC[tix(r)] = 1.0 + bp * (b.qw[r] - 2.0 * h);
+    b.tabG[tix(r)] = nbmh * b.pw[r];
+    b.tabC[tix(r)] = (1.0 + bp * (b.qw[r] - 2.0 * h)) * inb;
   }
   for (int bb = 0; bb <= N - 2; ++bb) {
-    b.tabG[MLT + tix(bb)] = b.pb[N - 1 - bb];
+    b.tabG[MLT + tix(bb)] = nbmh * b.pb[N - 1 - bb];
     cd c = 1.0 + bp * (b.qb - 2.0 * h);
     if (bb == 0) c *= floor_scale;
-    b.tabC[MLT + tix(bb)] = c;
+    b.tabC[MLT + tix(bb)] = c * inb;
   }
   // lane products by (chain, leading zero slots sc = 1..M, lane in chain tc):
   // slot j of the lane holds chain row tc*M + j - sc
@@ -337,8 +348,7 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
         cd p = 1.0;
         for (int j = 0; j < M; ++j) {
           const int r = tc * M + j - sc;
-          const cd gv = (r + M < (int)MLT) ? b.tabG[ch * MLT + tix(r)] : cd(0.0);
-          p *= nbmh * gv;
+          p *= (r + M < (int)MLT) ? b.tabG[ch * MLT + tix(r)] : cd(0.0);
         }
         b.tabP[((size_t)ch * (M + 1) + sc) * L + tc] = p;
       }
@@ -645,6 +655,8 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.bp_im = b.bp.imag();
   d.bm_re = b.bm.real();
   d.bm_im = b.bm.imag();
+  d.cbs_re = b.cbs.real();
+  d.cbs_im = b.cbs.imag();
   d.wb = b.wb;
   d.nc = b.nc;
   d.td = b.td;

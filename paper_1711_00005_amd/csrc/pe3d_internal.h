@@ -27,20 +27,22 @@ struct ProbDesc {
   int lt;               // LT, columns of the lane-major chain tables
   // chain tables, FP64 complex, [2][M][LT] (chain 0: all-water column top-down,
   // chain 1: all-bottom column bottom-up), chain row r at [(r+M) % M][(r+M) / M],
-  // zero outside rows 0..nz-2:
-  const void* tabG;     // 1 / pivot of the chain row
-  const void* tabC;     // diagonal of [I + beta_+ X] of the chain row
-  const void* tabP;     // [2][M+1][L]: product of -beta_- h G over a lane's M slots,
+  // zero outside rows 0..nz-2; nbmh = -beta_- h:
+  const void* tabG;     // nbmh / pivot of the chain row
+  const void* tabC;     // diagonal of [I + beta_+ X] of the chain row, divided by nbmh
+  const void* tabP;     // [2][M+1][L]: product of tabG over a lane's M slots,
                         //   by (chain, leading zero slots sc, lane in chain)
   const void* rec;      // [nth][12] interface rows of each column: for row k then
                         //   row k+1: RHS diagonal, previous and next coefficient
-                        //   along the chain, elimination multiplier, and the two
-                        //   entries of the 2x2 block inverse that give its value
+                        //   along the chain, elimination multiplier (these four
+                        //   divided by nbmh), and the two entries of the 2x2
+                        //   block inverse that give its value (times nbmh)
   const int* kcol;      // [nth] row k(m)
   double h;             // (k0 dz)^-2
   double qb_re, qb_im;  // n^2-1 of the bottom half-space
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
+  double cbs_re, cbs_im;  // beta_+ h / nbmh, off-diagonal of the scaled depth RHS
   // azimuth pass (pass B): W lanes per depth line, NC <= W chunks of M azimuths
   int wb;               // W, lanes per depth line (power of two, 1..64)
   int nc;               // NC = ceil(nth / M)

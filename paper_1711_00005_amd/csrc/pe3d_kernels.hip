@@ -198,14 +198,14 @@ __device__ __forceinline__ int ncp_of(int nc) {
 // chain's first lane has a zero transfer product and no carry crosses from
 // one chain into the next.
 //
-// Recurrences (G = 1/pivot, nbmh = -beta_- h the off-diagonal of every
-// non-interface row of [I + beta_- X] with the rigid floor row halved):
-//   elimination     yh_j = G_j (R_j + nbmh yh_{j-1})
-//   back substitution x_j = yh_j + nbmh G_j x_{j+1}
-// Both have the per-slot multiplier nbmh G_j, so one table of lane transfer
+// Recurrences (nbmh = -beta_- h is the off-diagonal of every non-interface
+// row of [I + beta_- X] with the rigid floor row halved; right-hand sides are
+// carried divided by nbmh, Rt = R / nbmh, and Gh = nbmh / pivot):
+//   elimination        yh_j = Gh_j (Rt_j + yh_{j-1})
+//   back substitution  x_j  = yh_j + Gh_j x_{j+1}
+// Both have the per-slot multiplier Gh_j, so one table of lane transfer
 // products serves the two scans.
 constexpr int kPassAThreads = 256;
-
 
 // Exclusive scan of the affine lane maps x -> A x + B within a column:
 // UP: lane t receives the composition of lanes 0..t-1 applied to 0; DOWN:
@@ -304,12 +304,34 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       const int e = lane + q * kPassAThreads;
       if (e < span) v[q] = base[e];
     }
+    // LDS index of span entry e (column c = e / N, row e - c N): c CS + GA + e - c N
+    if (cpw == 1) {
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = lane + q * kPassAThreads;
-      if (e < span) {
-        const int c = int((float(e) + 0.5f) * invN);
-        buf[c * CS + GA + (e - c * N)] = v[q];
+      for (int q = 0; q < M; ++q) {
+        const int e = lane + q * kPassAThreads;
+        if (e < span) buf[GA + e] = v[q];
+      }
+    } else if (N >= kPassAThreads) {
+      // e advances by 256 <= N per entry: the column advances by at most one
+      int r = lane, idx = GA + lane;
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        if (lane + q * kPassAThreads < span) buf[idx] = v[q];
+        r += kPassAThreads;
+        idx += kPassAThreads;
+        if (r >= N) {
+          r -= N;
+          idx += 2 * GA;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const int e = lane + q * kPassAThreads;
+        if (e < span) {
+          const int c = int((float(e) + 0.5f) * invN);
+          buf[c * CS + GA + (e - c * N)] = v[q];
+        }
       }
     }
   } else {
@@ -380,8 +402,6 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 #pragma unroll
     for (int j = 0; j < M; ++j) offb[j] = unsigned((j < sc ? lo : hi) + j * LT) * 16u;
   }
-  // the offset passes through an empty volatile asm so that the load is issued
-  // where it is written (in its prefetch slot), not hoisted to the phase start
   // A prefetch is issued only after the current slot's value `after` exists:
   // its offset passes through an empty volatile asm that also reads that
   // value, so the compiler can neither hoist the load to the phase start nor
@@ -400,19 +420,17 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // coefficient, elimination multiplier, then the two inverse entries
   const D* hrec = ((const D*)d.rec) + (size_t)(colok ? m : 0) * 12 + (bot ? 6 : 0);
 
-  const D nbmh = mk<double>(-d.bm_re * d.h, -d.bm_im * d.h);
-  const D cb = mk<double>(d.bp_re * d.h, d.bp_im * d.h);
+  const D cbs = mk<double>(d.cbs_re, d.cbs_im);
   D tp = zero<double>();
   if (top || bot) tp = ((const D*)d.tabP)[(tb * (M + 1) + sc) * L + tc];
   __syncthreads();
 
-  // Table values are prefetched PF slots ahead; the scheduling barrier at the
-  // end of each slot keeps the compiler from hoisting all M loads (and their
-  // registers) to the start of a phase.
+  // Table values are prefetched PF slots ahead.
   constexpr int PF = 4;
 
-  // ---- phase 1: R = [I + beta_+ X] w along the chain (sliding window), local
-  //      elimination with zero carry -> the lane's map yh_out = tp yh_in + E
+  // ---- phase 1: Rt = [I + beta_+ X] w / nbmh along the chain (sliding
+  //      window), local elimination with zero carry -> the lane's map
+  //      yh_out = tp yh_in + E
   const C<S>* col = buf + cw * CS + GA;
   D Rv[M];
   D E = zero<double>();
@@ -427,16 +445,17 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     const C<S>* p = col + row0;
     D wp = to_d(p[-dir]);
     D wc = to_d(p[0]);
+    const C<S>* pn = p;  // row of the next window entry, advanced by dir per slot
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
       const D cdv = cq[j % PF];
-      int wi = dir * (j + 1);
-      asm volatile("" : "+v"(wi) : "v"(E.re));
-      const D wn = to_d(p[wi]);
+      pn += dir;
+      asm volatile("" : "+v"(pn) : "v"(E.re));
+      const D wn = to_d(*pn);
       D R;
       if (j == M - 1) {
-        D c0 = cdv, cp = cb, cn = cb, cf = nbmh;
+        D c0 = cdv, cp = cbs, cn = cbs, cf = one<double>();
         if (head) {
           c0 = hrec[0];
           cp = hrec[1];
@@ -447,8 +466,8 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         const D y = fma(cf, E, R);
         E = head ? y : mul(g, y);
       } else {
-        R = fma(cdv, wc, mul(cb, add(wp, wn)));
-        E = mul(g, fma(nbmh, E, R));
+        R = fma(cdv, wc, mul(cbs, add(wp, wn)));
+        E = mul(g, add(R, E));
       }
       if (j + PF < M) {
         gq[j % PF] = G_at(j + PF, E);
@@ -462,7 +481,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const D cin = scan_excl<true>(tp, E, t, L, tot);
 
   // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
-  //      reduced interface right-hand side r_k or r_{k+1})
+  //      reduced interface right-hand side, divided by nbmh)
   {
     D yh = cin;
     D gq[PF];
@@ -473,23 +492,24 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
       if (j == M - 1) {
-        D cf = nbmh;
+        D cf = one<double>();
         if (head) cf = hrec[3];
         const D y = fma(cf, yh, Rv[j]);
         Rv[j] = head ? y : mul(g, y);
       } else {
-        yh = mul(g, fma(nbmh, yh, Rv[j]));
+        yh = mul(g, add(Rv[j], yh));
         Rv[j] = yh;
       }
       if (j + PF < M) gq[j % PF] = G_at(j + PF, yh);
     }
   }
   // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
+  //      (inverse entries times nbmh, r divided by nbmh)
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
   __syncthreads();
   if (head) Rv[M - 1] = fma(hrec[4], Rv[M - 1], mul(hrec[5], xch[2 * cw + (bot ? 0 : 1)]));
 
-  // ---- phase 3: local back substitution with zero carry -> x_out = tpb x_in + X
+  // ---- phase 3: local back substitution with zero carry -> x_out = tp x_in + X
   D X = zero<double>();
   {
     D gq[PF];
@@ -501,7 +521,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       const int j = M - 1 - jj;
       const D g = gq[jj % PF];
       if (j == M - 1 && head) X = Rv[j];
-      else X = fma(nbmh, mul(g, X), Rv[j]);
+      else X = fma(g, X, Rv[j]);
       if (jj + PF < M) gq[jj % PF] = G_at(j - PF, X);
     }
   }
@@ -516,14 +536,15 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 #pragma unroll
     for (int jj = 0; jj < PF; ++jj)
       if (jj < M) gq[jj] = G_at(M - 1 - jj, x);
-    C<S>* p = buf + cw * CS + GA + row0;
+    C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
 #pragma unroll
     for (int jj = 0; jj < M; ++jj) {
       const int j = M - 1 - jj;
       const D g = gq[jj % PF];
       if (j == M - 1 && head) x = Rv[j];
-      else x = fma(nbmh, mul(g, x), Rv[j]);
-      p[dir * j] = from_d<S>(x);
+      else x = fma(g, x, Rv[j]);
+      *p = from_d<S>(x);
+      p -= dir;
       if (jj + PF < M) gq[jj % PF] = G_at(j - PF, x);
     }
   }
@@ -533,12 +554,33 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     int lane_r = lane;
     asm volatile("" : "+v"(lane_r));
     C<S>* __restrict__ out = dst + (size_t)m0 * N;
+    if (cpw == 1) {
 #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = lane_r + q * kPassAThreads;
-      if (e < span) {
-        const int c = int((float(e) + 0.5f) * invN);
-        out[e] = buf[c * CS + GA + (e - c * N)];
+      for (int q = 0; q < M; ++q) {
+        const int e = lane_r + q * kPassAThreads;
+        if (e < span) out[e] = buf[GA + e];
+      }
+    } else if (N >= kPassAThreads) {
+      int r = lane_r, idx = GA + lane_r;
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const int e = lane_r + q * kPassAThreads;
+        if (e < span) out[e] = buf[idx];
+        r += kPassAThreads;
+        idx += kPassAThreads;
+        if (r >= N) {
+          r -= N;
+          idx += 2 * GA;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < M; ++q) {
+        const int e = lane_r + q * kPassAThreads;
+        if (e < span) {
+          const int c = int((float(e) + 0.5f) * invN);
+          out[e] = buf[c * CS + GA + (e - c * N)];
+        }
       }
     }
   }
@@ -640,26 +682,24 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       K->s1 = sigma_of(d, j + 1);
     }
   }
-  // ---- stage the tile: thread tid loads depth z0 + tid % TD of azimuths
-  //      tid / TD + q W, q < M (NT <= W M); all loads issued before the
+  // ---- stage the tile: thread tid loads chunk tid / TD of depth z0 + tid % TD
+  //      (W chunks x TD depths = 512 threads); all loads issued before the
   //      first LDS write
   const int sdl = tid & (TD - 1);
-  const int sm0 = tid >> lgTD;
+  const int sc0 = tid >> lgTD;
   const int szc = min(z0 + sdl, N - 1);
   const bool szok = z0 + sdl < N;
+  const int slen = EQ ? MM : (sc0 < NC - 1 ? M : (sc0 == NC - 1 ? NT - (NC - 1) * M : 0));
   {
-    const unsigned o0 = unsigned(sm0 * N + szc), dq = unsigned(W * N);
+    const unsigned o0 = unsigned(sc0 * M * N + szc);
     C<S> v[MM];
 #pragma unroll
-    for (int q = 0; q < MM; ++q) {
-      const int m = sm0 + q * W;
-      if ((EQ || q < M) && (EQ || m < NT)) v[q] = gload(src, o0 + unsigned(q) * dq);
-    }
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < slen) v[i] = gload(src, o0 + unsigned(i * N));
+    C<S>* Ts = tl + sc0 * CST + sdl * DS;
 #pragma unroll
-    for (int q = 0; q < MM; ++q) {
-      const int m = sm0 + q * W;
-      if ((EQ || q < M) && (EQ || m < NT)) tl[lidx(m, sdl)] = szok ? v[q] : zero<S>();
-    }
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < slen) Ts[i] = szok ? v[i] : zero<S>();
   }
   __syncthreads();
 
@@ -809,17 +849,15 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       }
   }
   __syncthreads();
-  // ---- store the tile (coalesced along depth).  The staging addresses are
-  //      recomputed here rather than kept live through the solve.
+  // ---- store the tile (coalesced along depth)
   if (szok) {
-    int sm0r = sm0, sdlr = sdl;
-    asm volatile("" : "+v"(sm0r), "+v"(sdlr));
-    const unsigned o0 = unsigned(sm0r * N + szc), dq = unsigned(W * N);
+    int sc0r = sc0;
+    asm volatile("" : "+v"(sc0r));  // recomputed here rather than kept live through the solve
+    const unsigned o0 = unsigned(sc0r * M * N + szc);
+    const C<S>* Ts = tl + sc0r * CST + sdl * DS;
 #pragma unroll
-    for (int q = 0; q < MM; ++q) {
-      const int m = sm0r + q * W;
-      if ((EQ || q < M) && (EQ || m < NT)) gstore(dst, o0 + unsigned(q) * dq, tl[lidx(m, sdlr)]);
-    }
+    for (int i = 0; i < MM; ++i)
+      if (EQ || i < slen) gstore(dst, o0 + unsigned(i * N), Ts[i]);
   }
 }
 
