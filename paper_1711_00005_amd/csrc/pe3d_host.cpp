@@ -425,6 +425,8 @@ struct BatchPlan {
   }
 };
 
+constexpr int kBatchClass = -1;  // profiling name "batch"
+
 std::mutex g_mu;
 std::map<std::vector<uintptr_t>, std::unique_ptr<BatchPlan>> g_plans;
 std::list<std::vector<uintptr_t>> g_lru;  // most recent first
@@ -475,7 +477,8 @@ hipEvent_t take_event() {
 
 int prof_name(const char* pass, int prec, int maxm) {
   char buf[48];
-  std::snprintf(buf, sizeof buf, "%s<%s,%d>", pass, prec ? "c128" : "c64", maxm);
+  if (maxm < 0) std::snprintf(buf, sizeof buf, "%s<%s,batch>", pass, prec ? "c128" : "c64");
+  else std::snprintf(buf, sizeof buf, "%s<%s,%d>", pass, prec ? "c128" : "c64", maxm);
   for (size_t i = 0; i < g_pnames.size(); ++i)
     if (g_pnames[i] == buf) return int(i);
   g_pnames.push_back(buf);
@@ -662,6 +665,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.td = b.td;
   d.mb = b.mb;
   d.ntile_b = b.ntile_b;
+  d.bcls = b.maxm_b;
   d.k0 = b.k0;
   d.dr = grid->dr;
   d.r0 = grid->r0;
@@ -728,11 +732,11 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
-          return launch_pass_a(h->prec, h->maxm_a, &d, nullptr, nullptr, 0, k, h->lds_a, st);
+          return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
     if (prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
-          return launch_pass_b(h->prec, h->maxm_b, &d, nullptr, nullptr, 0, k, h->lds_b, st);
+          return launch_pass_b(h->prec, &d, nullptr, nullptr, 0, k, h->lds_b, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
   }
@@ -767,7 +771,12 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::vector<int> order;
   for (int i = 0; i < n; ++i)
     if (nsteps[i] > 0) order.push_back(i);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nsteps[a] > nsteps[b]; });
+  // (and, among equal steps, deeper problems first: their heavier workgroups
+  // are dispatched before the light ones, which shortens the launch tail)
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (nsteps[a] != nsteps[b]) return nsteps[a] > nsteps[b];
+    return hs[a]->desc.nz > hs[b]->desc.nz;
+  });
   const int np = int(order.size());
   P.n = np;
   P.prec = hs[0]->prec;
@@ -789,19 +798,21 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     const ProbDesc& hd = h->desc;
     const double esz = h->prec ? 16.0 : 8.0;
     const int cpw = 256 / hd.lpc;
-    ia_lds[h->maxm_a] = std::max(ia_lds[h->maxm_a], h->lds_a);
+    // one launch per pass for all problems (the batch kernels switch on the
+    // problem's shape); class key kBatchClass
+    ia_lds[kBatchClass] = std::max(ia_lds[kBatchClass], h->lds_a);
     for (int t = 0; t < hd.ntile_a; ++t) {
-      ia[h->maxm_a].push_back({p, t});
-      ia_steps[h->maxm_a].push_back(nsteps[order[p]]);
+      ia[kBatchClass].push_back({p, t});
+      ia_steps[kBatchClass].push_back(nsteps[order[p]]);
       const int ncol = std::min(cpw, hd.nth - t * cpw);
-      ia_bytes[h->maxm_a].push_back(2.0 * esz * ncol * hd.nz);
+      ia_bytes[kBatchClass].push_back(2.0 * esz * ncol * hd.nz);
     }
-    ib_lds[h->maxm_b] = std::max(ib_lds[h->maxm_b], h->lds_b);
+    ib_lds[kBatchClass] = std::max(ib_lds[kBatchClass], h->lds_b);
     for (int t = 0; t < hd.ntile_b; ++t) {
-      ib[h->maxm_b].push_back({p, t});
-      ib_steps[h->maxm_b].push_back(nsteps[order[p]]);
+      ib[kBatchClass].push_back({p, t});
+      ib_steps[kBatchClass].push_back(nsteps[order[p]]);
       const int nd = std::min(hd.td, hd.nz - t * hd.td);
-      ib_bytes[h->maxm_b].push_back(2.0 * esz * nd * hd.nth);
+      ib_bytes[kBatchClass].push_back(2.0 * esz * nd * hd.nth);
     }
   }
   size_t nitems = 0;
@@ -856,14 +867,14 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
     for (auto& c : P.a) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_a(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
+            return launch_pass_a(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
           }) != hipSuccess)
         return PE3D_EDEVICE;
     }
     for (auto& c : P.b) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_b(P.prec, c.maxm, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
+            return launch_pass_b(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
           }) != hipSuccess)
         return PE3D_EDEVICE;
     }

@@ -49,6 +49,7 @@ struct ProbDesc {
   int td;               // depths per workgroup = kPassBThreads / W
   int mb;               // M, azimuth nodes per chunk (<= 16)
   int ntile_b;          // ceil(nz / td)
+  int bcls;             // kernel class: M (9..16) if nth == W*M, else 0 (general)
   double k0, dr, r0, dth;
   double dz;            // starter / TL only
 };
@@ -62,12 +63,14 @@ constexpr int kPassBThreads = 512;
 
 // kernel launchers (pe3d_kernels.hip); all return a hipError_t
 // single != nullptr: one problem, grid from single->ntile_a / ntile_b, the
-// descriptor passed by value.  Otherwise a batched launch over nitems items.
-hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st);
+// descriptor passed by value.  Otherwise a batched launch over nitems items
+// of problems of any shape.  lds: dynamic LDS bytes (pass_a_lds / pass_b_lds,
+// the largest over the problems of a batched launch).
+hipError_t launch_pass_a(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                         int nitems, int koff, int lds, hipStream_t st);
 int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pass A workgroup
-hipError_t launch_pass_b(int prec, int cls, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st);
+hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                         int nitems, int koff, int lds, hipStream_t st);
 int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n,
                           long long* jsingle, int add, hipStream_t st);

@@ -594,13 +594,24 @@ __global__ PE3D_PASS_A_ATTR void pass_a_single(ProbDesc d, int koff) {
   pass_a_body<S, M>(d, blockIdx.x, koff, smem_a);
 }
 
-template <typename S, int M>
-__global__ PE3D_PASS_A_ATTR void pass_a_batch(const ProbDesc* __restrict__ descs,
+// Batched launch over work items of problems with any M: each workgroup takes
+// the body specialised for its problem's M (a uniform branch).
+template <typename S>
+__global__ PE3D_PASS_A_ATTR __attribute__((amdgpu_waves_per_eu(3))) void pass_a_batch(const ProbDesc* __restrict__ descs,
                                               const WorkItem* __restrict__ items, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_a_body<S, M>(d, it.tile, koff, smem_a);
+  switch (d.ma) {
+    case 3: pass_a_body<S, 3>(d, it.tile, koff, smem_a); break;
+    case 5: pass_a_body<S, 5>(d, it.tile, koff, smem_a); break;
+    case 7: pass_a_body<S, 7>(d, it.tile, koff, smem_a); break;
+    case 9: pass_a_body<S, 9>(d, it.tile, koff, smem_a); break;
+    case 11: pass_a_body<S, 11>(d, it.tile, koff, smem_a); break;
+    case 13: pass_a_body<S, 13>(d, it.tile, koff, smem_a); break;
+    case 15: pass_a_body<S, 15>(d, it.tile, koff, smem_a); break;
+    default: pass_a_body<S, 17>(d, it.tile, koff, smem_a); break;
+  }
 }
 
 // ============================================================== pass B
@@ -870,14 +881,25 @@ __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_single(P
   pass_b_body<S, MM, EQ>(d, blockIdx.x, koff, smem_b);
 }
 
-template <typename S, int MM, bool EQ>
+// Batched launch over work items of problems of any class (a uniform branch).
+template <typename S>
 __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_batch(const ProbDesc* __restrict__ descs,
                                                               const WorkItem* __restrict__ items,
                                                               int koff) {
   extern __shared__ __align__(16) unsigned char smem_b[];
   const WorkItem it = items[blockIdx.x];
   const ProbDesc d = descs[it.prob];
-  pass_b_body<S, MM, EQ>(d, it.tile, koff, smem_b);
+  switch (d.bcls) {
+    case 9: pass_b_body<S, 9, true>(d, it.tile, koff, smem_b); break;
+    case 10: pass_b_body<S, 10, true>(d, it.tile, koff, smem_b); break;
+    case 11: pass_b_body<S, 11, true>(d, it.tile, koff, smem_b); break;
+    case 12: pass_b_body<S, 12, true>(d, it.tile, koff, smem_b); break;
+    case 13: pass_b_body<S, 13, true>(d, it.tile, koff, smem_b); break;
+    case 14: pass_b_body<S, 14, true>(d, it.tile, koff, smem_b); break;
+    case 15: pass_b_body<S, 15, true>(d, it.tile, koff, smem_b); break;
+    case 16: pass_b_body<S, 16, true>(d, it.tile, koff, smem_b); break;
+    default: pass_b_body<S, 16, false>(d, it.tile, koff, smem_b); break;
+  }
 }
 
 // ============================================================== small kernels
@@ -918,52 +940,66 @@ __global__ void tl_kernel(ProbDesc d, const C<R>* u, float* tl) {
 
 // ============================================================== launchers
 template <typename S, int M>
-static hipError_t run_a(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
-                        int nitems, int koff, int lds, hipStream_t st) {
+static hipError_t run_a(const ProbDesc& d, int koff, int lds, hipStream_t st) {
   // largest LDS any shape with this M can ask for: L = 4 lanes and nz = 3M - 1
   // (the host keeps nz <= (L-1) M - 1)
   constexpr int lds_max = pass_a_lds_bytes(int(sizeof(C<S>)), 4, 3 * M - 1, M);
   if (lds > lds_max) return hipErrorInvalidValue;
   static bool attr = false;  // allow more than the default dynamic LDS once per kernel
   if (!attr) {
-    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, M>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S, M>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e1 != hipSuccess || e2 != hipSuccess) return e1 != hipSuccess ? e1 : e2;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, M>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e != hipSuccess) return e;
     attr = true;
   }
-  if (single) {
-    hipLaunchKernelGGL((pass_a_single<S, M>), dim3(single->ntile_a), dim3(kPassAThreads), lds, st,
-                       *single, koff);
-  } else {
-    hipLaunchKernelGGL((pass_a_batch<S, M>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs,
-                       items, koff);
+  hipLaunchKernelGGL((pass_a_single<S, M>), dim3(d.ntile_a), dim3(kPassAThreads), lds, st, d, koff);
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t run_a_batch(const ProbDesc* d_descs, const WorkItem* items, int nitems, int koff, int lds,
+                              hipStream_t st) {
+  constexpr int lds_max = pass_a_lds_bytes(int(sizeof(C<S>)), 4, 3 * 17 - 1, 17);
+  if (lds > lds_max) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  hipLaunchKernelGGL((pass_a_batch<S>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs, items, koff);
   return hipGetLastError();
 }
 
 template <typename S, int MM, bool EQ>
-static hipError_t run_b(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
-                        int nitems, int koff, int lds, hipStream_t st) {
+static hipError_t run_b(const ProbDesc& d, int koff, int lds, hipStream_t st) {
   constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, MM);  // W = 64 is the largest tile
   if (lds > lds_max) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    hipError_t e1 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_single<S, MM, EQ>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    hipError_t e2 = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_batch<S, MM, EQ>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (e1 != hipSuccess || e2 != hipSuccess) return e1 != hipSuccess ? e1 : e2;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_single<S, MM, EQ>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e != hipSuccess) return e;
     attr = true;
   }
-  if (single) {
-    hipLaunchKernelGGL((pass_b_single<S, MM, EQ>), dim3(single->ntile_b), dim3(kPassBThreads), lds, st,
-                       *single, koff);
-  } else {
-    hipLaunchKernelGGL((pass_b_batch<S, MM, EQ>), dim3(nitems), dim3(kPassBThreads), lds, st, d_descs,
-                       items, koff);
+  hipLaunchKernelGGL((pass_b_single<S, MM, EQ>), dim3(d.ntile_b), dim3(kPassBThreads), lds, st, d, koff);
+  return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t run_b_batch(const ProbDesc* d_descs, const WorkItem* items, int nitems, int koff, int lds,
+                              hipStream_t st) {
+  constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, 16);
+  if (lds > lds_max) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_batch<S>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
+  hipLaunchKernelGGL((pass_b_batch<S>), dim3(nitems), dim3(kPassBThreads), lds, st, d_descs, items, koff);
   return hipGetLastError();
 }
 
@@ -972,51 +1008,51 @@ int pass_a_lds(int prec, int L, int nz, int M) {
 }
 
 template <typename S>
-static hipError_t run_a_m(int M, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
-                          int nitems, int koff, int lds, hipStream_t st) {
-  switch (M) {
-    case 3: return run_a<S, 3>(single, d_descs, items, nitems, koff, lds, st);
-    case 5: return run_a<S, 5>(single, d_descs, items, nitems, koff, lds, st);
-    case 7: return run_a<S, 7>(single, d_descs, items, nitems, koff, lds, st);
-    case 9: return run_a<S, 9>(single, d_descs, items, nitems, koff, lds, st);
-    case 11: return run_a<S, 11>(single, d_descs, items, nitems, koff, lds, st);
-    case 13: return run_a<S, 13>(single, d_descs, items, nitems, koff, lds, st);
-    case 15: return run_a<S, 15>(single, d_descs, items, nitems, koff, lds, st);
-    case 17: return run_a<S, 17>(single, d_descs, items, nitems, koff, lds, st);
+static hipError_t run_a_m(const ProbDesc& d, int koff, int lds, hipStream_t st) {
+  switch (d.ma) {
+    case 3: return run_a<S, 3>(d, koff, lds, st);
+    case 5: return run_a<S, 5>(d, koff, lds, st);
+    case 7: return run_a<S, 7>(d, koff, lds, st);
+    case 9: return run_a<S, 9>(d, koff, lds, st);
+    case 11: return run_a<S, 11>(d, koff, lds, st);
+    case 13: return run_a<S, 13>(d, koff, lds, st);
+    case 15: return run_a<S, 15>(d, koff, lds, st);
+    case 17: return run_a<S, 17>(d, koff, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass_a(int prec, int M, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
-  if (prec == 0) return run_a_m<float>(M, single, d_descs, items, nitems, koff, lds, st);
-  return run_a_m<double>(M, single, d_descs, items, nitems, koff, lds, st);
+hipError_t launch_pass_a(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                         int nitems, int koff, int lds, hipStream_t st) {
+  if (single) return prec == 0 ? run_a_m<float>(*single, koff, lds, st) : run_a_m<double>(*single, koff, lds, st);
+  return prec == 0 ? run_a_batch<float>(d_descs, items, nitems, koff, lds, st)
+                   : run_a_batch<double>(d_descs, items, nitems, koff, lds, st);
 }
 
 int pass_b_lds(int prec, int W, int M) { return pass_b_lds_bytes(prec ? 16 : 8, W, M); }
 
-// cls: M in 9..16 for lines of exactly W*M azimuths, 0 for the general kernel
+// class: M in 9..16 for lines of exactly W*M azimuths, 0 for the general kernel
 template <typename S>
-static hipError_t run_b_cls(int cls, const ProbDesc* single, const ProbDesc* d_descs,
-                            const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
-  switch (cls) {
-    case 0: return run_b<S, 16, false>(single, d_descs, items, nitems, koff, lds, st);
-    case 9: return run_b<S, 9, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 10: return run_b<S, 10, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 11: return run_b<S, 11, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 12: return run_b<S, 12, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 13: return run_b<S, 13, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 14: return run_b<S, 14, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 15: return run_b<S, 15, true>(single, d_descs, items, nitems, koff, lds, st);
-    case 16: return run_b<S, 16, true>(single, d_descs, items, nitems, koff, lds, st);
+static hipError_t run_b_cls(const ProbDesc& d, int koff, int lds, hipStream_t st) {
+  switch (d.bcls) {
+    case 0: return run_b<S, 16, false>(d, koff, lds, st);
+    case 9: return run_b<S, 9, true>(d, koff, lds, st);
+    case 10: return run_b<S, 10, true>(d, koff, lds, st);
+    case 11: return run_b<S, 11, true>(d, koff, lds, st);
+    case 12: return run_b<S, 12, true>(d, koff, lds, st);
+    case 13: return run_b<S, 13, true>(d, koff, lds, st);
+    case 14: return run_b<S, 14, true>(d, koff, lds, st);
+    case 15: return run_b<S, 15, true>(d, koff, lds, st);
+    case 16: return run_b<S, 16, true>(d, koff, lds, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_pass_b(int prec, int cls, const ProbDesc* single, const ProbDesc* d_descs,
-                         const WorkItem* items, int nitems, int koff, int lds, hipStream_t st) {
-  if (prec == 0) return run_b_cls<float>(cls, single, d_descs, items, nitems, koff, lds, st);
-  return run_b_cls<double>(cls, single, d_descs, items, nitems, koff, lds, st);
+hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                         int nitems, int koff, int lds, hipStream_t st) {
+  if (single) return prec == 0 ? run_b_cls<float>(*single, koff, lds, st) : run_b_cls<double>(*single, koff, lds, st);
+  return prec == 0 ? run_b_batch<float>(d_descs, items, nitems, koff, lds, st)
+                   : run_b_batch<double>(d_descs, items, nitems, koff, lds, st);
 }
 
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n, long long* jsingle,
