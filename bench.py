@@ -4,7 +4,7 @@
 Default workload: the wide-band batch of 64 frequencies (20-500 Hz, dz =
 lambda/8, Ntheta growing with sqrt(f), Munk-like profile over a periodic
 wedge, 107.6 M grid points, 861 MB of complex64 field) advanced together by
-the batched march (one launch per pass and kernel class per range step,
+the batched march (one launch per pass per range step for all 64 problems,
 replayed from a captured hipGraph).  One bench "step" is one range step of
 every problem: pass A + pass B over the whole batch.
 

@@ -59,8 +59,8 @@ typedef enum {
 typedef enum { PE3D_FLOOR_PRESSURE_RELEASE = 0, PE3D_FLOOR_RIGID = 1 } pe3d_floor;
 typedef enum { PE3D_C64 = 0, PE3D_C128 = 1 } pe3d_precision;
 
-/* Ocean environment (the sound sources, receivers and sound-speed profiles
- * read by Fig. 2, line 2).  Water: sound speed c(z) piecewise linear through
+/* Ocean environment (the sound-speed profiles, bathymetry and bottom that
+ * the set-up of Fig. 2 reads).  Water: sound speed c(z) piecewise linear through
  * (ssp_z[i], ssp_c[i]) with ssp_z strictly ascending, constant beyond the
  * ends; uniform density rho_w and attenuation atten_w.  Water depth D(theta)
  * is periodic piecewise linear through (bathy_theta[i], bathy_depth[i]) with
@@ -90,7 +90,7 @@ typedef struct {
  * periodic in azimuth with dtheta = 2 pi/ntheta and theta_m = theta0 + m dtheta;
  * a smaller width is a sector centred on theta0 with dtheta = width/(ntheta+1),
  * theta_m = theta0 - width/2 + (m+1) dtheta and zero field on the two edge
- * azimuths.  The march starts at range r0 with range step dr (Fig. 2, lines 3-5):
+ * azimuths.  The march starts at range r0 with range step dr (the range loop of Fig. 2):
  * r_j = r0 + j*dr. */
 typedef struct {
   int32_t nz, ntheta;
@@ -101,7 +101,7 @@ typedef struct {
 
 typedef struct { double f_hz; } pe3d_freq;
 
-/* Build a march for one frequency (Fig. 2, lines 1-2 and 7): validates all
+/* Build a march for one frequency (the set-up of Fig. 2): validates all
  * arguments before touching the device, builds the medium and the depth
  * operator in FP64 on the host, factors the depth system [1 + (1/4 - d/4) X]
  * once (the medium depends on (theta, z) only, so it is range invariant),
@@ -119,7 +119,7 @@ typedef struct { double f_hz; } pe3d_freq;
 pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,
                         const pe3d_freq* freq, pe3d_handle* out);
 
-/* Advance the field by nsteps range steps of Eq. (4) (Fig. 2, lines 4-9):
+/* Advance the field by nsteps range steps of Eq. (4) (the range loop of Fig. 2):
  * u_dev holds u^j on entry and u^{j+nsteps} on exit (in place).  Each step
  * forms RHS = [1 + (1/4 + d/4) X][1 + (d/4) Y] u^j, solves Eq. (5) per
  * azimuth column and Eq. (6) per depth.  Launches one kernel per pass per
@@ -147,20 +147,21 @@ pe3d_status pe3d_get_step(pe3d_handle h, int64_t* j, double* r);
 pe3d_status pe3d_set_step(pe3d_handle h, int64_t j);
 
 /* Fill u_dev with the Gaussian starter field of a source at depth zs
- * (Fig. 2, line 2; the same on every azimuth):
+ * (the initial field of Fig. 2; the same on every azimuth):
  *   u(z) = sqrt(k0) [exp(-k0^2 (z - zs)^2 / 2) - exp(-k0^2 (z + zs)^2 / 2)].
  * Asynchronous on `stream`.  Errors: PE3D_EINVAL (zs not finite or < 0). */
 pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
 
-/* Advance n problems together (the frequency loop of Fig. 2, lines 1 and
- * 12, distributed over MPI ranks in Sec. 3.2.3): problem i moves by
+/* Advance n problems together (the frequency loop of Fig. 2, distributed
+ * over MPI ranks in Sec. 3.2.3): problem i moves by
  * nsteps[i] >= 0 steps, its field u_devs[i] in place.  All handles must have
  * the same precision and be distinct.  Each step runs one launch per pass
- * and kernel class over every problem still stepping (a device work table
- * of (problem, tile) items).  When use_graph != 0 the whole sequence is
- * captured once into a hipGraph, cached on the first handle under the exact
- * argument tuple (handles, steps, field pointers), and replayed on later
- * identical calls.  Results are bitwise identical to pe3d_march of each
+ * over every problem still stepping (a device work table of (problem, tile)
+ * items; the kernels take each problem's shape from its descriptor).  When
+ * use_graph != 0 the whole sequence is captured once into a hipGraph, kept
+ * in a library-wide cache of at most 64 plans (least recently used evicted,
+ * plans of a destroyed handle dropped) under the exact argument tuple
+ * (handles, steps, field pointers), and replayed on later identical calls.  Results are bitwise identical to pe3d_march of each
  * problem alone.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
 pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
                              const int32_t* nsteps, void* const* u_devs,

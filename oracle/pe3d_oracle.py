@@ -252,7 +252,7 @@ def step(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
 
 
 def march(st: Setup, u0: np.ndarray, j0: int, nsteps: int, callback=None) -> np.ndarray:
-    """Advance u^{j0} by nsteps range steps (Fig. 2, lines 4-9).  If given,
+    """Advance u^{j0} by nsteps range steps (the range loop of Fig. 2).  If given,
     callback(j, u) is called after every step with the new step index."""
     u = np.asarray(u0, dtype=np.complex128).copy()
     for k in range(nsteps):
@@ -264,7 +264,7 @@ def march(st: Setup, u0: np.ndarray, j0: int, nsteps: int, callback=None) -> np.
 
 def starter(st: Setup, zs: float) -> np.ndarray:
     """Gaussian starter with a surface image (reading A11; the paper says only
-    'initialization', Fig. 2 line 2):
+    the initial field of Fig. 2):
         u0(z) = sqrt(k0) [exp(-k0^2 (z - zs)^2 / 2) - exp(-k0^2 (z + zs)^2 / 2)]
     identical on every azimuth."""
     k0, z = st.k0, st.z

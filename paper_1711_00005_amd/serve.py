@@ -13,7 +13,7 @@ Scheduling, per iteration:
      in the HBM budget - admission happens between iterations, so requests
      arriving while others run join the resident set (continuous batching);
   3. every resident request advances by min(K, steps left) range steps in one
-     batched march (one launch per pass and kernel class per step over all of
+     batched march (one launch per pass per step over all of
      them, pe3d_march_batch);
   4. requests that reached their range are checked (non-finite field ->
      failed), summarised, and their device memory is released.
