@@ -54,6 +54,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="also march config 2 to 5000 steps in complex64 and complex128 and compare "
+                         "with the stored oracle samples every 500 steps")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-range-scale", type=float, default=0.25)
     return ap.parse_args()
@@ -99,23 +102,37 @@ def march_steps(P, ms, us, nsteps, chunk, use_graph):
         done += k
 
 
+def _oracle_one_step(p):
+    import oracle as O
+    t0 = time.perf_counter()
+    st = O.setup(p.env, p.grid, p.f_hz)
+    u0 = O.starter(st, p.zs)
+    u1 = O.step(st, u0, 0)
+    return u1, time.perf_counter() - t0
+
+
 def cpu_baseline(probs, sample_every: int):
     """The oracle (complex128 NumPy) on a bounded sample: one range step of
-    every `sample_every`-th problem from its starter."""
-    import oracle as O
+    every `sample_every`-th problem from its starter, one process per
+    problem over the host cores this process may use (at most 16), as the
+    paper spreads frequencies over MPI ranks.  Runs before the GPU is
+    touched (the worker processes are forked)."""
+    import multiprocessing as mp
     sample = probs[::sample_every]
     pts = sum(p.points for p in sample)
-    t0 = time.perf_counter()
-    outs = []
-    for p in sample:
-        st = O.setup(p.env, p.grid, p.f_hz)
-        u0 = O.starter(st, p.zs)
-        outs.append(O.step(st, u0, 0))
-    dt = time.perf_counter() - t0
-    return dict(value=pts / dt, unit=UNIT, cores=1, kind="oracle",
+    cores = max(1, min(len(sample), len(os.sched_getaffinity(0)), 16))
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_one_step, sample, chunksize=1)
+        dt = time.perf_counter() - t0
+    outs = [r[0] for r in res]
+    busy = sum(r[1] for r in res)
+    return dict(value=pts / dt, unit=UNIT, cores=cores, kind="oracle",
                 sample=f"1 range step of {len(sample)} of the {len(probs)} problems "
-                       f"(every {sample_every}th, {pts} points) from the starter, single thread"), \
-        sample, outs
+                       f"(every {sample_every}th, {pts} points) from the starter, one process "
+                       f"per problem on {cores} cores",
+                single_core_value=pts / busy), sample, outs
 
 
 def main():
@@ -125,12 +142,19 @@ def main():
               "batch is independent, so N GPUs would each run their own share with no exchange.",
               file=sys.stderr)
         sys.exit(2)
+    probs, workload = problems_for(args)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle), before the GPU is initialised")
+        every = 8 if len(probs) >= 8 else 1
+        cpu = cpu_baseline(probs, every)
+        log(f"oracle {cpu[0]['value']:.3e} pt*steps/s on {cpu[0]['cores']} cores")
+
     import torch
     from paper_1711_00005_amd import pe3d as P
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
     torch.cuda.set_device(0)
-    probs, workload = problems_for(args)
     npts = sum(p.points for p in probs)
     log(f"workload: {len(probs)} problems, {npts} points")
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
@@ -211,19 +235,17 @@ def main():
         log(f"plain: {pv:.4e} pt*steps/s -> batched/plain = {value / pv:.2f}")
 
     # ---- oracle baseline and parity sample
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        every = 8 if len(probs) >= 8 else 1
-        cb, sample, outs = cpu_baseline(probs, every)
+    if cpu is not None:
+        cb, sample, outs = cpu
         out["cpu_baseline"] = cb
         errs = []
-        import oracle as O
         for p, ref in zip(sample, outs):
             m = P.Pe3d(p.env, p.grid, p.f_hz)
             u = m.starter(p.zs)
             m.march(1, u)
             torch.cuda.synchronize()
-            errs.append(O.rel_l2(u.cpu().numpy().astype(np.complex128), ref))
+            got = u.cpu().numpy().astype(np.complex128)
+            errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
             m.close()
         out["parity_sample"] = dict(max_rel_l2=max(errs), problems=len(errs), steps=1,
                                     reference="complex128 oracle")
@@ -254,7 +276,51 @@ def main():
         out["serving"] = rep
         log(f"serve: p50 {rep['p50_latency_s']:.3f} s, p99 {rep['p99_latency_s']:.3f} s, "
             f"{rep['throughput_pt_steps_per_s']:.3e} pt*steps/s")
+    if args.precision_study:
+        out["precision_study"] = precision_study(P)
     print(json.dumps(out), flush=True)
+
+
+def precision_study(P):
+    """Config 2 (Nz 2048, Ntheta 512, 100 Hz) marched to 5000 steps (50 km) in
+    complex64 (FP64 arithmetic) and complex128 on the GPU; at every 500 steps
+    the field on the stored sample nodes (every 4th azimuth, 16th depth) is
+    compared with the complex128 oracle: relative L2 over the samples, and
+    the TL difference |20 log10(|u_gpu| / |u_orc|)| (RMS and max, dB) over
+    the samples within 60 dB of the oracle's full-field peak."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "config3_oracle_samples.npz")
+    if not os.path.exists(path):
+        log("precision study: no stored oracle samples")
+        return None
+    g = np.load(path)
+    cps = [int(c) for c in g["checkpoints"]]
+    ts, zs = int(g["th_stride"]), int(g["z_stride"])
+    res = dict(workload="config2 to 5000 steps (50 km)", checkpoints=cps,
+               reference="complex128 oracle, sampled every 4th azimuth and 16th depth")
+    for prec, name in ((W.PREC_C64, "complex64"), (W.PREC_C128, "complex128")):
+        p = W.config2(nsteps=max(cps), precision=prec)
+        m = P.Pe3d(p.env, p.grid, p.f_hz)
+        u = m.starter(p.zs)
+        rel, tl_rms, tl_max = [], [], []
+        j = 0
+        t0 = time.perf_counter()
+        for c in cps:
+            m.march(c - j, u)
+            j = c
+            torch.cuda.synchronize()
+            us = u.cpu().numpy().astype(np.complex128)[::ts, ::zs]
+            ref = g[f"u{c}"]
+            rel.append(float(np.linalg.norm(us - ref) / np.linalg.norm(ref)))
+            keep = np.abs(ref) >= 1e-3 * float(g[f"peak{c}"])
+            d = np.abs(20.0 * np.log10(np.abs(us[keep]) / np.abs(ref[keep])))
+            tl_rms.append(float(np.sqrt(np.mean(d * d))))
+            tl_max.append(float(d.max()))
+        res[name] = dict(rel_l2=rel, tl_rms_db=tl_rms, tl_max_db=tl_max,
+                         seconds=round(time.perf_counter() - t0, 3))
+        log(f"precision {name}: rel L2 {['%.2e' % x for x in rel]}")
+        m.close()
+    return res
 
 
 if __name__ == "__main__":
