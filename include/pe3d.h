@@ -172,6 +172,16 @@ pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
  * device array of ntheta*nz floats.  Asynchronous on `stream`. */
 pe3d_status pe3d_tl(pe3d_handle h, const void* u_dev, float* tl_dev, void* stream);
 
+/* Complex pressure of the handle's current step j (at enqueue) from the
+ * envelope: p = u H0^(1)(k0 r_j), the outgoing Hankel factor split off by the
+ * PE ansatz (Sec. 2.1).  u_dev and p_dev are fields of the handle's shape and
+ * precision ([ntheta][nz], complex64 or complex128, 16-byte aligned, caller
+ * owned; p_dev may equal u_dev).  H0^(1) is evaluated once in FP64 on the
+ * host; the device multiplies in FP64 and rounds to the field type.
+ * Asynchronous on `stream`.  Errors: PE3D_EINVAL (null or unaligned
+ * pointer), PE3D_ESTATE (r_j <= 0, where H0^(1) is singular), PE3D_EDEVICE. */
+pe3d_status pe3d_pressure(pe3d_handle h, const void* u_dev, void* p_dev, void* stream);
+
 /* Static description of the handle (host memory, copied to *info). */
 typedef struct {
   int32_t nz, ntheta, periodic, precision;

@@ -31,7 +31,7 @@ ETA = 1.0 / (40.0 * math.pi * math.log10(math.e))
 __all__ = [
     "ETA", "Setup", "setup", "is_periodic", "interp_ssp", "interp_bathy",
     "thomas", "periodic_thomas_sm", "apply_tridiag", "d_theta", "y_apply", "x_apply",
-    "step", "march", "starter", "tl", "rel_l2",
+    "step", "march", "starter", "tl", "pressure", "rel_l2",
 ]
 
 
@@ -278,6 +278,17 @@ def tl(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
     Tappert factor's amplitude ~ r^-1/2, Sec. 2.1; additive constant dropped)."""
     with np.errstate(divide="ignore"):
         return -20.0 * np.log10(np.abs(u)) + 10.0 * math.log10(st.r(j))
+
+
+def pressure(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
+    """Complex pressure of step j from the envelope: p = u H0^(1)(k0 r_j), the
+    outgoing Hankel factor that the PE ansatz splits off (Sec. 2.1).  The
+    Hankel function is the library routine (SciPy); r_j must be positive."""
+    from scipy.special import hankel1
+    r = st.r(j)
+    if not r > 0.0:
+        raise ValueError("the pressure needs r_j > 0")
+    return u * hankel1(0, st.k0 * r)
 
 
 def rel_l2(x: np.ndarray, ref: np.ndarray) -> float:

@@ -759,6 +759,18 @@ pe3d_status pe3d_tl(pe3d_handle h, const void* u_dev, float* tl_dev, void* strea
   return PE3D_OK;
 }
 
+pe3d_status pe3d_pressure(pe3d_handle h, const void* u_dev, void* p_dev, void* stream) {
+  if (!h || !u_dev || !p_dev || !aligned16(u_dev) || !aligned16(p_dev)) return PE3D_EINVAL;
+  const double r = h->r0 + double(h->j) * h->dr;
+  if (!(r > 0.0)) return PE3D_ESTATE;
+  // H0^(1)(x) = J0(x) + i Y0(x), x = k0 r_j (C++17 special functions, FP64)
+  const double x = h->desc.k0 * r;
+  const double hre = std::cyl_bessel_j(0.0, x), him = std::cyl_neumann(0.0, x);
+  if (launch_scale(h->prec, h->desc, u_dev, p_dev, hre, him, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return PE3D_EDEVICE;
+  return PE3D_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batch

@@ -76,6 +76,8 @@ hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int 
                           long long* jsingle, int add, hipStream_t st);
 hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipStream_t st);
 hipError_t launch_tl(int prec, const ProbDesc& d, const void* u, float* tl, hipStream_t st);
+hipError_t launch_scale(int prec, const ProbDesc& d, const void* u, void* p, double hre, double him,
+                        hipStream_t st);  // p = u * (hre + i him)
 
 
 }  // namespace pe3d

@@ -938,6 +938,15 @@ __global__ void tl_kernel(ProbDesc d, const C<R>* u, float* tl) {
   }
 }
 
+// p = u * H, H = H0^(1)(k0 r_j) evaluated on the host
+template <typename R>
+__global__ void scale_kernel(const C<R>* u, C<R>* p, size_t n, double hre, double him) {
+  const D hh = mk<double>(hre, him);
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (size_t)gridDim.x * blockDim.x)
+    p[idx] = from_d<R>(mul(to_d(u[idx]), hh));
+}
+
 // ============================================================== launchers
 template <typename S, int M>
 static hipError_t run_a(const ProbDesc& d, int koff, int lds, hipStream_t st) {
@@ -1069,6 +1078,19 @@ hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipSt
     hipLaunchKernelGGL(starter_kernel<float>, dim3(blocks), dim3(256), 0, st, d, zs, (C<float>*)u);
   else
     hipLaunchKernelGGL(starter_kernel<double>, dim3(blocks), dim3(256), 0, st, d, zs, (C<double>*)u);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int prec, const ProbDesc& d, const void* u, void* p, double hre, double him,
+                        hipStream_t st) {
+  size_t n = (size_t)d.nz * d.nth;
+  int blocks = int(std::min<size_t>((n + 255) / 256, 4096));
+  if (prec == 0)
+    hipLaunchKernelGGL(scale_kernel<float>, dim3(blocks), dim3(256), 0, st, (const C<float>*)u, (C<float>*)p, n,
+                       hre, him);
+  else
+    hipLaunchKernelGGL(scale_kernel<double>, dim3(blocks), dim3(256), 0, st, (const C<double>*)u,
+                       (C<double>*)p, n, hre, him);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ PE3D_C64 = 0
 PE3D_C128 = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
-            "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_get_info",
+            "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
             "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror")
 
 
@@ -87,6 +87,7 @@ _lib.pe3d_starter.argtypes = [_H, ct.c_double, ct.c_void_p, ct.c_void_p]
 _lib.pe3d_march_batch.argtypes = [ct.POINTER(_H), ct.c_int32, ct.POINTER(ct.c_int32),
                                   ct.POINTER(ct.c_void_p), ct.c_int32, ct.c_void_p]
 _lib.pe3d_tl.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_pressure.argtypes = [_H, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.pe3d_get_info.argtypes = [_H, ct.POINTER(pe3d_info)]
 _lib.pe3d_host_tables.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), ct.POINTER(pe3d_freq),
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
@@ -232,6 +233,11 @@ def pe3d_get_info(h) -> pe3d_info:
     return info
 
 
+def pe3d_pressure(h, u_ptr: int, p_ptr: int, stream_ptr) -> None:
+    _check(_lib.pe3d_pressure(h, ct.c_void_p(u_ptr), ct.c_void_p(p_ptr), ct.c_void_p(stream_ptr)),
+           "pe3d_pressure")
+
+
 def pe3d_tl(h, u_ptr: int, tl_ptr: int, stream_ptr) -> None:
     _check(_lib.pe3d_tl(h, ct.c_void_p(u_ptr), ct.c_void_p(tl_ptr), ct.c_void_p(stream_ptr)), "pe3d_tl")
 
@@ -313,6 +319,14 @@ class Pe3d:
         out = torch.empty((self.ntheta, self.nz), dtype=torch.float32, device=u.device)
         pe3d_tl(self.h, _field_ptr(u, self.nz, self.ntheta, self.precision), out.data_ptr(),
                 _stream_ptr(stream))
+        return out
+
+    def pressure(self, u, stream=None):
+        """p = u H0^(1)(k0 r_j) at the current step, as a new field."""
+        import torch
+        out = torch.empty_like(u)
+        pe3d_pressure(self.h, _field_ptr(u, self.nz, self.ntheta, self.precision),
+                      _field_ptr(out, self.nz, self.ntheta, self.precision), _stream_ptr(stream))
         return out
 
     @property

@@ -88,6 +88,11 @@ def test_create_reports_unsupported_sizes(P):
                                   precision=W.PREC_C128)) == P.PE3D_EUNSUPPORTED
 
 
+def test_pressure_rejects_null_arguments(P):
+    with pytest.raises(P.Pe3dError):
+        P.pe3d_pressure(None, 16, 16, None)
+
+
 def test_null_handles_are_rejected(P):
     with pytest.raises(P.Pe3dError):
         P.pe3d_march(None, 1, 16, None)

@@ -297,6 +297,26 @@ def test_tl_matches_oracle(torch, P):
     m.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", [W.PREC_C128, W.PREC_C64])
+def test_pressure_matches_oracle(torch, P, prec):
+    env = W.wedge_env()
+    grid = W.Grid(nz=128, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec)
+    st = O.setup(env, grid, 50.0)
+    u0 = O.starter(st, 100.0)
+    say("pressure", prec)
+    m = P.Pe3d(env, grid, 50.0)
+    u = to_dev(torch, u0, prec)
+    with pytest.raises(P.Pe3dError):
+        m.pressure(u)  # r_0 = 0: H0^(1) is singular
+    m.march(8, u)
+    p = m.pressure(u)
+    torch.cuda.synchronize()
+    ref = O.pressure(st, O.march(st, u0, 0, 8), 8)
+    assert O.rel_l2(to_host(torch, p), ref) < TOL[prec]
+    m.close()
+
+
 def test_c_abi_rejects_bad_arguments_on_gpu(torch, P):
     env = W.wedge_env()
     grid = W.Grid(nz=64, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=10.0)

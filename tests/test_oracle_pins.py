@@ -350,3 +350,25 @@ def test_node_exactly_on_the_bottom_is_water():
     st = O.setup(env, grid, 30.0)
     assert st.dz == 5.0 and st.z[23] == 120.0
     assert st.water[0].sum() == 24
+
+
+def test_pressure_hankel_factor_textbook_values():
+    """p = u H0^(1)(k0 r): with k0 = 1 m^-1 (c0 = 2 pi m/s, f = 1 Hz) and
+    dr = 1 m, step j has k0 r_j = j.  Tabulated J0, Y0 (Abramowitz & Stegun,
+    Table 9.1): H0^(1)(1) = 0.7651976866 + 0.0882569642 i,
+    H0^(1)(10) = -0.2459357645 + 0.0556711673 i.  Large argument:
+    |H0^(1)(x)|^2 = 2/(pi x) (1 - 1/(8 x^2) + O(x^-4)) (A&S 9.2.28)."""
+    env = W.isovelocity_env(c0=2.0 * math.pi)
+    grid = W.Grid(nz=4, ntheta=3, theta0=0.0, width=W.TWO_PI, dr=1.0, precision=W.PREC_C128)
+    st = O.setup(env, grid, 1.0)
+    assert abs(st.k0 - 1.0) < 1e-15
+    one = np.ones((3, 4), complex)
+    h1 = O.pressure(st, one, 1)[0, 0]
+    h10 = O.pressure(st, one, 10)[0, 0]
+    assert abs(h1 - (0.7651976866 + 0.0882569642j)) < 1e-9
+    assert abs(h10 - (-0.2459357645 + 0.0556711673j)) < 1e-9
+    x = 1000.0
+    hx = O.pressure(st, one, 1000)[0, 0]
+    assert abs(abs(hx) ** 2 * math.pi * x / 2.0 - (1.0 - 1.0 / (8.0 * x * x))) < 1e-11
+    with pytest.raises(ValueError):
+        O.pressure(st, one, 0)
