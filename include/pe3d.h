@@ -58,6 +58,12 @@ typedef enum {
 
 typedef enum { PE3D_FLOOR_PRESSURE_RELEASE = 0, PE3D_FLOOR_RIGID = 1 } pe3d_floor;
 typedef enum { PE3D_C64 = 0, PE3D_C128 = 1 } pe3d_precision;
+/* Coupling between azimuths.  PE3D_MODE_3D: the full operator of Eq. (4).
+ * PE3D_MODE_NX2D: the "weak 3D" (N x 2D) approximation contrasted with the
+ * method in Sec. 1, which ignores the azimuthal coupling: Y = 0, so each step
+ * is [1 + (1/4 - d/4) X] u^{j+1} = [1 + (1/4 + d/4) X] u^j per azimuth and
+ * the azimuth pass is not run. */
+typedef enum { PE3D_MODE_3D = 0, PE3D_MODE_NX2D = 1 } pe3d_mode;
 
 /* Ocean environment (the sound-speed profiles, bathymetry and bottom that
  * the set-up of Fig. 2 reads).  Water: sound speed c(z) piecewise linear through
@@ -91,12 +97,14 @@ typedef struct {
  * a smaller width is a sector centred on theta0 with dtheta = width/(ntheta+1),
  * theta_m = theta0 - width/2 + (m+1) dtheta and zero field on the two edge
  * azimuths.  The march starts at range r0 with range step dr (the range loop of Fig. 2):
- * r_j = r0 + j*dr. */
+ * r_j = r0 + j*dr.  mode selects the azimuthal coupling (pe3d_mode; a
+ * zero-initialised grid is the full 3D march). */
 typedef struct {
   int32_t nz, ntheta;
   double theta0, width;
   double dr, r0;
   int32_t precision;          /* pe3d_precision */
+  int32_t mode;               /* pe3d_mode */
 } pe3d_grid;
 
 typedef struct { double f_hz; } pe3d_freq;
@@ -122,8 +130,9 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,
 /* Advance the field by nsteps range steps of Eq. (4) (the range loop of Fig. 2):
  * u_dev holds u^j on entry and u^{j+nsteps} on exit (in place).  Each step
  * forms RHS = [1 + (1/4 + d/4) X][1 + (d/4) Y] u^j, solves Eq. (5) per
- * azimuth column and Eq. (6) per depth.  Launches one kernel per pass per
- * step on `stream` (the plain, per-problem march).  nsteps == 0 is a no-op.
+ * azimuth column and Eq. (6) per depth (in PE3D_MODE_NX2D: Eq. (5) only).
+ * Launches one kernel per pass per step on `stream` (the plain, per-problem
+ * march).  nsteps == 0 is a no-op.
  * The handle's step counter advances by nsteps at enqueue.  Errors:
  * PE3D_EINVAL (null handle or field, nsteps < 0, misaligned field),
  * PE3D_EDEVICE (launch failure). */
@@ -184,7 +193,7 @@ pe3d_status pe3d_pressure(pe3d_handle h, const void* u_dev, void* p_dev, void* s
 
 /* Static description of the handle (host memory, copied to *info). */
 typedef struct {
-  int32_t nz, ntheta, periodic, precision;
+  int32_t nz, ntheta, periodic, precision, mode;
   double k0, dz, dtheta, dr, r0;
   int32_t pass_a_lanes;   /* lanes per depth column in the depth pass  */
   int32_t pass_a_chunk;   /* rows per lane                              */

@@ -23,6 +23,7 @@ import numpy as np
 
 FLOOR_PRESSURE_RELEASE = 0
 FLOOR_RIGID = 1
+MODE_NX2D = 1
 
 #: dB-per-wavelength to imaginary wavenumber fraction: k = k_r (1 + i*ETA*a)
 #: with a in dB/lambda, because a = 20*log10(e) * k_i * lambda.
@@ -79,6 +80,8 @@ class Setup:
         nz, nth = int(grid.nz), int(grid.ntheta)
         self.nz, self.nth = nz, nth
         self.k0 = 2.0 * math.pi * self.f / env.c0
+        # N x 2D ("weak 3D", Sec. 1): no coupling between azimuths, Y = 0
+        self.nx2d = int(getattr(grid, "mode", 0)) == MODE_NX2D
         # depth nodes z_l = l dz, l = 1..Nz (reading A9)
         if env.floor == FLOOR_RIGID:
             self.dz = env.zmax / nz
@@ -133,7 +136,10 @@ class Setup:
         """Azimuth coefficient of the step j -> j+1: (delta/4) Y = s_j D_theta
         with Y = (k0 r)^-2 d^2/dtheta^2 discretised by the 3-point second
         difference, evaluated at r_{j+1} on both sides of Eq. (4) (reading A3:
-        Fig. 2 advances r before the matrices are updated)."""
+        Fig. 2 advances r before the matrices are updated).  Zero in the
+        N x 2D mode, where Y is dropped."""
+        if self.nx2d:
+            return 0.0 + 0.0j
         r = self.r(j + 1)
         return 1j * self.dr / (4.0 * self.k0 * r * r * self.dth * self.dth)
 
@@ -238,6 +244,8 @@ def step(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
     w = y_apply(st, u, s, +1.0)
     rhs = x_apply(st, w, st.beta_p)
     v = thomas(st.beta_m * st.xl, 1.0 + st.beta_m * st.xd, st.beta_m * st.xu, rhs)
+    if st.nx2d:
+        return v                     # [I - 0 D] u^{j+1} = v
     # azimuth systems: one per depth, unknowns along theta -> move theta last
     vt = v.T
     nth = st.nth

@@ -68,6 +68,7 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (is_periodic(g->width) ? g->ntheta < 3 : g->ntheta < 1) return PE3D_EINVAL;
   if (!is_fin(g->dr) || g->dr <= 0.0 || !is_fin(g->r0) || g->r0 < 0.0) return PE3D_EINVAL;
   if (g->precision != PE3D_C64 && g->precision != PE3D_C128) return PE3D_EINVAL;
+  if (g->mode != PE3D_MODE_3D && g->mode != PE3D_MODE_NX2D) return PE3D_EINVAL;
   if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   if (g->precision == PE3D_C128 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   return PE3D_OK;
@@ -671,6 +672,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.r0 = grid->r0;
   d.dth = b.dth;
   d.dz = b.dz;
+  d.nx2d = grid->mode == PE3D_MODE_NX2D;
   *out = h;
   return PE3D_OK;
 }
@@ -707,6 +709,7 @@ pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info) {
   info->ntheta = d.nth;
   info->periodic = d.periodic;
   info->precision = h->prec;
+  info->mode = d.nx2d ? PE3D_MODE_NX2D : PE3D_MODE_3D;
   info->k0 = d.k0;
   info->dz = d.dz;
   info->dtheta = d.dth;
@@ -735,7 +738,7 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
           return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
-    if (prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
+    if (!d.nx2d && prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
           return launch_pass_b(h->prec, &d, nullptr, nullptr, 0, k, h->lds_b, st);
         }) != hipSuccess)
       return PE3D_EDEVICE;
@@ -819,6 +822,9 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
       const int ncol = std::min(cpw, hd.nth - t * cpw);
       ia_bytes[kBatchClass].push_back(2.0 * esz * ncol * hd.nz);
     }
+    // N x 2D problems have no azimuth pass: the items of the still-stepping
+    // problems stay a prefix of the list, as the steps stay non-increasing
+    if (hd.nx2d) continue;
     ib_lds[kBatchClass] = std::max(ib_lds[kBatchClass], h->lds_b);
     for (int t = 0; t < hd.ntile_b; ++t) {
       ib[kBatchClass].push_back({p, t});

@@ -52,6 +52,9 @@ struct ProbDesc {
   int bcls;             // kernel class: M (9..16) if nth == W*M, else 0 (general)
   double k0, dr, r0, dth;
   double dz;            // starter / TL only
+  int nx2d;             // N x 2D mode (Y = 0): pass A writes the caller's field on
+                        //   the last step, the first step reads it unchanged, and
+                        //   pass B is not launched
 };
 
 struct WorkItem {

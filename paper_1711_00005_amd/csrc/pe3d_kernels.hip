@@ -281,8 +281,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   D* xch = reinterpret_cast<D*>(smem + pass_a_align(cpw * CS * int(sizeof(C<S>))));
   D* tot = xch + 2 * cpw;
   const bool first = (koff == 0);
+  const bool ystage = first && !d.nx2d;  // first step of a 3D march: apply [I + s_0 D]
   const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
-  C<S>* __restrict__ dst = (C<S>*)d.scr;
+  C<S>* __restrict__ dst = (C<S>*)((d.nx2d && koff == d.nsteps - 1) ? d.u : d.scr);
 
   // ---- zero the guard rows of every column buffer, stage the columns.  The
   //      workgroup's columns are one contiguous span of ncols*N values;
@@ -297,7 +298,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const int span = ncols * N;
   const float invN = 1.0f / float(N);
   const C<S>* __restrict__ base = src + (size_t)m0 * N;
-  if (!first) {
+  if (!ystage) {
     C<S> v[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {

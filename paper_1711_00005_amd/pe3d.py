@@ -34,6 +34,8 @@ PE3D_FLOOR_PRESSURE_RELEASE = 0
 PE3D_FLOOR_RIGID = 1
 PE3D_C64 = 0
 PE3D_C128 = 1
+PE3D_MODE_3D = 0
+PE3D_MODE_NX2D = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
@@ -53,7 +55,7 @@ class pe3d_env(ct.Structure):
 class pe3d_grid(ct.Structure):
     _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("theta0", ct.c_double),
                 ("width", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
-                ("precision", ct.c_int32)]
+                ("precision", ct.c_int32), ("mode", ct.c_int32)]
 
 
 class pe3d_freq(ct.Structure):
@@ -62,7 +64,7 @@ class pe3d_freq(ct.Structure):
 
 class pe3d_info(ct.Structure):
     _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("periodic", ct.c_int32),
-                ("precision", ct.c_int32), ("k0", ct.c_double), ("dz", ct.c_double),
+                ("precision", ct.c_int32), ("mode", ct.c_int32), ("k0", ct.c_double), ("dz", ct.c_double),
                 ("dtheta", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
                 ("pass_a_lanes", ct.c_int32), ("pass_a_chunk", ct.c_int32),
                 ("pass_b_chunks", ct.c_int32), ("pass_b_depths", ct.c_int32),
@@ -133,7 +135,8 @@ def make_env(env):
 def make_grid(grid):
     return pe3d_grid(nz=int(grid.nz), ntheta=int(grid.ntheta), theta0=float(grid.theta0),
                      width=float(grid.width), dr=float(grid.dr), r0=float(getattr(grid, "r0", 0.0)),
-                     precision=int(getattr(grid, "precision", PE3D_C64)))
+                     precision=int(getattr(grid, "precision", PE3D_C64)),
+                     mode=int(getattr(grid, "mode", PE3D_MODE_3D)))
 
 
 def _stream_ptr(stream) -> Optional[int]:

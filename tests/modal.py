@@ -14,9 +14,11 @@ import oracle as O
 import workloads as W
 
 
-def modal_march(st, u0, nsteps, floor):
+def modal_march(st, u0, nsteps, floor, coupled=True):
     """Separable problem (theta-independent constant q, uniform density):
-    X = q I + h D2 with sine eigenvectors, D_theta with Fourier modes."""
+    X = q I + h D2 with sine eigenvectors, D_theta with Fourier modes.
+    coupled=False: the N x 2D march (Y = 0), every H_q = 1; then the azimuth
+    transform is the identity and any azimuth grid (sector too) qualifies."""
     nz, nth = st.nz, st.nth
     l = np.arange(1, nz + 1)
     k = np.arange(1, nz + 1)
@@ -37,7 +39,7 @@ def modal_march(st, u0, nsteps, floor):
     cq = np.fft.fft(u0, axis=0) / nth               # cq[q, l]
     ck = np.linalg.solve(phi, cq.T)                 # ck[k, q]
     fac = np.ones(nth, dtype=complex)
-    for j in range(nsteps):
+    for j in range(nsteps if coupled else 0):
         r = st.r0 + (j + 1) * st.dr
         s = 1j * st.dr / (4 * k0 * r * r * (2 * math.pi / nth) ** 2)
         fac *= (1 + s * mu) / (1 - s * mu)

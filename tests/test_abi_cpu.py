@@ -63,7 +63,7 @@ def test_create_rejects_invalid_arguments_without_a_device(P):
     ok = dict(nz=64, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=10.0)
     bad_grids = [
         dict(ok, nz=1), dict(ok, ntheta=2), dict(ok, dr=0.0), dict(ok, dr=float("nan")),
-        dict(ok, r0=-1.0), dict(ok, width=0.0), dict(ok, precision=7),
+        dict(ok, r0=-1.0), dict(ok, width=0.0), dict(ok, precision=7), dict(ok, mode=2), dict(ok, mode=-1),
     ]
     for g in bad_grids:
         assert _status(P, env, W.Grid(**g)) == P.PE3D_EINVAL, g

@@ -5,6 +5,7 @@ mode <= 1e-12, complex64 mode <= 1e-5, both against the oracle on identical
 seeded inputs.  Integer-valued state (the step counter) and the batched vs
 plain and graph vs direct paths are compared bit for bit.
 """
+import dataclasses
 import math
 import os
 import sys
@@ -253,6 +254,66 @@ def test_batch_is_bitwise_equal_to_plain(torch, P, prec, use_graph):
     assert [m.step for m in ms] == steps
     for m in ms:
         m.close()
+
+
+# ---------------------------------------------------------------- N x 2D mode
+NX2D = [c for c in CASES if c[0] in ("wedge", "sector", "sector_1az", "min_periodic", "multi_tile", "sector_90")]
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C128, W.PREC_C64])
+@pytest.mark.parametrize("case", NX2D, ids=[c[0] for c in NX2D])
+def test_nx2d_matches_oracle(torch, P, case, prec):
+    """N x 2D mode (Y = 0): depth pass only.  A one-step call (the depth pass
+    reads and writes the caller's field in place), then the rest."""
+    name, env, gk, f, steps = case
+    grid = W.Grid(precision=prec, mode=W.MODE_NX2D, **gk)
+    st = O.setup(env, grid, f)
+    u0 = O.starter(st, 0.3 * env.zmax) + 0.3 * W.random_field(grid.ntheta, grid.nz, _seed(name))
+    say("nx2d", name, prec)
+    m = P.Pe3d(env, grid, f)
+    assert m.info().mode == W.MODE_NX2D
+    u = to_dev(torch, u0, prec)
+    m.march(1, u)
+    m.march(steps - 1, u)
+    torch.cuda.synchronize()
+    ref = O.march(st, u0, 0, steps)
+    assert O.rel_l2(to_host(torch, u), ref) < TOL[prec], name
+    m.close()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_batch_mixing_nx2d_and_3d(torch, P, prec):
+    """A batch holding both modes equals the plain marches bit for bit, and its
+    N x 2D problems match the oracle."""
+    probs = _batch_problems(prec)
+    modes = [W.MODE_NX2D, W.MODE_3D, W.MODE_NX2D, W.MODE_3D, W.MODE_NX2D][:len(probs)]
+    probs = [(env, dataclasses.replace(g, mode=md), f) for (env, g, f), md in zip(probs, modes)]
+    steps = [6, 3, 1, 4, 5][:len(probs)]
+    u0s = []
+    for env, grid, f in probs:
+        st = O.setup(env, grid, f)
+        u0s.append(O.starter(st, 60.0) * (1 + 0.2 * np.sin(st.theta))[:, None])
+    say("batch nx2d/3d", prec)
+    plain = []
+    for (env, grid, f), u0, n in zip(probs, u0s, steps):
+        m = P.Pe3d(env, grid, f)
+        u = to_dev(torch, u0, prec)
+        m.march(n, u)
+        plain.append(u)
+        m.close()
+    for use_graph in (False, True):
+        ms = [P.Pe3d(env, grid, f) for env, grid, f in probs]
+        us = [to_dev(torch, u0, prec) for u0 in u0s]
+        P.march_batch(ms, steps, us, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(plain, us)):
+            assert torch.equal(a, b), f"problem {i} graph={use_graph}"
+        for m in ms:
+            m.close()
+    for i, ((env, grid, f), u0, n) in enumerate(zip(probs, u0s, steps)):
+        if grid.mode == W.MODE_NX2D:
+            ref = O.march(O.setup(env, grid, f), u0, 0, n)
+            assert O.rel_l2(to_host(torch, plain[i]), ref) < TOL[prec], f"problem {i}"
 
 
 def test_graph_replays_match_direct_calls(torch, P):

@@ -162,6 +162,39 @@ def test_closed_form_modal_march(floor, c, att):
     assert O.rel_l2(u, ref) < 1e-12
 
 
+@pytest.mark.parametrize("width", [W.TWO_PI, 1.0])
+def test_nx2d_closed_form_per_azimuth(width):
+    """N x 2D mode (Y = 0, Sec. 1): every azimuth column follows the 2D
+    Crank-Nicolson march alone, G_k^j per depth mode, whatever its
+    neighbours hold; and the 3D march of the same field differs."""
+    env = W.isovelocity_env(depth=200.0, c=1510.0, atten=0.1, floor=W.FLOOR_RIGID)
+    kw = dict(nz=48, ntheta=10, theta0=0.2, width=width, dr=5.0, r0=40.0, precision=W.PREC_C128)
+    st = O.setup(env, W.Grid(mode=W.MODE_NX2D, **kw), 25.0)
+    assert st.s(0) == 0.0
+    u0 = O.starter(st, 50.0) * (1.0 + np.arange(10)[:, None]) + 0.3j * W.random_field(10, 48, seed=9)
+    u = O.march(st, u0, 0, 60)
+    assert O.rel_l2(u, _modal_march(st, u0, 60, W.FLOOR_RIGID, coupled=False)) < 1e-12
+    # a column evolves alone: zeroing the others changes nothing in it
+    v0 = np.zeros_like(u0)
+    v0[4] = u0[4]
+    v = O.march(st, v0, 0, 60)
+    assert np.array_equal(v[4], u[4]) and not v[3].any()
+    u3 = O.march(O.setup(env, W.Grid(**kw), 25.0), u0, 0, 60)
+    assert O.rel_l2(u3, u) > 1e-4
+
+
+def test_nx2d_equals_3d_for_azimuth_uniform_field():
+    """Periodic grid, azimuth-independent medium and field: D_theta u = 0 at
+    every step, so the coupled march reduces to the N x 2D one."""
+    env = W.isovelocity_env(depth=120.0, c=1480.0, floor=W.FLOOR_PRESSURE_RELEASE)
+    kw = dict(nz=40, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=4.0, precision=W.PREC_C128)
+    s3 = O.setup(env, W.Grid(**kw), 30.0)
+    s2 = O.setup(env, W.Grid(mode=W.MODE_NX2D, **kw), 30.0)
+    u0 = np.repeat(O.starter(s3, 30.0)[:1], 8, axis=0)
+    u3, u2 = O.march(s3, u0, 0, 40), O.march(s2, u0, 0, 40)
+    assert O.rel_l2(u3, u2) < 1e-13
+
+
 def test_closed_form_nonzero_start_range():
     env = W.isovelocity_env(depth=150.0, c=1490.0, floor=W.FLOOR_PRESSURE_RELEASE)
     grid = W.Grid(nz=20, ntheta=12, theta0=0.3, width=W.TWO_PI, dr=7.0, r0=350.0)

@@ -25,6 +25,9 @@ FLOOR_PRESSURE_RELEASE = 0
 FLOOR_RIGID = 1
 PREC_C64 = 0
 PREC_C128 = 1
+#: coupling between azimuths: full 3D (Eq. (4)) or N x 2D (Y = 0, Sec. 1)
+MODE_3D = 0
+MODE_NX2D = 1
 TWO_PI = 2.0 * math.pi
 
 
@@ -56,7 +59,8 @@ class Env:
 class Grid:
     """Computational grid.  width == 2*pi means the full circle (periodic in
     azimuth); a smaller width is a sector centred on theta0 with zero field on
-    the two edge azimuths.  The march starts at range r0."""
+    the two edge azimuths.  The march starts at range r0.  mode MODE_NX2D
+    drops the azimuth operator (Y = 0): N independent 2D marches."""
     nz: int
     ntheta: int
     theta0: float
@@ -64,6 +68,7 @@ class Grid:
     dr: float
     r0: float = 0.0
     precision: int = PREC_C64
+    mode: int = MODE_3D
 
 
 @dataclass(frozen=True)
