@@ -18,6 +18,7 @@ throughput on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -57,6 +58,8 @@ def parse():
     ap.add_argument("--precision-study", action="store_true",
                     help="also march config 2 to 5000 steps in complex64 and complex128 and compare "
                          "with the stored oracle samples every 500 steps")
+    ap.add_argument("--nx2d-report", action="store_true",
+                    help="also compare the N x 2D (Y = 0) mode with the 3D march on the config-2 wedge")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-range-scale", type=float, default=0.25)
     return ap.parse_args()
@@ -278,6 +281,8 @@ def main():
             f"{rep['throughput_pt_steps_per_s']:.3e} pt*steps/s")
     if args.precision_study:
         out["precision_study"] = precision_study(P)
+    if args.nx2d_report:
+        out["nx2d_report"] = nx2d_report(P)
     print(json.dumps(out), flush=True)
 
 
@@ -319,6 +324,53 @@ def precision_study(P):
         res[name] = dict(rel_l2=rel, tl_rms_db=tl_rms, tl_max_db=tl_max,
                          seconds=round(time.perf_counter() - t0, 3))
         log(f"precision {name}: rel L2 {['%.2e' % x for x in rel]}")
+        m.close()
+    return res
+
+
+def nx2d_report(P, nsteps=2000, every=500):
+    """The config-2 wedge (Nz 2048, Ntheta 512, 100 Hz, complex64) marched
+    nsteps in the full 3D mode and in the N x 2D mode (Y = 0) from the same
+    starter: GPU time per step of each (plain march, HIP events), and at every
+    `every` steps the TL difference 20 log10(|u_2d| / |u_3d|) in dB (RMS, max
+    and the fraction of nodes beyond 3 dB) over the nodes within 60 dB of the
+    3D field's peak, the 3D field taken as the reference."""
+    import torch
+    base = W.config2(nsteps=nsteps, precision=W.PREC_C64)
+    res = dict(workload=f"config2 wedge, {nsteps} steps ({nsteps * base.grid.dr / 1000:.0f} km), complex64",
+               checkpoints=list(range(every, nsteps + 1, every)))
+    ms, us = {}, {}
+    for name, mode in (("3d", W.MODE_3D), ("nx2d", W.MODE_NX2D)):
+        g = dataclasses.replace(base.grid, mode=mode)
+        ms[name] = P.Pe3d(base.env, g, base.f_hz)
+        us[name] = ms[name].starter(base.zs)
+    for name in ms:  # warm-up (module load, first launches), then rewind
+        v = us[name].clone()
+        ms[name].march(5, v)
+        ms[name].set_step(0)
+    torch.cuda.synchronize()
+    ms_per_step = {k: 0.0 for k in ms}
+    rms, mx, frac3 = [], [], []
+    for j in range(0, nsteps, every):
+        for name in ms:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ms[name].march(every, us[name])
+            e1.record()
+            torch.cuda.synchronize()
+            ms_per_step[name] += e0.elapsed_time(e1) / nsteps
+        a3 = us["3d"].abs().double().cpu().numpy()
+        a2 = us["nx2d"].abs().double().cpu().numpy()
+        keep = a3 >= 1e-3 * a3.max()
+        d = 20.0 * np.log10(np.maximum(a2[keep], 1e-300) / a3[keep])
+        rms.append(float(np.sqrt(np.mean(d * d))))
+        mx.append(float(np.abs(d).max()))
+        frac3.append(float(np.mean(np.abs(d) > 3.0)))
+    res.update(ms_per_step={k: round(v, 5) for k, v in ms_per_step.items()},
+               speedup_nx2d=round(ms_per_step["3d"] / ms_per_step["nx2d"], 3),
+               tl_diff_rms_db=rms, tl_diff_max_db=mx, frac_beyond_3db=frac3)
+    log(f"nx2d vs 3d: {ms_per_step}, TL diff RMS {['%.2f' % x for x in rms]} dB")
+    for m in ms.values():
         m.close()
     return res
 
