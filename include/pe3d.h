@@ -75,6 +75,14 @@ typedef enum { PE3D_MODE_3D = 0, PE3D_MODE_NX2D = 1 } pe3d_mode;
  * fluid half-space (c_b, rho_b, atten_b).  zmax is the computational floor
  * with boundary condition `floor`.  The surface is pressure release.
  * Index of refraction n^2 = (c0/c)^2 (1 + i*eta*atten)^2, eta = 1/(40 pi log10 e).
+ * Range-dependent depth D(r, theta) (the per-step matrix update of Fig. 2):
+ * n_bathy_r >= 2 rows at ranges bathy_r0 + i*bathy_dr (bathy_dr > 0), and
+ * bathy_depth then holds n_bathy_r rows of n_bathy samples (row-major), each
+ * row periodic piecewise linear in theta as above; D is linear in r between
+ * rows (the usual interpolation formula, correctly rounded FP64, no fused
+ * multiply-add) and constant before the first and after the last row.  The
+ * step j -> j+1 uses the medium at r_{j+1} on both sides of Eq. (4).
+ * n_bathy_r == 0 or 1: range independent, bathy_depth holds n_bathy samples.
  * The arrays are copied by pe3d_create; the caller may free them after. */
 typedef struct {
   double c0;                  /* reference sound speed, k0 = 2 pi f / c0   */
@@ -86,6 +94,8 @@ typedef struct {
   int32_t n_bathy;
   const double* bathy_theta;
   const double* bathy_depth;
+  int32_t n_bathy_r;          /* range rows of bathy_depth (0 or 1: none) */
+  double bathy_r0, bathy_dr;  /* range of the first row, row spacing      */
   double zmax;
   int32_t floor;              /* pe3d_floor */
 } pe3d_env;
@@ -112,16 +122,20 @@ typedef struct { double f_hz; } pe3d_freq;
 /* Build a march for one frequency (the set-up of Fig. 2): validates all
  * arguments before touching the device, builds the medium and the depth
  * operator in FP64 on the host, factors the depth system [1 + (1/4 - d/4) X]
- * once (the medium depends on (theta, z) only, so it is range invariant),
- * and allocates the handle's device buffers (coefficient tables and one
- * scratch field).  The range counter starts at step j = 0 (range r0).
+ * once, and allocates the handle's device buffers (coefficient tables and one
+ * scratch field).  Every column is the all-water column above its interface
+ * and the all-bottom column below it, so the factorisation is two shared
+ * pivot chains plus one 2x2 interface block per number of water nodes; with
+ * a range-dependent depth the depth kernel finds each column's water nodes
+ * at r_{j+1} every step, which is the exact factorisation of that step's
+ * matrix.  The range counter starts at step j = 0 (range r0).
  * Limits of the built kernels: nz <= 4096 in both precisions,
  * ntheta <= 1024; nz >= 2; ntheta >= 3 (periodic) or >= 1 (sector).
  * Precision: in both modes every coefficient and every arithmetic operation
  * is FP64; PE3D_C64 stores the field (and values held between sweeps) in
  * complex64.  Errors: PE3D_EINVAL (null pointer, non-finite or non-positive
  * f, c0, dr, zmax, speeds or densities, negative attenuation, r0 < 0,
- * unordered samples, unknown enum), PE3D_EUNSUPPORTED
+ * unordered samples, unknown enum, n_bathy_r < 0, non-positive bathy_dr), PE3D_EUNSUPPORTED
  * (outside the limits, or a depth pivot smaller than 1e-10 of the largest
  * diagonal), PE3D_ENOMEM, PE3D_EDEVICE.  On error *out is set to NULL. */
 pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,

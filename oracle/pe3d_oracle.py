@@ -98,17 +98,37 @@ class Setup:
             self.theta = grid.theta0 - 0.5 * grid.width + self.dth * np.arange(1, nth + 1)
         self.dr = float(grid.dr)
         self.r0 = float(grid.r0)
-        # medium (readings A7, A8, A9): water iff z_l <= D(theta_m)
-        depth = interp_bathy(self.theta, env.bathy_theta, env.bathy_depth)
+        # water depth per azimuth column: D(theta_m), or with range nodes
+        # (reading A22) D(r_i, theta_m) at r_i = bathy_r0 + i bathy_dr, each
+        # row periodic piecewise linear in theta, linear in r between rows and
+        # constant beyond the first and last row
+        nr = int(getattr(env, "bathy_nr", 0))
+        self.range_dependent = nr >= 2
+        nb = len(env.bathy_theta)
+        if self.range_dependent:
+            rows = np.asarray(env.bathy_depth, dtype=np.float64).reshape(nr, nb)
+            self.bathy_r = env.bathy_r0 + env.bathy_dr * np.arange(nr, dtype=np.float64)
+            self.dcol = np.stack([interp_bathy(self.theta, env.bathy_theta, rows[i])
+                                  for i in range(nr)], axis=1)          # (Ntheta, nr)
+        # the medium at r_0 (the only one when the depth has no range rows)
+        self.water, self.rho, self.q, self.xl, self.xd, self.xu = self.medium(self.depth_at(self.r0))
+        self._xcache = {}
+        # Eq. (4): delta = i k0 dr; 1 + (1/4 +- delta/4) X = I + beta_pm X
+        self.beta_p = (1.0 + 1j * self.k0 * self.dr) / 4.0
+        self.beta_m = (1.0 - 1j * self.k0 * self.dr) / 4.0
+
+    def medium(self, depth: np.ndarray):
+        """Medium and depth operator for water depths D_m of the columns
+        (readings A7, A8, A9): water iff z_l <= D_m.  Returns water, rho,
+        q = n^2 - 1 and the diagonals xl, xd, xu of X, each (Ntheta, Nz)."""
+        env = self.env
         water = self.z[None, :] <= depth[:, None]
         cw = interp_ssp(self.z, env.ssp_z, env.ssp_c)
         c = np.where(water, cw[None, :], env.c_b)
         rho = np.where(water, env.rho_w, env.rho_b).astype(np.float64)
         att = np.where(water, env.atten_w, env.atten_b)
         n2 = (env.c0 / c) ** 2 * (1.0 + 1j * ETA * att) ** 2
-        self.water = water
-        self.rho = rho
-        self.q = n2 - 1.0
+        q = n2 - 1.0
         # density weights with ghost densities rho_0 = rho_1, rho_{Nz+1} = rho_Nz
         rpad = np.concatenate([rho[:, :1], rho, rho[:, -1:]], axis=1)
         lm = 2.0 * rpad[:, 1:-1] / (rpad[:, :-2] + rpad[:, 1:-1])
@@ -117,15 +137,32 @@ class Setup:
         h = self.h
         xl = (h * lm).astype(np.complex128)
         xu = (h * lp).astype(np.complex128)
-        xd = self.q - h * (lm + lp)
+        xd = q - h * (lm + lp)
         xl[:, 0] = 0.0                      # surface: u_0 = 0
         if env.floor == FLOOR_RIGID:        # u_{Nz+1} = u_{Nz-1}
             xl[:, -1] = xl[:, -1] + xu[:, -1]
         xu[:, -1] = 0.0
-        self.xl, self.xd, self.xu = xl, xd, xu
-        # Eq. (4): delta = i k0 dr; 1 + (1/4 +- delta/4) X = I + beta_pm X
-        self.beta_p = (1.0 + 1j * self.k0 * self.dr) / 4.0
-        self.beta_m = (1.0 - 1j * self.k0 * self.dr) / 4.0
+        return water, rho, q, xl, xd, xu
+
+    def depth_at(self, r: float) -> np.ndarray:
+        """Water depth of every column at range r (reading A22): linear
+        interpolation between the range rows (the library routine), constant
+        beyond the first and last row; D(theta_m) when there are no rows."""
+        if not self.range_dependent:
+            return interp_bathy(self.theta, self.env.bathy_theta, self.env.bathy_depth)
+        return np.array([np.interp(r, self.bathy_r, self.dcol[m]) for m in range(self.nth)])
+
+    def x_at(self, j: int):
+        """Diagonals (xl, xd, xu) of X for the step j -> j+1: the medium at
+        r_{j+1} on both sides of Eq. (4) (reading A3: Fig. 2 advances r, then
+        updates both matrices)."""
+        if not self.range_dependent:
+            return self.xl, self.xd, self.xu
+        if j not in self._xcache:
+            if len(self._xcache) > 64:
+                self._xcache.clear()
+            self._xcache[j] = self.medium(self.depth_at(self.r(j + 1)))[3:]
+        return self._xcache[j]
 
     def r(self, j: int) -> float:
         """Range of step j: r_j = r0 + j dr (Fig. 2: r starts at 0 and grows
@@ -229,9 +266,11 @@ def y_apply(st: Setup, u: np.ndarray, s: complex, sign: float = 1.0) -> np.ndarr
     return u + sign * s * d_theta(st, u)
 
 
-def x_apply(st: Setup, w: np.ndarray, beta: complex) -> np.ndarray:
-    """(I + beta X) w, X applied down every azimuth column (Eq. (4))."""
-    return w + beta * apply_tridiag(st.xl, st.xd, st.xu, w)
+def x_apply(st: Setup, w: np.ndarray, beta: complex, x=None) -> np.ndarray:
+    """(I + beta X) w, X applied down every azimuth column (Eq. (4)); X is
+    the medium's at r_0 unless the diagonals x = (xl, xd, xu) are given."""
+    xl, xd, xu = (st.xl, st.xd, st.xu) if x is None else x
+    return w + beta * apply_tridiag(xl, xd, xu, w)
 
 
 def step(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
@@ -241,9 +280,10 @@ def step(st: Setup, u: np.ndarray, j: int) -> np.ndarray:
       [I + beta_- X] v = RHS                         (Eq. (5)/(7), per azimuth)
       [I - s_j D] u^{j+1} = v                        (Eq. (6)/(8), per depth)"""
     s = st.s(j)
+    xl, xd, xu = st.x_at(j)
     w = y_apply(st, u, s, +1.0)
-    rhs = x_apply(st, w, st.beta_p)
-    v = thomas(st.beta_m * st.xl, 1.0 + st.beta_m * st.xd, st.beta_m * st.xu, rhs)
+    rhs = x_apply(st, w, st.beta_p, (xl, xd, xu))
+    v = thomas(st.beta_m * xl, 1.0 + st.beta_m * xd, st.beta_m * xu, rhs)
     if st.nx2d:
         return v                     # [I - 0 D] u^{j+1} = v
     # azimuth systems: one per depth, unknowns along theta -> move theta last

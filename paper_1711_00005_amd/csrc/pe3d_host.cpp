@@ -55,10 +55,15 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
       !is_fin(e->atten_b) || e->atten_b < 0.0)
     return PE3D_EINVAL;
   if (e->n_bathy < 1 || !e->bathy_theta || !e->bathy_depth) return PE3D_EINVAL;
+  if (e->n_bathy_r < 0 || e->n_bathy_r > 1000000) return PE3D_EINVAL;
+  if (e->n_bathy_r >= 2 && (!is_fin(e->bathy_r0) || !is_fin(e->bathy_dr) || e->bathy_dr <= 0.0))
+    return PE3D_EINVAL;
   for (int i = 0; i < e->n_bathy; ++i) {
-    if (!is_fin(e->bathy_theta[i]) || !is_fin(e->bathy_depth[i])) return PE3D_EINVAL;
+    if (!is_fin(e->bathy_theta[i])) return PE3D_EINVAL;
     if (i > 0 && !(e->bathy_theta[i] > e->bathy_theta[i - 1])) return PE3D_EINVAL;
   }
+  for (long long i = 0; i < (long long)e->n_bathy * std::max(e->n_bathy_r, 1); ++i)
+    if (!is_fin(e->bathy_depth[i])) return PE3D_EINVAL;
   if (e->n_bathy > 1 && !(e->bathy_theta[e->n_bathy - 1] - e->bathy_theta[0] < 2.0 * kPi))
     return PE3D_EINVAL;
   if (!is_fin(e->zmax) || e->zmax <= 0.0) return PE3D_EINVAL;
@@ -91,9 +96,10 @@ double interp_ssp(const pe3d_env& e, double z) {
   return slope * (z - e.ssp_z[lo]) + e.ssp_c[lo];
 }
 
-double interp_bathy(const pe3d_env& e, double th) {
+// D(theta) of one depth row dep[0..n_bathy-1]
+double interp_bathy(const pe3d_env& e, const double* dep, double th) {
   const int n = e.n_bathy;
-  if (n == 1) return e.bathy_depth[0];
+  if (n == 1) return dep[0];
   const double t0 = e.bathy_theta[0];
   double md = std::fmod(th - t0, 2.0 * kPi);
   if (md < 0.0) md += 2.0 * kPi;
@@ -103,14 +109,41 @@ double interp_bathy(const pe3d_env& e, double th) {
     double a = e.bathy_theta[i];
     double b = (i + 1 < n) ? e.bathy_theta[i + 1] : t0 + 2.0 * kPi;
     if (t >= a && t < b) {
-      double da = e.bathy_depth[i];
-      double db = (i + 1 < n) ? e.bathy_depth[i + 1] : e.bathy_depth[0];
+      double da = dep[i];
+      double db = (i + 1 < n) ? dep[i + 1] : dep[0];
       if (t == a) return da;
       double slope = (db - da) / (b - a);
       return slope * (t - a) + da;
     }
   }
-  return e.bathy_depth[0];
+  return dep[0];
+}
+
+// D at range r from a column's depths dc[i] at ranges r_i = r0b + i*drb
+// (i < nr, nr >= 2): the interval [r_i, r_{i+1}) holding r, the depth at an
+// exact node, slope * (r - r_i) + dc[i] inside, the end values outside.  The
+// depth kernel evaluates the same operations (no fused multiply-add), so
+// both sides count the same water nodes.
+double depth_in_range(const double* dc, int nr, double r0b, double drb, double r) {
+  auto node = [&](int i) { return r0b + double(i) * drb; };
+  if (r <= node(0)) return dc[0];
+  if (r >= node(nr - 1)) return dc[nr - 1];
+  int i = 0, hi = nr - 1;  // node(i) < r < node(hi)
+  while (hi - i > 1) {
+    const int mid = (i + hi) / 2;
+    if (node(mid) <= r) i = mid; else hi = mid;
+  }
+  const double ra = node(i);
+  if (r == ra) return dc[i];
+  const double slope = (dc[i + 1] - dc[i]) / (node(i + 1) - ra);
+  return slope * (r - ra) + dc[i];
+}
+
+// water nodes of a column of depth D: #{l = 1..N : l dz <= D}
+int water_count(double D, double dz, int N) {
+  int nw = 0;
+  while (nw < N && double(nw + 1) * dz <= D) ++nw;
+  return nw;
 }
 
 // FP64 problem description built on the host
@@ -121,8 +154,11 @@ struct Built {
   cd cbs;  // beta_+ h / (-beta_- h): off-diagonal of the scaled depth RHS
   std::vector<cd> qw, pw, pb;
   std::vector<cd> tabG, tabC, tabP;  // depth-kernel chain tables and lane products
-  std::vector<int> k;
-  std::vector<std::array<cd, 12>> rec;  // interface rows of each column
+  std::vector<int> nw, k;                // water nodes and interface row of each column at r0
+  std::vector<std::array<cd, 12>> rec;  // interface rows by water count nw = 0..N
+  std::vector<double> dcol;             // [NT][nbr] column depths at the range rows
+  int nbr = 0;                          // range rows (0: range independent)
+  double br0 = 0, bdr = 0;
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
   int wb = 0, nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
 };
@@ -237,21 +273,48 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
       b.pb[l] = 1.0 / eb[l];
     }
   }
-  // per-column interface rows
+  // water nodes of every column: at r0 (the only depth when it has no range
+  // rows); with range rows the column's depths at the row ranges, from which
+  // the depth kernel finds the water nodes at r_{j+1} every step
+  b.nbr = e.n_bathy_r >= 2 ? e.n_bathy_r : 0;
+  b.br0 = e.bathy_r0;
+  b.bdr = e.bathy_dr;
+  b.nw.resize(NT);
   b.k.resize(NT);
-  b.rec.resize(NT);
-  double maxb = 0.0, minpiv = 1e300;
-  int kmin = N, kmax = 0;
-  const cd bp = b.bp;
+  if (b.nbr) b.dcol.assign((size_t)NT * b.nbr, 0.0);
+  int nwlo = N, nwhi = 0;
   for (int m = 0; m < NT; ++m) {
     double th = b.periodic ? g.theta0 + m * b.dth : g.theta0 - 0.5 * g.width + (m + 1) * b.dth;
-    double D = interp_bathy(e, th);
-    int nw = 0;
-    while (nw < N && (nw + 1) * b.dz <= D) ++nw;  // z_l = (l+1) dz <= D
-    int k = std::min(std::max(nw - 1, 0), N - 2);
-    b.k[m] = k;
-    kmin = std::min(kmin, k);
-    kmax = std::max(kmax, k);
+    double D;
+    if (b.nbr) {
+      double* dc = b.dcol.data() + (size_t)m * b.nbr;
+      for (int i = 0; i < b.nbr; ++i) {
+        dc[i] = interp_bathy(e, e.bathy_depth + (size_t)i * e.n_bathy, th);
+        // interpolated depths lie between row values: their water counts bound
+        // every count the march meets (widened by one for rounding)
+        const int c = water_count(dc[i], b.dz, N);
+        nwlo = std::min(nwlo, std::max(c - 1, 0));
+        nwhi = std::max(nwhi, std::min(c + 1, N));
+      }
+      D = depth_in_range(dc, b.nbr, b.br0, b.bdr, g.r0);
+    } else {
+      D = interp_bathy(e, e.bathy_depth, th);
+    }
+    const int nw = water_count(D, b.dz, N);
+    b.nw[m] = nw;
+    b.k[m] = std::min(std::max(nw - 1, 0), N - 2);
+    nwlo = std::min(nwlo, nw);
+    nwhi = std::max(nwhi, nw);
+  }
+  // interface record for every water count nw = 0..N (interface row
+  // k = clamp(nw - 1, 0, N - 2)); the pivot check covers the counts met
+  b.rec.assign(N + 1, {});
+  double maxb = 0.0, minpiv = 1e300;
+  const int kmin = std::min(std::max(nwlo - 1, 0), N - 2), kmax = std::min(std::max(nwhi - 1, 0), N - 2);
+  const cd bp = b.bp;
+  for (int nw = 0; nw <= N; ++nw) {
+    const int k = std::min(std::max(nw - 1, 0), N - 2);
+    const bool used = nw >= nwlo && nw <= nwhi;
     // the column's own X rows k-1..k+2 from the density-weighted operator
     auto rho_at = [&](int l) {
       l = std::min(std::max(l, 0), N - 1);  // ghost densities
@@ -289,9 +352,13 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     }
     cd c01 = bm * xu0, c10 = bm * xl1;
     cd det = P * Q - c01 * c10;
-    maxb = std::max({maxb, std::abs(P), std::abs(Q)});
-    minpiv = std::min(minpiv, std::abs(det) / std::max(std::abs(P), std::abs(Q)));
-    if (det == 0.0 || !std::isfinite(std::abs(det))) return PE3D_EUNSUPPORTED;
+    if (!used) {
+      if (det == 0.0 || !std::isfinite(std::abs(det))) continue;  // never read
+    } else {
+      maxb = std::max({maxb, std::abs(P), std::abs(Q)});
+      minpiv = std::min(minpiv, std::abs(det) / std::max(std::abs(P), std::abs(Q)));
+      if (det == 0.0 || !std::isfinite(std::abs(det))) return PE3D_EUNSUPPORTED;
+    }
     cd id = 1.0 / det;
     // row k (top chain: previous row k-1, next row k+1), then row k+1
     // (bottom chain, reversed: previous row k+2, next row k).  The kernel
@@ -299,7 +366,7 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     // the RHS and elimination coefficients are divided by nbmh and the
     // inverse entries multiplied by it.
     const cd nb = -bm * h, inb = 1.0 / nb;
-    b.rec[m] = {(1.0 + bp * xd0) * inb, bp * xl0 * inb, bp * xu0 * inb, cft * inb, Q * id * nb, -c01 * id * nb,
+    b.rec[nw] = {(1.0 + bp * xd0) * inb, bp * xl0 * inb, bp * xu0 * inb, cft * inb, Q * id * nb, -c01 * id * nb,
                 (1.0 + bp * xd1) * inb, bp * xu1 * inb, bp * xl1 * inb, cfb * inb, P * id * nb, -c10 * id * nb};
   }
   // pivots actually used: water rows < kmax, bottom rows > kmin + 1
@@ -361,8 +428,9 @@ size_t table_bytes(const Built& b) {
   size_t n = 0;
   n += 2 * 2 * (size_t)b.ma * b.lt * csz;        // tabG, tabC
   n += 2 * (size_t)(b.ma + 1) * b.lpc * csz;    // tabP
-  n += (size_t)b.NT * 12 * csz;                 // rec
-  n += (size_t)b.NT * sizeof(int);              // kcol
+  n += (size_t)(b.N + 1) * 12 * csz;            // rec, by water count
+  n += (size_t)b.NT * b.nbr * sizeof(double);   // dcol (range rows only)
+  n += (size_t)b.NT * sizeof(int);              // nwcol
   n = (n + 255) & ~size_t(255);
   n += 256;                                     // step counter
   return n;
@@ -416,7 +484,7 @@ struct BatchPlan {
     std::vector<int> nitems_at;        // active items at step k (problems sorted by steps)
     std::vector<double> bytes_prefix;  // algorithmic bytes of the first i items
   };
-  std::vector<Class> a, b;
+  std::vector<Class> a, b, u;          // depth pass, azimuth pass, depth update
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   ~BatchPlan() {
@@ -542,6 +610,7 @@ pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3
   b.N = grid->nz;
   b.NT = grid->ntheta;
   b.prec = grid->precision;
+  b.nbr = env->n_bathy_r >= 2 ? env->n_bathy_r : 0;
   st = choose_shapes(b);
   if (st != PE3D_OK) return st;
   *bytes = table_bytes(b) + field_bytes(b);
@@ -567,8 +636,8 @@ pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const p
   for (int m = 0; m < b.NT; ++m) {
     kcol[m] = b.k[m];
     for (int q = 0; q < 12; ++q) {
-      blk[24 * m + 2 * q] = b.rec[m][q].real();
-      blk[24 * m + 2 * q + 1] = b.rec[m][q].imag();
+      blk[24 * m + 2 * q] = b.rec[b.nw[m]][q].real();
+      blk[24 * m + 2 * q + 1] = b.rec[b.nw[m]][q].imag();
     }
   }
   return PE3D_OK;
@@ -590,17 +659,19 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   std::vector<unsigned char> img(tb, 0);
   const size_t o_G = 0, o_C = o_G + b.tabG.size() * csz, o_P = o_C + b.tabC.size() * csz;
   const size_t o_rec = o_P + b.tabP.size() * csz;
-  const size_t o_k = o_rec + (size_t)b.NT * 12 * csz;
+  const size_t o_dc = o_rec + (size_t)(b.N + 1) * 12 * csz;
+  const size_t o_k = o_dc + b.dcol.size() * sizeof(double);
   const size_t o_j = tb - 256;
   std::vector<cd> recflat;
-  recflat.reserve((size_t)b.NT * 12);
+  recflat.reserve((size_t)(b.N + 1) * 12);
   for (auto& a : b.rec)
     for (auto& z : a) recflat.push_back(z);
   pack<double>(b.tabG, img, o_G);
   pack<double>(b.tabC, img, o_C);
   pack<double>(b.tabP, img, o_P);
   pack<double>(recflat, img, o_rec);
-  std::memcpy(img.data() + o_k, b.k.data(), b.NT * sizeof(int));
+  if (!b.dcol.empty()) std::memcpy(img.data() + o_dc, b.dcol.data(), b.dcol.size() * sizeof(double));
+  std::memcpy(img.data() + o_k, b.nw.data(), b.NT * sizeof(int));
 
   pe3d_handle h = new (std::nothrow) pe3d_handle_s();
   if (!h) return PE3D_ENOMEM;
@@ -651,7 +722,11 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.tabC = base + o_C;
   d.tabP = base + o_P;
   d.rec = base + o_rec;
-  d.kcol = reinterpret_cast<const int*>(base + o_k);
+  d.nwcol = reinterpret_cast<int*>(base + o_k);
+  d.dcol = b.nbr ? reinterpret_cast<const double*>(base + o_dc) : nullptr;
+  d.nbr = b.nbr;
+  d.br0 = b.br0;
+  d.bdr = b.bdr;
   d.h = b.h;
   d.qb_re = b.qb.real();
   d.qb_im = b.qb.imag();
@@ -734,6 +809,7 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   d.nsteps = nsteps;
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
+    if (d.nbr && launch_depth_update(&d, nullptr, nullptr, 0, k, st) != hipSuccess) return PE3D_EDEVICE;
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
           return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
         }) != hipSuccess)
@@ -799,9 +875,9 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::vector<ProbDesc> descs(np);
   std::vector<long long*> jdevs(np);
   std::vector<int> adds(np);
-  std::map<int, std::vector<WorkItem>> ia, ib;
-  std::map<int, std::vector<int>> ia_steps, ib_steps;  // steps of the problem of each item
-  std::map<int, std::vector<double>> ia_bytes, ib_bytes;
+  std::map<int, std::vector<WorkItem>> ia, ib, iu;
+  std::map<int, std::vector<int>> ia_steps, ib_steps, iu_steps;  // steps of the problem of each item
+  std::map<int, std::vector<double>> ia_bytes, ib_bytes, iu_bytes;
   std::map<int, int> ia_lds, ib_lds;
   for (int p = 0; p < np; ++p) {
     pe3d_handle h = hs[order[p]];
@@ -822,6 +898,13 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
       const int ncol = std::min(cpw, hd.nth - t * cpw);
       ia_bytes[kBatchClass].push_back(2.0 * esz * ncol * hd.nz);
     }
+    // problems with range rows: water nodes of 256 columns per item
+    if (hd.nbr)
+      for (int t = 0; t < (hd.nth + 255) / 256; ++t) {
+        iu[kBatchClass].push_back({p, t});
+        iu_steps[kBatchClass].push_back(nsteps[order[p]]);
+        iu_bytes[kBatchClass].push_back(0.0);
+      }
     // N x 2D problems have no azimuth pass: the items of the still-stepping
     // problems stay a prefix of the list, as the steps stay non-increasing
     if (hd.nx2d) continue;
@@ -836,6 +919,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   size_t nitems = 0;
   for (auto& kv : ia) nitems += kv.second.size();
   for (auto& kv : ib) nitems += kv.second.size();
+  for (auto& kv : iu) nitems += kv.second.size();
   size_t off_desc = 0;
   size_t off_j = (off_desc + np * sizeof(ProbDesc) + 255) & ~size_t(255);
   size_t off_add = (off_j + np * sizeof(long long*) + 255) & ~size_t(255);
@@ -876,12 +960,18 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   for (auto& c : P.a) c.lds = ia_lds[c.maxm];
   emit(ib, ib_steps, ib_bytes, P.b);
   for (auto& c : P.b) c.lds = ib_lds[c.maxm];
+  emit(iu, iu_steps, iu_bytes, P.u);
   if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
 }
 
 pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
   for (int k = 0; k < P.maxsteps; ++k) {
+    for (auto& c : P.u) {
+      int ni = c.nitems_at[k];
+      if (ni > 0 && launch_depth_update(nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+        return PE3D_EDEVICE;
+    }
     for (auto& c : P.a) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {

@@ -32,12 +32,17 @@ struct ProbDesc {
   const void* tabC;     // diagonal of [I + beta_+ X] of the chain row, divided by nbmh
   const void* tabP;     // [2][M+1][L]: product of tabG over a lane's M slots,
                         //   by (chain, leading zero slots sc, lane in chain)
-  const void* rec;      // [nth][12] interface rows of each column: for row k then
+  const void* rec;      // [nz+1][12] interface rows of a column with nw water nodes
+                        //   (interface row k = clamp(nw-1, 0, nz-2)): for row k then
                         //   row k+1: RHS diagonal, previous and next coefficient
                         //   along the chain, elimination multiplier (these four
                         //   divided by nbmh), and the two entries of the 2x2
                         //   block inverse that give its value (times nbmh)
-  const int* kcol;      // [nth] row k(m)
+  int* nwcol;           // [nth] water nodes of each column: fixed for a depth without
+                        //   range rows, else rewritten for r_{j+1} before every depth pass
+  const double* dcol;   // [nth][nbr] column depths at the range rows, or null
+  int nbr;              // range rows (0: the depth does not depend on range)
+  double br0, bdr;      // range of the first row, row spacing
   double h;             // (k0 dz)^-2
   double qb_re, qb_im;  // n^2-1 of the bottom half-space
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
@@ -75,6 +80,10 @@ int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pas
 hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                          int nitems, int koff, int lds, hipStream_t st);
 int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
+// water nodes at r_{j+1} of every column of problems with range rows (single:
+// one problem; else nitems items of 256 columns each)
+hipError_t launch_depth_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                               int nitems, int koff, hipStream_t st);
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n,
                           long long* jsingle, int add, hipStream_t st);
 hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipStream_t st);

@@ -159,6 +159,44 @@ __device__ __forceinline__ double sigma_of(const ProbDesc& d, long long j) {
   double r = d.r0 + double(j + 1) * d.dr;
   return d.dr / (4.0 * d.k0 * r * r * d.dth * d.dth);
 }
+// Water nodes of column m at range r_{j+1} when the depth has range rows
+// (the per-step matrix update of Fig. 2; depth_update writes them for the
+// depth pass): D(r) between the column's depths at
+// the rows r_i = br0 + i bdr (slope * (r - r_i) + D_i inside an interval, D_i
+// at a node, the end values outside), then #{l = 1..nz : l dz <= D}.  Every
+// operation is a correctly rounded FP64 one with no contraction, as on the
+// host and in a plain evaluation of the same formula, so the integer count is
+// the same everywhere.  Uniform across the column's lanes.
+__device__ __forceinline__ int water_nodes_at(const ProbDesc& d, int m, long long j) {
+  const double r = __dadd_rn(d.r0, __dmul_rn(double(j + 1), d.dr));
+  const double* dc = d.dcol + (size_t)m * d.nbr;
+  const int nr = d.nbr;
+  auto node = [&](int i) { return __dadd_rn(d.br0, __dmul_rn(double(i), d.bdr)); };
+  double D;
+  if (r <= node(0)) {
+    D = dc[0];
+  } else if (r >= node(nr - 1)) {
+    D = dc[nr - 1];
+  } else {
+    // the interval node(i) <= r < node(i+1): a first guess, then exact steps
+    int i = int(fmin(fmax(floor(__ddiv_rn(__dsub_rn(r, d.br0), d.bdr)), 0.0), double(nr - 2)));
+    while (i > 0 && node(i) > r) --i;
+    while (i < nr - 2 && node(i + 1) <= r) ++i;
+    const double ra = node(i);
+    if (r == ra) {
+      D = dc[i];
+    } else {
+      const double slope = __ddiv_rn(__dsub_rn(dc[i + 1], dc[i]), __dsub_rn(node(i + 1), ra));
+      D = __dadd_rn(__dmul_rn(slope, __dsub_rn(r, ra)), dc[i]);
+    }
+  }
+  const int N = d.nz;
+  int nw = int(fmin(fmax(floor(__ddiv_rn(D, d.dz)), 0.0), double(N)));
+  while (nw < N && __dmul_rn(double(nw + 1), d.dz) <= D) ++nw;
+  while (nw > 0 && __dmul_rn(double(nw), d.dz) > D) --nw;
+  return nw;
+}
+
 // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle, s = i sigma:
 // rho = 2s / (1 + 2s + sqrt(1 + 4s))
 __device__ __forceinline__ C<double> rho_of(double sigma) {
@@ -379,8 +417,11 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     }
   }
 
-  // ---- lane role
-  const int k = colok ? d.kcol[m] : 0;
+  // ---- lane role: the column's water nodes nw (at r_{j+1}, written by
+  //      depth_update before this launch, when the depth depends on range)
+  //      set its interface row k and record
+  const int nw = colok ? d.nwcol[m] : 0;
+  const int k = min(max(nw - 1, 0), N - 2);
   const int a = (k + 1) / M + 1;
   const int s = a * M - (k + 1);
   const int nbl = (N - k - 1) / M + 1;
@@ -419,7 +460,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   };
   // the head lanes' interface coefficients: RHS diagonal, previous and next
   // coefficient, elimination multiplier, then the two inverse entries
-  const D* hrec = ((const D*)d.rec) + (size_t)(colok ? m : 0) * 12 + (bot ? 6 : 0);
+  const D* hrec = ((const D*)d.rec) + (size_t)nw * 12 + (bot ? 6 : 0);
 
   const D cbs = mk<double>(d.cbs_re, d.cbs_im);
   D tp = zero<double>();
@@ -904,6 +945,21 @@ __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_batch(co
 }
 
 // ============================================================== small kernels
+// Water nodes of every column at r_{j+1}, j = the problem's step counter +
+// koff, for a problem whose depth has range rows: one thread per column,
+// launched before the depth pass of the step.
+__global__ void depth_update_single(ProbDesc d, int koff) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m < d.nth) d.nwcol[m] = water_nodes_at(d, m, *d.jdev + koff);
+}
+__global__ void depth_update_batch(const ProbDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                   int koff) {
+  const WorkItem it = items[blockIdx.x];
+  const ProbDesc& d = descs[it.prob];
+  const int m = it.tile * 256 + threadIdx.x;
+  if (m < d.nth) d.nwcol[m] = water_nodes_at(d, m, *d.jdev + koff);
+}
+
 __global__ void advance_kernel(long long* const* jdevs, const int* adds, int n, long long* js,
                                int add1) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1063,6 +1119,15 @@ hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_des
   if (single) return prec == 0 ? run_b_cls<float>(*single, koff, lds, st) : run_b_cls<double>(*single, koff, lds, st);
   return prec == 0 ? run_b_batch<float>(d_descs, items, nitems, koff, lds, st)
                    : run_b_batch<double>(d_descs, items, nitems, koff, lds, st);
+}
+
+hipError_t launch_depth_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+                               int nitems, int koff, hipStream_t st) {
+  if (single)
+    hipLaunchKernelGGL(depth_update_single, dim3((single->nth + 255) / 256), dim3(256), 0, st, *single, koff);
+  else
+    hipLaunchKernelGGL(depth_update_batch, dim3(nitems), dim3(256), 0, st, d_descs, items, koff);
+  return hipGetLastError();
 }
 
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n, long long* jsingle,

@@ -49,6 +49,7 @@ class pe3d_env(ct.Structure):
                 ("c_b", ct.c_double), ("rho_b", ct.c_double), ("atten_b", ct.c_double),
                 ("n_bathy", ct.c_int32),
                 ("bathy_theta", ct.POINTER(ct.c_double)), ("bathy_depth", ct.POINTER(ct.c_double)),
+                ("n_bathy_r", ct.c_int32), ("bathy_r0", ct.c_double), ("bathy_dr", ct.c_double),
                 ("zmax", ct.c_double), ("floor", ct.c_int32)]
 
 
@@ -128,7 +129,9 @@ def make_env(env):
     s = pe3d_env(c0=env.c0, n_ssp=len(env.ssp_z), ssp_z=keep[0], ssp_c=keep[1],
                  rho_w=env.rho_w, atten_w=env.atten_w, c_b=env.c_b, rho_b=env.rho_b,
                  atten_b=env.atten_b, n_bathy=len(env.bathy_theta), bathy_theta=keep[2],
-                 bathy_depth=keep[3], zmax=env.zmax, floor=int(env.floor))
+                 bathy_depth=keep[3], n_bathy_r=int(getattr(env, "bathy_nr", 0)),
+                 bathy_r0=float(getattr(env, "bathy_r0", 0.0)), bathy_dr=float(getattr(env, "bathy_dr", 0.0)),
+                 zmax=env.zmax, floor=int(env.floor))
     return s, keep
 
 

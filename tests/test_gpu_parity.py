@@ -316,6 +316,90 @@ def test_batch_mixing_nx2d_and_3d(torch, P, prec):
             assert O.rel_l2(to_host(torch, plain[i]), ref) < TOL[prec], f"problem {i}"
 
 
+# ---------------------------------------------------------------- range-dependent depth
+def _tie_env():
+    """Rigid floor with dz = 5 m exactly (nz = 60, zmax = 300) and depth rows
+    on whole multiples of dz at r = 40, 65, 90 m: with dr = 5 m the steps
+    reach the rows exactly and the water-node decisions there are ties."""
+    base = W.random_env(32, zmax=300.0, floor=W.FLOOR_RIGID, nbathy=4)
+    rows = 5.0 * np.array([[10, 20, 30, 40], [11, 25, 7, 59], [3, 60, 33, 12]], dtype=float)
+    return dataclasses.replace(base, bathy_theta=(-3.0, -1.0, 0.5, 2.0), bathy_depth=tuple(rows.ravel()),
+                               bathy_nr=3, bathy_r0=40.0, bathy_dr=25.0)
+
+
+RANGE = [
+    # name, env, grid kwargs, f, steps of the successive calls
+    ("rd_periodic", W.random_range_env(41, nr=6, row_dr=20.0),
+     dict(nz=60, ntheta=12, theta0=0.0, width=W.TWO_PI, dr=5.0), 40.0, (3, 14)),
+    ("rd_sector_r0", W.random_range_env(42, nr=5, row_dr=15.0, r0=30.0, floor=W.FLOOR_RIGID),
+     dict(nz=45, ntheta=7, theta0=1.0, width=1.0, dr=4.0, r0=22.0), 50.0, (1, 8, 12)),
+    ("rd_ties", _tie_env(), dict(nz=60, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=5.0), 40.0, (9, 11)),
+    ("rd_multi_tile", W.random_range_env(43, zmax=600.0, nr=8, row_dr=25.0),
+     dict(nz=300, ntheta=70, theta0=0.3, width=W.TWO_PI, dr=10.0), 60.0, (4, 5)),
+    ("rd_slope", W.slope_env(rmax=2000.0), dict(nz=256, ntheta=64, theta0=0.0, width=W.TWO_PI, dr=25.0), 30.0,
+     (10, 10)),
+]
+
+
+@pytest.mark.parametrize("mode", [W.MODE_3D, W.MODE_NX2D])
+@pytest.mark.parametrize("prec", [W.PREC_C128, W.PREC_C64])
+@pytest.mark.parametrize("case", RANGE, ids=[c[0] for c in RANGE])
+def test_range_dependent_depth_matches_oracle(torch, P, case, prec, mode):
+    """Depth D(r, theta) with range rows: every step uses the medium at
+    r_{j+1}; the march is split over several calls."""
+    name, env, gk, f, calls = case
+    grid = W.Grid(precision=prec, mode=mode, **gk)
+    st = O.setup(env, grid, f)
+    th = st.theta[:, None]
+    u0 = O.starter(st, 0.3 * env.zmax) * (1 + 0.3 * np.cos(th)) + 0.05 * W.random_field(1, grid.nz, _seed(name))
+    say("range-dependent", name, prec, mode)
+    m = P.Pe3d(env, grid, f)
+    u = to_dev(torch, u0, prec)
+    for n in calls:
+        m.march(n, u)
+    torch.cuda.synchronize()
+    ref = O.march(st, u0, 0, sum(calls))
+    assert O.rel_l2(to_host(torch, u), ref) < TOL[prec], name
+    m.close()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_batch_mixing_range_dependent_problems(torch, P, prec):
+    """Range-dependent and range-independent problems (3D and N x 2D) in one
+    batch equal their plain marches bit for bit, graph or not."""
+    probs = [
+        (RANGE[0][1], W.Grid(precision=prec, **RANGE[0][2]), RANGE[0][3]),
+        (W.wedge_env(), W.Grid(nz=200, ntheta=24, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 40.0),
+        (RANGE[3][1], W.Grid(precision=prec, mode=W.MODE_NX2D, **RANGE[3][2]), RANGE[3][3]),
+        (RANGE[2][1], W.Grid(precision=prec, **RANGE[2][2]), RANGE[2][3]),
+    ]
+    steps = [7, 5, 9, 12]
+    u0s = []
+    for env, grid, f in probs:
+        st = O.setup(env, grid, f)
+        u0s.append(O.starter(st, 0.3 * env.zmax) * (1 + 0.2 * np.sin(st.theta))[:, None])
+    say("batch range-dependent", prec)
+    plain = []
+    for (env, grid, f), u0, n in zip(probs, u0s, steps):
+        m = P.Pe3d(env, grid, f)
+        u = to_dev(torch, u0, prec)
+        m.march(n, u)
+        plain.append(u)
+        m.close()
+    for use_graph in (False, True):
+        ms = [P.Pe3d(env, grid, f) for env, grid, f in probs]
+        us = [to_dev(torch, u0, prec) for u0 in u0s]
+        P.march_batch(ms, steps, us, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(plain, us)):
+            assert torch.equal(a, b), f"problem {i} graph={use_graph}"
+        for m in ms:
+            m.close()
+    env, grid, f = probs[0]
+    ref = O.march(O.setup(env, grid, f), u0s[0], 0, steps[0])
+    assert O.rel_l2(to_host(torch, plain[0]), ref) < TOL[prec]
+
+
 def test_graph_replays_match_direct_calls(torch, P):
     probs = _batch_problems(W.PREC_C64)
     steps = [4, 4, 4, 4, 4]

@@ -32,7 +32,30 @@ CASES = [
     ("near_floor_rigid", dataclasses.replace(W.wedge_env(), bathy_theta=(0.0, 3.0), bathy_depth=(2990.0, 1.0),
                                             floor=W.FLOOR_RIGID, zmax=3000.0),
      W.Grid(nz=60, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=10.0), 40.0),
+    ("range_rows", W.random_range_env(31, nr=5, row_dr=30.0, r0=20.0),
+     W.Grid(nz=64, ntheta=12, theta0=0.3, width=W.TWO_PI, dr=5.0, r0=57.0), 50.0),
 ]
+
+
+def _tie_env():
+    """Rigid floor, dz = 5 m exactly, depth rows on whole multiples of dz:
+    water-node decisions that are exact ties at the range nodes."""
+    base = W.random_env(32, zmax=300.0, floor=W.FLOOR_RIGID, nbathy=4)
+    rows = 5.0 * np.array([[10, 20, 30, 40], [11, 25, 7, 59], [3, 60, 33, 12]], dtype=float)
+    return dataclasses.replace(base, bathy_theta=(-3.0, -1.0, 0.5, 2.0), bathy_depth=tuple(rows.ravel()),
+                               bathy_nr=3, bathy_r0=40.0, bathy_dr=25.0)
+
+
+@pytest.mark.parametrize("r0", [0.0, 40.0, 52.5, 64.999, 65.0, 77.0, 90.0, 1000.0])
+def test_water_nodes_at_a_range_match_the_oracle(P, r0):
+    """The host's D(r) between range rows and its water count give the
+    oracle's mask at r0: exact nodes, ties l dz == D, inside, both ends."""
+    env = _tie_env()
+    grid = W.Grid(nz=60, ntheta=4, theta0=0.0, width=W.TWO_PI, dr=5.0, r0=r0)
+    st = O.setup(env, grid, 40.0)
+    T = P.pe3d_host_tables(env, grid, 40.0)
+    nw = st.water.sum(axis=1)
+    assert np.array_equal(T["kcol"], np.clip(nw - 1, 0, 58)), (T["kcol"], nw)
 
 
 def _lu_pivots(a, b, c):
@@ -58,7 +81,8 @@ def test_host_tables_match_the_oracle_operators(P, name, env, grid, f):
     # n^2 - 1 of the water column: equals the oracle's q on water nodes
     for m in range(NT):
         wet = st.water[m]
-        assert np.allclose(T["qw"][wet], st.q[m][wet], rtol=1e-14, atol=0)
+        # q = n^2 - 1 cancels where c is near c0: compare to an ulp of n^2
+        assert np.allclose(T["qw"][wet], st.q[m][wet], rtol=1e-14, atol=1e-15)
     # all-water column, top-down pivots of I + beta_- X (uniform density)
     qw = T["qw"]
     xl = np.full(N, h, complex); xl[0] = 0.0

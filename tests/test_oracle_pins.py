@@ -5,6 +5,7 @@ against an independent route (a dense LAPACK solve, the FFT diagonalisation of
 a circulant, the closed-form modal solution of a separable problem, an exact
 conservation law, a physical interface condition, symmetries).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -405,3 +406,55 @@ def test_pressure_hankel_factor_textbook_values():
     assert abs(abs(hx) ** 2 * math.pi * x / 2.0 - (1.0 - 1.0 / (8.0 * x * x))) < 1e-11
     with pytest.raises(ValueError):
         O.pressure(st, one, 0)
+
+
+# --------------------------------------------------------------- range-dependent depth
+def test_equal_range_rows_reduce_to_range_independent():
+    base = W.random_env(21, floor=W.FLOOR_RIGID)
+    rd = dataclasses.replace(base, bathy_depth=base.bathy_depth * 3, bathy_nr=3,
+                             bathy_r0=10.0, bathy_dr=40.0)
+    g = W.Grid(nz=40, ntheta=9, theta0=0.1, width=W.TWO_PI, dr=7.0, precision=W.PREC_C128)
+    u0 = W.random_field(9, 40, seed=5)
+    a = O.march(O.setup(base, g, 45.0), u0, 0, 30)
+    b = O.march(O.setup(rd, g, 45.0), u0, 0, 30)
+    assert np.array_equal(a, b)
+
+
+def test_range_dependent_step_uses_the_medium_at_the_next_range():
+    """Fig. 2 advances r, then updates the matrices: the step j -> j+1 is the
+    range-independent step of the medium at r_{j+1}.  Rows one range step
+    apart put row j+1 exactly there (and the last row beyond the rows)."""
+    base = W.random_env(22)
+    nr, nb = 5, len(base.bathy_theta)
+    rng = np.random.default_rng(3)
+    rows = rng.uniform(0.05 * base.zmax, 0.95 * base.zmax, (nr, nb))
+    dr, r0 = 6.0, 18.0
+    rd = dataclasses.replace(base, bathy_depth=tuple(rows.ravel()), bathy_nr=nr,
+                             bathy_r0=r0, bathy_dr=dr)
+    g = W.Grid(nz=50, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=dr, r0=r0, precision=W.PREC_C128)
+    st = O.setup(rd, g, 40.0)
+    u = u0 = W.random_field(8, 50, seed=6)
+    for j in range(7):
+        row = rows[min(j + 1, nr - 1)]
+        sj = O.setup(dataclasses.replace(base, bathy_depth=tuple(row)), g, 40.0)
+        u = O.step(sj, u, j)
+    got = O.march(st, u0, 0, 7)
+    assert np.array_equal(got, u)
+    # the columns really change their water nodes along the way
+    counts = {tuple(st.medium(st.depth_at(st.r(j)))[0].sum(axis=1)) for j in range(1, 5)}
+    assert len(counts) == 4
+
+
+def test_depth_is_linear_in_range_between_rows():
+    base = W.random_env(23)
+    a = np.array(base.bathy_depth)
+    b = a[::-1].copy()
+    rd = dataclasses.replace(base, bathy_depth=tuple(np.concatenate([a, b])), bathy_nr=2,
+                             bathy_r0=100.0, bathy_dr=50.0)
+    st = O.setup(rd, W.Grid(nz=20, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=5.0), 30.0)
+    da = O.interp_bathy(st.theta, base.bathy_theta, a)
+    db = O.interp_bathy(st.theta, base.bathy_theta, b)
+    assert np.array_equal(st.depth_at(100.0), da) and np.array_equal(st.depth_at(0.0), da)
+    assert np.array_equal(st.depth_at(150.0), db) and np.array_equal(st.depth_at(1e6), db)
+    assert np.allclose(st.depth_at(125.0), 0.5 * (da + db), rtol=1e-14, atol=1e-12)
+    assert np.allclose(st.depth_at(110.0), 0.8 * da + 0.2 * db, rtol=1e-14, atol=1e-12)

@@ -39,7 +39,10 @@ class Env:
     ends.  bathy_theta/bathy_depth: water depth D(theta), periodic
     piecewise-linear in theta (one sample means a flat bottom).  Below D the
     medium is a homogeneous fluid half-space (c_b, rho_b, atten_b).  zmax is the
-    computational floor and `floor` its boundary condition.
+    computational floor and `floor` its boundary condition.  Range-dependent
+    depth: bathy_nr >= 2 rows at ranges bathy_r0 + i*bathy_dr, bathy_depth
+    then holding bathy_nr rows of len(bathy_theta) samples (row-major); D is
+    linear in r between rows and constant beyond the first and last.
     """
     c0: float
     ssp_z: tuple
@@ -53,6 +56,9 @@ class Env:
     bathy_depth: tuple
     zmax: float
     floor: int
+    bathy_nr: int = 0
+    bathy_r0: float = 0.0
+    bathy_dr: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -128,6 +134,27 @@ def wedge_env(zmax: float = 3000.0, d_max: float = 2000.0, d_min: float = 200.0,
                zmax=zmax, floor=floor)
 
 
+def slope_env(d0: float = 400.0, slope_deg: float = 3.0, d_min: float = 30.0,
+              d_max: float = 2500.0, zmax: float = 3000.0, rmax: float = 60000.0,
+              row_dr: float = 250.0, nb: int = 72, c_b: float = 1700.0,
+              rho_b: float = 1.5, atten_b: float = 0.5,
+              floor: int = FLOOR_PRESSURE_RELEASE, ssp_dz: float = 10.0) -> Env:
+    """Munk-like water over a planar sloping fluid bottom seen from a source
+    where the depth is d0: D = d0 - y tan(slope) with y = r sin(theta) the
+    cross-slope coordinate (upslope towards theta = pi/2), clipped to
+    [d_min, d_max].  Range- and azimuth-dependent: sampled on range rows every
+    row_dr metres out to rmax and nb azimuths."""
+    z, c = munk_samples(zmax=zmax, dz=ssp_dz)
+    th = -math.pi + (2.0 * math.pi / nb) * np.arange(nb)
+    nr = int(math.ceil(rmax / row_dr)) + 1
+    r = row_dr * np.arange(nr)
+    d = np.clip(d0 - np.outer(r, np.sin(th)) * math.tan(math.radians(slope_deg)), d_min, d_max)
+    return Env(c0=1500.0, ssp_z=z, ssp_c=c, rho_w=1.0, atten_w=0.0,
+               c_b=c_b, rho_b=rho_b, atten_b=atten_b,
+               bathy_theta=tuple(map(float, th)), bathy_depth=tuple(map(float, d.ravel())),
+               zmax=zmax, floor=floor, bathy_nr=nr, bathy_r0=0.0, bathy_dr=row_dr)
+
+
 def flat_layered_env(depth: float = 120.0, zmax: float = 200.0,
                      c_w: float = 1510.0, c_b: float = 1650.0,
                      rho_b: float = 1.8, atten_b: float = 0.3,
@@ -157,6 +184,15 @@ def config2(nsteps: int = 5000, precision: int = PREC_C64) -> Problem:
     grid = Grid(nz=2048, ntheta=512, theta0=0.0, width=TWO_PI, dr=10.0,
                 precision=precision)
     return Problem(env, grid, 100.0, 100.0, nsteps, "config2")
+
+
+def config2_slope(nsteps: int = 1000, precision: int = PREC_C64) -> Problem:
+    """The config-2 grid (Nz=2048, Ntheta=512, dr=10 m, 100 Hz, source at
+    100 m, zmax 3000 m) over the range- and azimuth-dependent sloping bottom
+    of slope_env (a true 3D cross-slope wedge)."""
+    grid = Grid(nz=2048, ntheta=512, theta0=0.0, width=TWO_PI, dr=10.0,
+                precision=precision)
+    return Problem(slope_env(), grid, 100.0, 100.0, nsteps, "config2_slope")
 
 
 def config4_problems(nsteps: int = 1000, nfreq: int = 64,
@@ -241,6 +277,18 @@ def random_env(seed: int, zmax: float = 300.0, lossless: bool = False,
                atten_b=0.0 if lossless else float(rng.uniform(0.1, 1.0)),
                bathy_theta=tuple(map(float, th)), bathy_depth=tuple(map(float, d)),
                zmax=zmax, floor=floor)
+
+
+def random_range_env(seed: int, zmax: float = 300.0, nr: int = 6, row_dr: float = 20.0,
+                     r0: float = 0.0, floor: int = FLOOR_PRESSURE_RELEASE, nbathy: int = 5) -> Env:
+    """random_env with nr random depth rows (inside (0.05..0.98)*zmax, so
+    columns gain and lose water nodes from step to step) at ranges
+    r0 + i*row_dr."""
+    base = random_env(seed, zmax=zmax, floor=floor, nbathy=nbathy)
+    rng = np.random.default_rng(seed + 7919)
+    d = rng.uniform(0.05 * zmax, 0.98 * zmax, (nr, nbathy))
+    return replace(base, bathy_depth=tuple(map(float, d.ravel())), bathy_nr=nr,
+                   bathy_r0=float(r0), bathy_dr=float(row_dr))
 
 
 def with_grid(p: Problem, **kw) -> Problem:
