@@ -60,6 +60,8 @@ def parse():
                          "with the stored oracle samples every 500 steps")
     ap.add_argument("--nx2d-report", action="store_true",
                     help="also compare the N x 2D (Y = 0) mode with the 3D march on the config-2 wedge")
+    ap.add_argument("--range-report", action="store_true",
+                    help="also time the config-2 grid over the range-dependent sloping bottom")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-range-scale", type=float, default=0.25)
     return ap.parse_args()
@@ -283,6 +285,8 @@ def main():
         out["precision_study"] = precision_study(P)
     if args.nx2d_report:
         out["nx2d_report"] = nx2d_report(P)
+    if args.range_report:
+        out["range_report"] = range_report(P)
     print(json.dumps(out), flush=True)
 
 
@@ -372,6 +376,37 @@ def nx2d_report(P, nsteps=2000, every=500):
     log(f"nx2d vs 3d: {ms_per_step}, TL diff RMS {['%.2f' % x for x in rms]} dB")
     for m in ms.values():
         m.close()
+    return res
+
+
+def range_report(P, nsteps=1000):
+    """GPU time per step of the config-2 grid (Nz 2048, Ntheta 512, 100 Hz,
+    complex64, plain march, HIP events over nsteps after a warm-up) over the
+    range-independent wedge and over the range- and azimuth-dependent sloping
+    bottom (per-step water-node update + the same two passes)."""
+    import torch
+    res = {}
+    for name, p in (("wedge_range_independent", W.config2(nsteps=nsteps)),
+                    ("slope_range_dependent", W.config2_slope(nsteps=nsteps))):
+        m = P.Pe3d(p.env, p.grid, p.f_hz)
+        u = m.starter(p.zs)
+        m.march(5, u.clone())
+        m.set_step(0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.march(nsteps, u)
+        e1.record()
+        torch.cuda.synchronize()
+        msps = e0.elapsed_time(e1) / nsteps
+        res[name] = dict(ms_per_step=round(msps, 5),
+                         pt_steps_per_s=p.points / (msps * 1e-3))
+        m.close()
+    res.update(workload="config2 grid: periodic wedge vs slope_env (d0 400 m, 3 deg plane slope "
+                        "clipped to 30-2500 m, rows every 250 m), complex64, plain march",
+               slowdown_range_dependent=round(res["slope_range_dependent"]["ms_per_step"]
+                                              / res["wedge_range_independent"]["ms_per_step"], 3))
+    log(f"range report: {res}")
     return res
 
 

@@ -364,6 +364,24 @@ def test_range_dependent_depth_matches_oracle(torch, P, case, prec, mode):
 
 
 @pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_full_size_sloping_bottom_matches_oracle(torch, P, prec):
+    """The config-2 grid (Nz 2048, Ntheta 512) over the range-dependent
+    sloping bottom, started at r0 = 2 km (so every column meets the slope):
+    3 steps against the oracle over the whole field."""
+    p = W.config2_slope(nsteps=3, precision=prec)
+    grid = dataclasses.replace(p.grid, r0=2000.0)
+    st = O.setup(p.env, grid, p.f_hz)
+    u0 = O.starter(st, p.zs)
+    say("full-size slope", prec)
+    m = P.Pe3d(p.env, grid, p.f_hz)
+    u = to_dev(torch, u0, prec)
+    m.march(3, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, 3)) < TOL[prec]
+    m.close()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
 def test_batch_mixing_range_dependent_problems(torch, P, prec):
     """Range-dependent and range-independent problems (3D and N x 2D) in one
     batch equal their plain marches bit for bit, graph or not."""
