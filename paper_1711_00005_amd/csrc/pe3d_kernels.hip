@@ -125,6 +125,25 @@ __device__ __forceinline__ void gstore(C<S>* base, unsigned off, C<S> val) {
   p[off] = v;
 }
 
+// Registers that stage field values in pass A: the complex itself for
+// complex64, a double2 vector for complex128 (a 16-byte struct assigned under
+// a condition into a private array is not promoted to registers by the
+// compiler: it would live in scratch memory, each load waiting for the last).
+template <typename S>
+struct Stage {
+  using T = C<S>;
+};
+template <>
+struct Stage<double> {
+  using T = Vec2<double>::type;
+};
+__device__ __forceinline__ C<float> stage_load(const C<float>* p, size_t e) { return p[e]; }
+__device__ __forceinline__ Vec2<double>::type stage_load(const C<double>* p, size_t e) {
+  return *reinterpret_cast<const Vec2<double>::type*>(p + e);
+}
+__device__ __forceinline__ C<float> stage_val(C<float> v) { return v; }
+__device__ __forceinline__ C<double> stage_val(Vec2<double>::type v) { return mk<double>(v.x, v.y); }
+
 __device__ __forceinline__ C<double> cdiv(C<double> a, C<double> b) {
   // Smith's algorithm
   if (fabs(b.re) >= fabs(b.im)) {
@@ -337,25 +356,25 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const float invN = 1.0f / float(N);
   const C<S>* __restrict__ base = src + (size_t)m0 * N;
   if (!ystage) {
-    C<S> v[M];
+    typename Stage<S>::T v[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
       const int e = lane + q * kPassAThreads;
-      if (e < span) v[q] = base[e];
+      if (e < span) v[q] = stage_load(base, e);
     }
     // LDS index of span entry e (column c = e / N, row e - c N): c CS + GA + e - c N
     if (cpw == 1) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane + q * kPassAThreads;
-        if (e < span) buf[GA + e] = v[q];
+        if (e < span) buf[GA + e] = stage_val(v[q]);
       }
     } else if (N >= kPassAThreads) {
       // e advances by 256 <= N per entry: the column advances by at most one
       int r = lane, idx = GA + lane;
 #pragma unroll
       for (int q = 0; q < M; ++q) {
-        if (lane + q * kPassAThreads < span) buf[idx] = v[q];
+        if (lane + q * kPassAThreads < span) buf[idx] = stage_val(v[q]);
         r += kPassAThreads;
         idx += kPassAThreads;
         if (r >= N) {
@@ -369,7 +388,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         const int e = lane + q * kPassAThreads;
         if (e < span) {
           const int c = int((float(e) + 0.5f) * invN);
-          buf[c * CS + GA + (e - c * N)] = v[q];
+          buf[c * CS + GA + (e - c * N)] = stage_val(v[q]);
         }
       }
     }
@@ -381,7 +400,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     constexpr int QG = 4;
 #pragma unroll 1
     for (int q0 = 0; q0 < M; q0 += QG) {
-      C<S> vc[QG], vl[QG], vr[QG];
+      typename Stage<S>::T vc[QG], vl[QG], vr[QG];
 #pragma unroll
       for (int qq = 0; qq < QG; ++qq) {
         const int e = lane + (q0 + qq) * kPassAThreads;
@@ -395,9 +414,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
             if (mr >= NT) mr = 0;
           }
           // sector edges: load an in-range column, zero it below
-          vc[qq] = base[e];
-          vl[qq] = src[(size_t)max(ml, 0) * N + r];
-          vr[qq] = src[(size_t)min(mr, NT - 1) * N + r];
+          vc[qq] = stage_load(base, e);
+          vl[qq] = stage_load(src, (size_t)max(ml, 0) * N + r);
+          vr[qq] = stage_load(src, (size_t)min(mr, NT - 1) * N + r);
         }
       }
 #pragma unroll
@@ -407,9 +426,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
           const int c = int((float(e) + 0.5f) * invN);
           const int mm = m0 + c;
           const bool hl = d.periodic || mm > 0, hr = d.periodic || mm < NT - 1;
-          const D uc = to_d(vc[qq]);
-          const D ul = hl ? to_d(vl[qq]) : zero<double>();
-          const D ur = hr ? to_d(vr[qq]) : zero<double>();
+          const D uc = to_d(stage_val(vc[qq]));
+          const D ul = hl ? to_d(stage_val(vl[qq])) : zero<double>();
+          const D ur = hr ? to_d(stage_val(vr[qq])) : zero<double>();
           const D dd = sub(add(ul, ur), scl(2.0, uc));
           buf[c * CS + GA + (e - c * N)] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));
         }
