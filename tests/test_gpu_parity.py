@@ -508,7 +508,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "config2_oracle_sampl
 def test_config2_matches_oracle_checkpoints(torch, P, prec):
     """Config 2 at full size (Nz=2048, Ntheta=512) marched from the GPU
     starter, compared with the oracle's stored checkpoints on every 4th
-    azimuth and 16th depth node: c64 <= 1e-5, FP64 <= 1e-11."""
+    azimuth and 16th depth node: c64 <= 1e-5, FP64 within fp64_bar(steps)."""
     g = np.load(GOLDEN)
     cps = [int(c) for c in g["checkpoints"]]
     ts, zs_ = int(g["th_stride"]), int(g["z_stride"])
@@ -526,6 +526,47 @@ def test_config2_matches_oracle_checkpoints(torch, P, prec):
         nrm = np.linalg.norm(got)
         assert abs(nrm - float(g[f"norm{c}"])) < 1e-4 * float(g[f"norm{c}"])
     say("config2 errors", prec, errs)
-    lim = 1e-5 if prec == W.PREC_C64 else 1e-11
-    assert max(errs.values()) < lim, errs
+    for c, e in errs.items():
+        assert e < (1e-5 if prec == W.PREC_C64 else fp64_bar(c)), errs
+    m.close()
+
+
+def fp64_bar(steps):
+    """FP64 mode against the complex128 oracle after `steps` steps.  Two FP64
+    implementations of one step (here the twisted and circulant
+    factorisations against Thomas and Sherman-Morrison) differ by a fixed
+    perturbation of a few units in the last place of the step operator, the
+    same at every step, so their difference grows linearly: bar = 9 ulp (1e-15)
+    per step plus 1e-13 for the starter (the device's exp against NumPy's;
+    4e-14 after one step on config 2, where the narrow Gaussian dominates)."""
+    return 1e-13 + 1e-15 * steps
+
+
+GOLDEN3 = os.path.join(os.path.dirname(__file__), "golden", "config3_oracle_samples.npz")
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_config3_precision_study(torch, P, prec):
+    """Config 2 marched to 5000 steps (50 km) from the GPU starter; at every
+    500 steps the sampled field (every 4th azimuth, 16th depth) against the
+    stored complex128 oracle field: complex64 <= 1e-5 at every checkpoint,
+    FP64 within fp64_bar; the full-field norm within 1e-4."""
+    g = np.load(GOLDEN3)
+    cps = [int(c) for c in g["checkpoints"]]
+    ts, zs_ = int(g["th_stride"]), int(g["z_stride"])
+    p = W.config2(nsteps=max(cps), precision=prec)
+    say("config3 precision", prec)
+    m = P.Pe3d(p.env, p.grid, p.f_hz)
+    u = m.starter(p.zs)
+    done, errs = 0, {}
+    for c in cps:
+        m.march(c - done, u)
+        done = c
+        got = to_host(torch, u)
+        errs[c] = O.rel_l2(got[::ts, ::zs_], g[f"u{c}"])
+        nrm = np.linalg.norm(got)
+        assert abs(nrm - float(g[f"norm{c}"])) < 1e-4 * float(g[f"norm{c}"])
+    say("config3 errors", prec, errs)
+    for c, e in errs.items():
+        assert e < (1e-5 if prec == W.PREC_C64 else fp64_bar(c)), errs
     m.close()
