@@ -542,7 +542,14 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const D cin = scan_excl<true>(tp, E, t, L, tot);
 
   // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
-  //      reduced interface right-hand side, divided by nbmh)
+  //      reduced interface right-hand side, divided by nbmh).  The same sweep
+  //      accumulates the lane's local back-substitution end value with zero
+  //      carry, X = sum_j (Gh_0 ... Gh_{j-1}) yh_j (the back substitution
+  //      x_j = yh_j + Gh_j x_{j+1} unrolled from the lane's first slot), so the
+  //      back substitution needs one sweep only; a head lane adds its own
+  //      slot's term once the interface value is known.
+  D X = zero<double>();
+  D pr = one<double>();  // Gh_0 ... Gh_{j-1}
   {
     D yh = cin;
     D gq[PF];
@@ -557,9 +564,14 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         if (head) cf = hrec[3];
         const D y = fma(cf, yh, Rv[j]);
         Rv[j] = head ? y : mul(g, y);
+        if (!head) X = fma(pr, Rv[j], X);
       } else {
         yh = mul(g, add(Rv[j], yh));
         Rv[j] = yh;
+        X = fma(pr, yh, X);
+        pr = mul(pr, g);
+        // keep the accumulation in slot order (not batched up over the sweep)
+        asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
       }
       if (j + PF < M) gq[j % PF] = G_at(j + PF, yh);
     }
@@ -568,23 +580,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      (inverse entries times nbmh, r divided by nbmh)
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
   __syncthreads();
-  if (head) Rv[M - 1] = fma(hrec[4], Rv[M - 1], mul(hrec[5], xch[2 * cw + (bot ? 0 : 1)]));
-
-  // ---- phase 3: local back substitution with zero carry -> x_out = tp x_in + X
-  D X = zero<double>();
-  {
-    D gq[PF];
-#pragma unroll
-    for (int jj = 0; jj < PF; ++jj)
-      if (jj < M) gq[jj] = G_at(M - 1 - jj, X);
-#pragma unroll
-    for (int jj = 0; jj < M; ++jj) {
-      const int j = M - 1 - jj;
-      const D g = gq[jj % PF];
-      if (j == M - 1 && head) X = Rv[j];
-      else X = fma(g, X, Rv[j]);
-      if (jj + PF < M) gq[jj % PF] = G_at(j - PF, X);
-    }
+  if (head) {
+    Rv[M - 1] = fma(hrec[4], Rv[M - 1], mul(hrec[5], xch[2 * cw + (bot ? 0 : 1)]));
+    X = fma(pr, Rv[M - 1], X);
   }
   const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
 
