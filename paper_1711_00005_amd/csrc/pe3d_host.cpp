@@ -160,6 +160,8 @@ struct Built {
   int nbr = 0;                          // range rows (0: range independent)
   double br0 = 0, bdr = 0;
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
+  int bconv[2] = {0, 0};   // first row of each chain's converged tail
+  cd gtail[2], ctail[2];   // the tail's Gh and RHS diagonal / nbmh
   int wb = 0, nc = 0, td = 0, mb = 0, maxm_b = 0, ntile_b = 0;
 };
 
@@ -406,6 +408,27 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
     cd c = 1.0 + bp * (b.qb - 2.0 * h);
     if (bb == 0) c *= floor_scale;
     b.tabC[MLT + tix(bb)] = c * inb;
+  }
+  // converged tails: a uniform stretch of a chain (the whole bottom column;
+  // the water column where the sound speed is constant) has a constant RHS
+  // diagonal and pivots that converge geometrically.  From chain row
+  // bconv[ch] on, every row's diagonal equals the chain's last one and its
+  // Gh is within 2^-51 of the last one's; those rows take exactly the last
+  // row's values (a change within the recurrence's own rounding).  Wavefronts
+  // of the depth kernel whose lanes hold only tail and zero rows use these
+  // constants instead of reading the tables.
+  for (int ch = 0; ch < 2; ++ch) {
+    const cd gl = b.tabG[ch * MLT + tix(N - 2)], cl = b.tabC[ch * MLT + tix(N - 2)];
+    int bc = N - 2;
+    while (bc > 0) {
+      const cd g = b.tabG[ch * MLT + tix(bc - 1)], c = b.tabC[ch * MLT + tix(bc - 1)];
+      if (c != cl || !(std::abs(g - gl) <= 0x1p-51 * std::abs(gl))) break;
+      --bc;
+    }
+    for (int r = bc; r <= N - 2; ++r) b.tabG[ch * MLT + tix(r)] = gl;
+    b.bconv[ch] = bc;
+    b.gtail[ch] = gl;
+    b.ctail[ch] = cl;
   }
   // lane products by (chain, leading zero slots sc = 1..M, lane in chain tc):
   // slot j of the lane holds chain row tc*M + j - sc
@@ -736,6 +759,13 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.bm_im = b.bm.imag();
   d.cbs_re = b.cbs.real();
   d.cbs_im = b.cbs.imag();
+  for (int ch = 0; ch < 2; ++ch) {
+    d.bconv[ch] = b.bconv[ch];
+    d.gt_re[ch] = b.gtail[ch].real();
+    d.gt_im[ch] = b.gtail[ch].imag();
+    d.ct_re[ch] = b.ctail[ch].real();
+    d.ct_im[ch] = b.ctail[ch].imag();
+  }
   d.wb = b.wb;
   d.nc = b.nc;
   d.td = b.td;

@@ -48,6 +48,8 @@ struct ProbDesc {
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
   double cbs_re, cbs_im;  // beta_+ h / nbmh, off-diagonal of the scaled depth RHS
+  int bconv[2];         // per chain: rows >= bconv hold the tail values below
+  double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
   // azimuth pass (pass B): W lanes per depth line, NC <= W chunks of M azimuths
   int wb;               // W, lanes per depth line (power of two, 1..64)
   int nc;               // NC = ceil(nth / M)

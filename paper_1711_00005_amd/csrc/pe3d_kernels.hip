@@ -38,6 +38,7 @@
 // amount on every step and the error would grow linearly with range; data
 // roundings change from step to step and only accumulate as a random walk.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include "pe3d_internal.h"
 
@@ -467,15 +468,36 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // its offset passes through an empty volatile asm that also reads that
   // value, so the compiler can neither hoist the load to the phase start nor
   // sink the slot's arithmetic below it.
-  auto G_at = [&](int j, const D& after) {
-    unsigned o = offb[j];
-    asm volatile("" : "+v"(o) : "v"(after.re));
-    return gload_b(d.tabG, o);
+  // Table reads.  A lane needs the tables only for its chain rows below the
+  // chain's converged tail: slots j < jlo are the chain's leading zero rows
+  // (only its first lane has them), slots j >= jhi tail rows (the chain's
+  // constants); idle lanes need none.  A wavefront in which no lane needs
+  // them (wtab false) runs the sweeps with the constants instead of reads
+  // (the tables hold the same values, so both forms give the same numbers).
+  const int jlo = (top || bot) ? max(sc - tc * M, 0) : M;
+  const int jhi = (top || bot) ? min(max(d.bconv[tb] + sc - tc * M, jlo), M) : M;
+  const bool wtab = __ballot(jlo < jhi) != 0;
+  auto G_at = [&](auto tab, int j, const D& after) {
+    if constexpr (decltype(tab)::value) {
+      unsigned o = offb[j];
+      asm volatile("" : "+v"(o) : "v"(after.re));
+      return gload_b(d.tabG, o);
+    } else {
+      D v = j < jlo ? zero<double>() : mk<double>(d.gt_re[tb], d.gt_im[tb]);
+      asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));  // same order as the reads
+      return v;
+    }
   };
-  auto C_at = [&](int j, const D& after) {
-    unsigned o = offb[j];
-    asm volatile("" : "+v"(o) : "v"(after.re));
-    return gload_b(d.tabC, o);
+  auto C_at = [&](auto tab, int j, const D& after) {
+    if constexpr (decltype(tab)::value) {
+      unsigned o = offb[j];
+      asm volatile("" : "+v"(o) : "v"(after.re));
+      return gload_b(d.tabC, o);
+    } else {
+      D v = j < jlo ? zero<double>() : mk<double>(d.ct_re[tb], d.ct_im[tb]);
+      asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));
+      return v;
+    }
   };
   // the head lanes' interface coefficients: RHS diagonal, previous and next
   // coefficient, elimination multiplier, then the two inverse entries
@@ -495,13 +517,13 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const C<S>* col = buf + cw * CS + GA;
   D Rv[M];
   D E = zero<double>();
-  {
+  auto phase1 = [&](auto tab) {
     D gq[PF], cq[PF];
 #pragma unroll
     for (int j = 0; j < PF; ++j)
       if (j < M) {
-        gq[j] = G_at(j, E);
-        cq[j] = C_at(j, E);
+        gq[j] = G_at(tab, j, E);
+        cq[j] = C_at(tab, j, E);
       }
     const C<S>* p = col + row0;
     D wp = to_d(p[-dir]);
@@ -531,14 +553,18 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         E = mul(g, add(R, E));
       }
       if (j + PF < M) {
-        gq[j % PF] = G_at(j + PF, E);
-        cq[j % PF] = C_at(j + PF, E);
+        gq[j % PF] = G_at(tab, j + PF, E);
+        cq[j % PF] = C_at(tab, j + PF, E);
       }
       Rv[j] = R;
       wp = wc;
       wc = wn;
     }
-  }
+  };
+  if (wtab)
+    phase1(std::true_type{});
+  else
+    phase1(std::false_type{});
   const D cin = scan_excl<true>(tp, E, t, L, tot);
 
   // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
@@ -550,12 +576,12 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      slot's term once the interface value is known.
   D X = zero<double>();
   D pr = one<double>();  // Gh_0 ... Gh_{j-1}
-  {
+  auto phase2 = [&](auto tab) {
     D yh = cin;
     D gq[PF];
 #pragma unroll
     for (int j = 0; j < PF; ++j)
-      if (j < M) gq[j] = G_at(j, yh);
+      if (j < M) gq[j] = G_at(tab, j, yh);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
@@ -573,9 +599,10 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         // keep the accumulation in slot order (not batched up over the sweep)
         asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
       }
-      if (j + PF < M) gq[j % PF] = G_at(j + PF, yh);
+      if (j + PF < M) gq[j % PF] = G_at(tab, j + PF, yh);
     }
-  }
+  };
+  phase2(std::true_type{});
   // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
   //      (inverse entries times nbmh, r divided by nbmh)
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
@@ -589,12 +616,12 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // ---- phase 4: back substitution with the exact carry, written to the column
   //      buffer (the input was last read before the interface barrier; zero
   //      slots and idle lanes write guard rows only)
-  {
+  auto phase4 = [&](auto tab) {
     D x = xin;
     D gq[PF];
 #pragma unroll
     for (int jj = 0; jj < PF; ++jj)
-      if (jj < M) gq[jj] = G_at(M - 1 - jj, x);
+      if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
     C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
 #pragma unroll
     for (int jj = 0; jj < M; ++jj) {
@@ -604,9 +631,13 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       else x = fma(g, x, Rv[j]);
       *p = from_d<S>(x);
       p -= dir;
-      if (jj + PF < M) gq[jj % PF] = G_at(j - PF, x);
+      if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
     }
-  }
+  };
+  if (wtab)
+    phase4(std::true_type{});
+  else
+    phase4(std::false_type{});
   __syncthreads();
   {
     // the staging addresses are recomputed here rather than kept live
