@@ -939,7 +939,9 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     // problems stay a prefix of the list, as the steps stay non-increasing
     if (hd.nx2d) continue;
     ib_lds[kBatchClass] = std::max(ib_lds[kBatchClass], h->lds_b);
-    for (int t = 0; t < hd.ntile_b; ++t) {
+    const bool pairs = pass_b_pairs(hd.td, h->prec ? 16 : 8);
+    for (int b = 0; b < hd.ntile_b; ++b) {
+      const int t = pairs ? pass_b_paired_tile(b, hd.ntile_b) : b;
       ib[kBatchClass].push_back({p, t});
       ib_steps[kBatchClass].push_back(nsteps[order[p]]);
       const int nd = std::min(hd.td, hd.nz - t * hd.td);

@@ -71,6 +71,20 @@ struct WorkItem {
 
 constexpr int kPassBThreads = 512;
 
+// Depth tiles of the azimuth pass: tile t covers depths [t td, (t+1) td).
+// When a tile's row segment (td values) is half a 128-byte cache line, tiles
+// 2q and 2q+1 share their lines.  Workgroups are dispatched round-robin over
+// the 8 XCDs, each with its own L2, so such a pair goes to workgroups 8
+// apart: the same XCD, dispatched together, one fetch of each line.  A
+// bijection of [0, n): each group of 16 workgroups holds 8 pairs; a ragged
+// last group keeps the identity.
+__host__ __device__ inline int pass_b_paired_tile(int b, int n) {
+  const int g = b >> 4, pos = b & 15;
+  if ((g << 4) + 16 > n) return b;
+  return (g << 4) + 2 * (pos & 7) + (pos >> 3);
+}
+__host__ __device__ inline bool pass_b_pairs(int td, int value_bytes) { return td * value_bytes < 128; }
+
 // kernel launchers (pe3d_kernels.hip); all return a hipError_t
 // single != nullptr: one problem, grid from single->ntile_a / ntile_b, the
 // descriptor passed by value.  Otherwise a batched launch over nitems items

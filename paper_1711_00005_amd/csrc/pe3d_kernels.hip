@@ -968,7 +968,9 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
 template <typename S, int MM, bool EQ>
 __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_single(ProbDesc d, int koff) {
   extern __shared__ __align__(16) unsigned char smem_b[];
-  pass_b_body<S, MM, EQ>(d, blockIdx.x, koff, smem_b);
+  const int b = blockIdx.x;
+  const int tile = pass_b_pairs(d.td, int(sizeof(C<S>))) ? pass_b_paired_tile(b, d.ntile_b) : b;
+  pass_b_body<S, MM, EQ>(d, tile, koff, smem_b);
 }
 
 // Batched launch over work items of problems of any class (a uniform branch).
