@@ -46,11 +46,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed range steps of the whole batch")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--chunk", type=int, default=10, help="range steps per batched call (one graph)")
+    ap.add_argument("--chunk", type=int, default=50, help="range steps per batched call (one graph)")
     ap.add_argument("--workload", choices=["config4", "config2"], default="config4")
     ap.add_argument("--nfreq", type=int, default=64)
     ap.add_argument("--plain-steps", type=int, default=10)
-    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
@@ -78,9 +78,10 @@ def problems_for(args):
                  "complex64 field, FP64 arithmetic")
 
 
-def measured_traffic(kernel_name):
+def measured_traffic(kernel_name, first_frac):
     """HBM bytes per launch of a kernel from the committed counter summary,
-    or None if the kernel source changed since the counters were taken."""
+    in a launch mix with a fraction first_frac of first steps of a call, or
+    None if the kernel source changed since the counters were taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "config4_batch_hbm_traffic.md")
     src = os.path.join(ROOT, "paper_1711_00005_amd", "csrc", "pe3d_kernels.hip")
@@ -92,11 +93,14 @@ def measured_traffic(kernel_name):
     rec = dict(l.split()[0:2] for l in txt.splitlines() if l.startswith("kernel_sha256"))
     if rec.get("kernel_sha256") != sha:
         return None
+    rec = {}
     for l in txt.splitlines():
         f = l.split()
-        if len(f) == 3 and f[0] == "traffic_bytes" and kernel_name.startswith(f[1]):
-            return int(f[2])
-    return None
+        if len(f) == 4 and f[0] == "traffic_bytes" and kernel_name.startswith(f[1]):
+            rec[f[2]] = int(f[3])
+    if "steady" not in rec:
+        return None
+    return int(round((1.0 - first_frac) * rec["steady"] + first_frac * rec.get("first", rec["steady"])))
 
 
 def march_steps(P, ms, us, nsteps, chunk, use_graph):
@@ -133,7 +137,15 @@ def cpu_baseline(probs, sample_every: int):
         dt = time.perf_counter() - t0
     outs = [r[0] for r in res]
     busy = sum(r[1] for r in res)
-    return dict(value=pts / dt, unit=UNIT, cores=cores, kind="oracle",
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=pts / dt, unit=UNIT, cores=cores, cpu_model=model, kind="oracle",
                 sample=f"1 range step of {len(sample)} of the {len(probs)} problems "
                        f"(every {sample_every}th, {pts} points) from the starter, one process "
                        f"per problem on {cores} cores",
@@ -151,7 +163,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle), before the GPU is initialised")
-        every = 8 if len(probs) >= 8 else 1
+        every = 4 if len(probs) >= 16 else 1
         cpu = cpu_baseline(probs, every)
         log(f"oracle {cpu[0]['value']:.3e} pt*steps/s on {cpu[0]['cores']} cores")
 
@@ -167,11 +179,15 @@ def main():
     torch.cuda.synchronize()
     use_graph = not args.no_graph
 
-    # ---- warmup (captures the graphs of both chunk sizes used below)
+    # ---- warmup; the graphs of the call sizes of the timed region are
+    #      captured (not run) beforehand, so no capture falls inside it
     log("warmup")
-    march_steps(P, ms, us, max(args.warmup, 1), args.chunk, use_graph)
-    if args.steps % args.chunk:
-        march_steps(P, ms, us, args.steps % args.chunk, args.chunk, use_graph)
+    if use_graph:
+        for k in {min(args.chunk, args.steps), args.steps % args.chunk}:
+            if k:
+                P.prepare_batch(ms, k, us)
+    if args.warmup:
+        march_steps(P, ms, us, args.warmup, args.chunk, use_graph)
     torch.cuda.synchronize()
 
     # ---- timed region
@@ -194,6 +210,8 @@ def main():
     P.pe3d_profile_enable(True)
     march_steps(P, ms, us, args.profile_steps, args.chunk, False)
     torch.cuda.synchronize()
+    # first steps of a call in the replayed mix (they also read the neighbour columns)
+    first_frac = -(-args.profile_steps // args.chunk) / args.profile_steps
     stats = P.pe3d_profile_read()
     P.pe3d_profile_enable(False)
     prof_ms = sum(s["total_ms"] for s in stats)
@@ -209,7 +227,8 @@ def main():
     dom_gbs = (dom["algo_bytes"] / dom["launches"]) / (dom_avg * 1e-3) / 1e9
     step_bytes = 32.0 * npts  # both passes, complex64
     roofline = dict(bound="hbm", achieved=round(dom_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom["name"]),
+                    frac=round(dom_gbs / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(dom["name"], first_frac),
                     traffic_unit="bytes per launch",
                     algo_bytes_per_launch=dom["algo_bytes"] / dom["launches"], kernel=dom["name"],
                     step_achieved=round(step_bytes * args.steps / elapsed / 1e9, 1),

@@ -184,8 +184,11 @@ pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
  * use_graph != 0 the whole sequence is captured once into a hipGraph, kept
  * in a library-wide cache of at most 64 plans (least recently used evicted,
  * plans of a destroyed handle dropped) under the exact argument tuple
- * (handles, steps, field pointers), and replayed on later identical calls.  Results are bitwise identical to pe3d_march of each
- * problem alone.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
+ * (handles, steps, field pointers), and replayed on later identical calls.
+ * use_graph == 2 only builds the plan and captures its graph (a later call
+ * with use_graph == 1 and the same tuple replays it): nothing runs, no field
+ * or step counter changes.  Results are bitwise identical to pe3d_march of
+ * each problem alone.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
 pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
                              const int32_t* nsteps, void* const* u_devs,
                              int32_t use_graph, void* stream);

@@ -1061,6 +1061,8 @@ extern "C" pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, i
   return st;
 }
 
+constexpr int32_t kPrepareOnly = 2;  // pe3d_march_batch: build and capture, do not launch
+
 extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const int32_t* nsteps,
                                         void* const* u_devs, int32_t use_graph, void* stream) {
   if (!hs || !nsteps || !u_devs || n < 1) return PE3D_EINVAL;
@@ -1128,6 +1130,7 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
         return PE3D_EDEVICE;
       }
     }
+    if (use_graph == kPrepareOnly) return PE3D_OK;  // captured, not run; steps unchanged
     if (hipGraphLaunch(plan->exec, st) != hipSuccess) return PE3D_EDEVICE;
   } else {
     pe3d_status s = enqueue_plan(*plan, st);

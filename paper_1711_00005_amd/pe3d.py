@@ -249,12 +249,14 @@ def pe3d_tl(h, u_ptr: int, tl_ptr: int, stream_ptr) -> None:
 
 
 def pe3d_march_batch(handles: Sequence[int], nsteps: Sequence[int], u_ptrs: Sequence[int],
-                     use_graph: bool, stream_ptr) -> None:
+                     use_graph: int, stream_ptr) -> None:
+    """use_graph: 0 direct launches, 1 graph (captured once, replayed), 2
+    capture only (nothing runs)."""
     n = len(handles)
     hs = (_H * n)(*handles)
     ns = (ct.c_int32 * n)(*[int(s) for s in nsteps])
     us = (ct.c_void_p * n)(*u_ptrs)
-    _check(_lib.pe3d_march_batch(hs, n, ns, us, int(bool(use_graph)), ct.c_void_p(stream_ptr)),
+    _check(_lib.pe3d_march_batch(hs, n, ns, us, int(use_graph), ct.c_void_p(stream_ptr)),
            "pe3d_march_batch")
 
 
@@ -354,4 +356,13 @@ def march_batch(marches: Sequence[Pe3d], nsteps, fields, use_graph: bool = True,
     if isinstance(nsteps, int):
         nsteps = [nsteps] * len(marches)
     ptrs = [_field_ptr(u, m.nz, m.ntheta, m.precision) for m, u in zip(marches, fields)]
-    pe3d_march_batch([m.h for m in marches], nsteps, ptrs, use_graph, _stream_ptr(stream))
+    pe3d_march_batch([m.h for m in marches], nsteps, ptrs, 1 if use_graph else 0, _stream_ptr(stream))
+
+
+def prepare_batch(marches: Sequence[Pe3d], nsteps, fields, stream=None) -> None:
+    """Build and capture the graph that march_batch(marches, nsteps, fields)
+    replays, without running it (fields and steps unchanged)."""
+    if isinstance(nsteps, int):
+        nsteps = [nsteps] * len(marches)
+    ptrs = [_field_ptr(u, m.nz, m.ntheta, m.precision) for m, u in zip(marches, fields)]
+    pe3d_march_batch([m.h for m in marches], nsteps, ptrs, 2, _stream_ptr(stream))

@@ -418,6 +418,33 @@ def test_batch_mixing_range_dependent_problems(torch, P, prec):
     assert O.rel_l2(to_host(torch, plain[0]), ref) < TOL[prec]
 
 
+def test_prepared_graph_runs_nothing_then_replays(torch, P):
+    """Capture-only (use_graph == 2) leaves fields and step counters alone;
+    the next identical call replays it and equals direct launches bitwise."""
+    probs = _batch_problems(W.PREC_C64)
+    ms = [P.Pe3d(env, grid, f) for env, grid, f in probs]
+    ref = [P.Pe3d(env, grid, f) for env, grid, f in probs]
+    us, rs = [], []
+    for env, grid, f in probs:
+        st = O.setup(env, grid, f)
+        u0 = to_dev(torch, O.starter(st, 60.0), W.PREC_C64)
+        us.append(u0.clone())
+        rs.append(u0.clone())
+    say("prepare_batch")
+    before = [u.clone() for u in us]
+    P.prepare_batch(ms, 3, us)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(us, before))
+    assert [m.step for m in ms] == [0] * len(ms)
+    P.march_batch(ms, 3, us, use_graph=True)
+    P.march_batch(ref, 3, rs, use_graph=False)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(us, rs))
+    assert [m.step for m in ms] == [3] * len(ms)
+    for m in ms + ref:
+        m.close()
+
+
 def test_graph_replays_match_direct_calls(torch, P):
     probs = _batch_problems(W.PREC_C64)
     steps = [4, 4, 4, 4, 4]
