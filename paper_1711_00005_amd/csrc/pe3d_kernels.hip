@@ -576,12 +576,21 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      slot's term once the interface value is known.
   D X = zero<double>();
   D pr = one<double>();  // Gh_0 ... Gh_{j-1}
-  auto phase2 = [&](auto tab) {
+  // The elimination sweep reads the table in every wavefront; a lane that
+  // needs no entry reads the chain's tail row or a zero row instead (the same
+  // address for many lanes, fewer cache lines per read).
+  const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
+  auto G2_at = [&](int j, const D& after) {
+    unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
+    asm volatile("" : "+v"(o) : "v"(after.re));
+    return gload_b(d.tabG, o);
+  };
+  {
     D yh = cin;
     D gq[PF];
 #pragma unroll
     for (int j = 0; j < PF; ++j)
-      if (j < M) gq[j] = G_at(tab, j, yh);
+      if (j < M) gq[j] = G2_at(j, yh);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
@@ -599,10 +608,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         // keep the accumulation in slot order (not batched up over the sweep)
         asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
       }
-      if (j + PF < M) gq[j % PF] = G_at(tab, j + PF, yh);
+      if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
     }
-  };
-  phase2(std::true_type{});
+  }
   // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
   //      (inverse entries times nbmh, r divided by nbmh)
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
