@@ -5,8 +5,8 @@
 //  pass A (depth pass, Eqs. (5)/(7)): per azimuth column, R = [I + beta_+ X] w
 //    with w = [I + s_j D_theta] u^j, then solve [I + beta_- X] v = R.
 //    A 256-lane workgroup owns 256/L columns; each column is split into L
-//    contiguous chunks of M <= 16 rows, one per lane (L up to 256 lanes, so
-//    a column may span several wavefronts).  The column is staged through
+//    contiguous chunks of M <= 17 rows (M odd), one per lane (L up to 256
+//    lanes, so a column may span several wavefronts).  The column is staged through
 //    LDS so that global loads and stores are coalesced along depth.  The
 //    solve is a twisted factorisation: rows above the water/bottom interface
 //    are eliminated top-down with the shared pivots of the all-water column,
@@ -14,7 +14,9 @@
 //    and the two interface rows form a 2x2 block.  Every first-order
 //    recurrence of that elimination is split over the lanes: a local sweep
 //    with zero carry, a segmented wavefront scan of the chunk's affine maps
-//    (cross-lane shuffles), and a fix-up with the exact carry.
+//    (cross-lane shuffles), and a fix-up with the exact carry; three sweeps
+//    in all (RHS and elimination end value; elimination, which also sums the
+//    back-substitution end value; back substitution).
 //
 //  pass B (azimuth pass, Eqs. (6)/(8)): per depth, solve [I - s_j D_theta] u = v.
 //    The operator is circulant (periodic) or Toeplitz (sector) with constant
@@ -621,10 +623,10 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   }
   const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
 
-  // ---- phase 4: back substitution with the exact carry, written to the column
+  // ---- phase 3: back substitution with the exact carry, written to the column
   //      buffer (the input was last read before the interface barrier; zero
   //      slots and idle lanes write guard rows only)
-  auto phase4 = [&](auto tab) {
+  auto phase3 = [&](auto tab) {
     D x = xin;
     D gq[PF];
 #pragma unroll
@@ -643,9 +645,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     }
   };
   if (wtab)
-    phase4(std::true_type{});
+    phase3(std::true_type{});
   else
-    phase4(std::false_type{});
+    phase3(std::false_type{});
   __syncthreads();
   {
     // the staging addresses are recomputed here rather than kept live
