@@ -140,9 +140,16 @@ template <>
 struct Stage<double> {
   using T = Vec2<double>::type;
 };
-__device__ __forceinline__ C<float> stage_load(const C<float>* p, size_t e) { return p[e]; }
+// (global address space: the field pointers of a batched launch come from
+// memory, and a generic access would be a FLAT one)
+__device__ __forceinline__ C<float> stage_load(const C<float>* p, size_t e) {
+  using V = Vec2<float>::type;
+  const V v = ((const __attribute__((address_space(1))) V*)p)[e];
+  return mk<float>(v.x, v.y);
+}
 __device__ __forceinline__ Vec2<double>::type stage_load(const C<double>* p, size_t e) {
-  return *reinterpret_cast<const Vec2<double>::type*>(p + e);
+  using V = Vec2<double>::type;
+  return ((const __attribute__((address_space(1))) V*)p)[e];
 }
 __device__ __forceinline__ C<float> stage_val(C<float> v) { return v; }
 __device__ __forceinline__ C<double> stage_val(Vec2<double>::type v) { return mk<double>(v.x, v.y); }
@@ -442,7 +449,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // ---- lane role: the column's water nodes nw (at r_{j+1}, written by
   //      depth_update before this launch, when the depth depends on range)
   //      set its interface row k and record
-  const int nw = colok ? d.nwcol[m] : 0;
+  const int nw = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
   const int k = min(max(nw - 1, 0), N - 2);
   const int a = (k + 1) / M + 1;
   const int s = a * M - (k + 1);
@@ -503,11 +510,12 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   };
   // the head lanes' interface coefficients: RHS diagonal, previous and next
   // coefficient, elimination multiplier, then the two inverse entries
-  const D* hrec = ((const D*)d.rec) + (size_t)nw * 12 + (bot ? 6 : 0);
+  const unsigned hoff = unsigned(nw * 12 + (bot ? 6 : 0)) * 16u;  // byte offset in d.rec
+  auto hrec = [&](int q) { return gload_b(d.rec, hoff + unsigned(q) * 16u); };
 
   const D cbs = mk<double>(d.cbs_re, d.cbs_im);
   D tp = zero<double>();
-  if (top || bot) tp = ((const D*)d.tabP)[(tb * (M + 1) + sc) * L + tc];
+  if (top || bot) tp = gload_b(d.tabP, unsigned((tb * (M + 1) + sc) * L + tc) * 16u);
   __syncthreads();
 
   // Table values are prefetched PF slots ahead.
@@ -530,22 +538,25 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     const C<S>* p = col + row0;
     D wp = to_d(p[-dir]);
     D wc = to_d(p[0]);
-    const C<S>* pn = p;  // row of the next window entry, advanced by dir per slot
+    // row of the next window entry, advanced by dir per slot; the empty asm
+    // orders the read after the previous slot's value and is applied to the
+    // index, not to a pointer, so the read stays an LDS read
+    int rn = row0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
       const D cdv = cq[j % PF];
-      pn += dir;
-      asm volatile("" : "+v"(pn) : "v"(E.re));
-      const D wn = to_d(*pn);
+      rn += dir;
+      asm volatile("" : "+v"(rn) : "v"(E.re));
+      const D wn = to_d(col[rn]);
       D R;
       if (j == M - 1) {
         D c0 = cdv, cp = cbs, cn = cbs, cf = one<double>();
         if (head) {
-          c0 = hrec[0];
-          cp = hrec[1];
-          cn = hrec[2];
-          cf = hrec[3];
+          c0 = hrec(0);
+          cp = hrec(1);
+          cn = hrec(2);
+          cf = hrec(3);
         }
         R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
         const D y = fma(cf, E, R);
@@ -598,7 +609,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       const D g = gq[j % PF];
       if (j == M - 1) {
         D cf = one<double>();
-        if (head) cf = hrec[3];
+        if (head) cf = hrec(3);
         const D y = fma(cf, yh, Rv[j]);
         Rv[j] = head ? y : mul(g, y);
         if (!head) X = fma(pr, Rv[j], X);
@@ -618,7 +629,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
   __syncthreads();
   if (head) {
-    Rv[M - 1] = fma(hrec[4], Rv[M - 1], mul(hrec[5], xch[2 * cw + (bot ? 0 : 1)]));
+    Rv[M - 1] = fma(hrec(4), Rv[M - 1], mul(hrec(5), xch[2 * cw + (bot ? 0 : 1)]));
     X = fma(pr, Rv[M - 1], X);
   }
   const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
@@ -658,14 +669,14 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
-        if (e < span) out[e] = buf[GA + e];
+        if (e < span) gstore(out, unsigned(e), buf[GA + e]);
       }
     } else if (N >= kPassAThreads) {
       int r = lane_r, idx = GA + lane_r;
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
-        if (e < span) out[e] = buf[idx];
+        if (e < span) gstore(out, unsigned(e), buf[idx]);
         r += kPassAThreads;
         idx += kPassAThreads;
         if (r >= N) {
@@ -679,7 +690,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         const int e = lane_r + q * kPassAThreads;
         if (e < span) {
           const int c = int((float(e) + 0.5f) * invN);
-          out[e] = buf[c * CS + GA + (e - c * N)];
+          gstore(out, unsigned(e), buf[c * CS + GA + (e - c * N)]);
         }
       }
     }
