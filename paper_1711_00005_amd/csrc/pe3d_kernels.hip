@@ -785,25 +785,6 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     return c * CST + dl * DS + (m - c * M);
   };
 
-  // ---- step constants (wavefront 0; read by all after the staging barrier)
-  if (tid < 64) {
-    const D rho = rho_of(sigma_of(d, j));
-    const int lastlen = NT - (NC - 1) * M;
-    const D rM = cpow(rho, M);
-    sPowC[tid] = cpow(rM, tid);
-    if (!periodic) sPowS[tid] = cpow(rho, 2 * (long long)NT - (long long)M * tid);
-    if (tid == 0) {
-      K->rho = rho;
-      K->rinv = cdiv(one<double>(), rho);
-      K->rL = cpow(rho, lastlen);
-      const D rN = cpow(rho, NT);
-      K->winv = cdiv(one<double>(), mk<double>(1.0 - rN.re, -rN.im));
-      const D r2 = cpow(rho, 2 * (long long)NT + 2);
-      K->sinv = cdiv(one<double>(), mk<double>(1.0 - r2.re, -r2.im));
-      K->rM = rM;
-      K->s1 = sigma_of(d, j + 1);
-    }
-  }
   // ---- stage the tile: thread tid loads chunk tid / TD of depth z0 + tid % TD
   //      (W chunks x TD depths = 512 threads); all loads issued before the
   //      first LDS write
@@ -818,6 +799,26 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
 #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < slen) v[i] = gload(src, o0 + unsigned(i * N));
+    // the step constants are computed while the loads are in flight
+    // ---- step constants (wavefront 0; read by all after the staging barrier)
+    if (tid < 64) {
+      const D rho = rho_of(sigma_of(d, j));
+      const int lastlen = NT - (NC - 1) * M;
+      const D rM = cpow(rho, M);
+      sPowC[tid] = cpow(rM, tid);
+      if (!periodic) sPowS[tid] = cpow(rho, 2 * (long long)NT - (long long)M * tid);
+      if (tid == 0) {
+        K->rho = rho;
+        K->rinv = cdiv(one<double>(), rho);
+        K->rL = cpow(rho, lastlen);
+        const D rN = cpow(rho, NT);
+        K->winv = cdiv(one<double>(), mk<double>(1.0 - rN.re, -rN.im));
+        const D r2 = cpow(rho, 2 * (long long)NT + 2);
+        K->sinv = cdiv(one<double>(), mk<double>(1.0 - r2.re, -r2.im));
+        K->rM = rM;
+        K->s1 = sigma_of(d, j + 1);
+      }
+    }
     C<S>* Ts = tl + sc0 * CST + sdl * DS;
 #pragma unroll
     for (int i = 0; i < MM; ++i)
