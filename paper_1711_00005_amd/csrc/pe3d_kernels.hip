@@ -357,6 +357,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      thread `lane` takes entries lane + 256 q, q < M (ncols*N < 256 M),
   //      all loads issued before the first LDS write.  On the first step
   //      apply [I + s_0 D_theta] from the neighbouring columns.
+  // the column's water nodes (they set the lane roles) are read first, so
+  // that their latency overlaps the staging
+  const int nw_early = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
   for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
     const int c = i / (2 * GA);
     const int g = i - c * 2 * GA;
@@ -449,7 +452,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // ---- lane role: the column's water nodes nw (at r_{j+1}, written by
   //      depth_update before this launch, when the depth depends on range)
   //      set its interface row k and record
-  const int nw = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
+  const int nw = nw_early;
   const int k = min(max(nw - 1, 0), N - 2);
   const int a = (k + 1) / M + 1;
   const int s = a * M - (k + 1);
