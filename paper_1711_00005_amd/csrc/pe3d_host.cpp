@@ -40,6 +40,35 @@ int next_pow2(int x) {
   return p;
 }
 
+// ------------------------------------------------------------------ uploads
+// Host-to-device copies of set-up data (coefficient tables, batch plans) go
+// through a non-blocking stream of the library's own, one per device, at the
+// default priority, and only that stream is waited for: a copy does not wait
+// for kernels the caller has queued (a copy on the legacy default stream
+// would).
+hipError_t upload(void* dst, const void* src, size_t n) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipStream_t s = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) {
+      s = it->second;
+    } else {
+      e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+      if (e != hipSuccess) return e;
+      streams[dev] = s;
+    }
+  }
+  e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 // ------------------------------------------------------------------ validation
 pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) {
   if (!e || !g || !f) return PE3D_EINVAL;
@@ -716,7 +745,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     delete h;
     return PE3D_ENOMEM;
   }
-  if (hipMemcpy(h->d_tables, img.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+  if (upload(h->d_tables, img.data(), tb) != hipSuccess) {
     (void)hipFree(h->d_tables);
     (void)hipFree(h->d_scr);
     delete h;
@@ -993,7 +1022,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   emit(ib, ib_steps, ib_bytes, P.b);
   for (auto& c : P.b) c.lds = ib_lds[c.maxm];
   emit(iu, iu_steps, iu_bytes, P.u);
-  if (hipMemcpy(P.d_mem, img.data(), total, hipMemcpyHostToDevice) != hipSuccess) return PE3D_EDEVICE;
+  if (upload(P.d_mem, img.data(), total) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
 }
 

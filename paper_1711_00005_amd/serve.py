@@ -14,7 +14,8 @@ Scheduling, per iteration:
      arriving while others run join the resident set (continuous batching);
   3. every resident request advances by min(K, steps left) range steps in one
      batched march (one launch per pass per step over all of
-     them, pe3d_march_batch);
+     them, pe3d_march_batch); while the device runs it, newly arrived
+     requests are admitted and set up (they join the next iteration);
   4. requests that reached their range are checked (non-finite field ->
      failed), summarised, and their device memory is released.
 
@@ -60,7 +61,11 @@ class Backend:
         raise NotImplementedError
 
     def march(self, states: Sequence, nsteps: Sequence[int]) -> None:
+        """Advance the states; may return before the device has finished."""
         raise NotImplementedError
+
+    def wait(self) -> None:
+        """Block until the last march has finished (host-only backends: no-op)."""
 
     def finish(self, state, rid: int) -> dict:
         """Summary of a finished request; must report {'finite': bool, ...}."""
@@ -97,13 +102,18 @@ class Pe3dBackend(Backend):
         ms = [s[0] for s in states]
         us = [s[1] for s in states]
         self.P.march_batch(ms, list(nsteps), us, use_graph=self.use_graph)
+
+    def wait(self) -> None:
+        import torch
         torch.cuda.synchronize()
 
     def finish(self, state, rid: int = -1) -> dict:
         import torch
         m, u = state
-        finite = bool(torch.isfinite(torch.view_as_real(u)).all().item())
-        nrm = float(torch.linalg.vector_norm(u).item())
+        # one transfer for both checks
+        chk = torch.stack((torch.isfinite(torch.view_as_real(u)).all().double(),
+                           torch.linalg.vector_norm(u).double())).cpu()
+        finite, nrm = bool(chk[0].item()), float(chk[1].item())
         if rid in self.keep:
             self.kept[rid] = u.detach().cpu().numpy()
         return {"finite": finite, "norm": nrm, "step": m.step, "range_m": m.range_m}
@@ -138,7 +148,9 @@ class Scheduler:
         resident: List[list] = []   # [rid, state, steps_left, footprint]
         used = 0
         t0 = self.clock()
-        while pending or waiting or resident:
+
+        def admit():
+            nonlocal used
             now = self.clock() - t0
             while pending and pending[0].arrival_s <= now:
                 r = pending.popleft()
@@ -159,16 +171,23 @@ class Scheduler:
                 resident.append([r.rid, state, probs[r.rid].nsteps, rec.footprint])
             self.max_used = max(self.max_used, used)
             self.max_resident = max(self.max_resident, len(resident))
+
+        while pending or waiting or resident:
+            admit()
             if not resident:
                 if pending:
                     wait = pending[0].arrival_s - (self.clock() - t0)
                     if wait > 0:
                         self.sleep(wait)
                 continue
-            steps = [min(self.K, x[2]) for x in resident]
-            self.backend.march([x[1] for x in resident], steps)
+            marching = list(resident)
+            steps = [min(self.K, x[2]) for x in marching]
+            self.backend.march([x[1] for x in marching], steps)
+            # while the device works: admit and set up new arrivals (next iteration)
+            admit()
+            self.backend.wait()
             self.iterations += 1
-            for x, s in zip(resident, steps):
+            for x, s in zip(marching, steps):
                 x[2] -= s
             now = self.clock() - t0
             keep = []
