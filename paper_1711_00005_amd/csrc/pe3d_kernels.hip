@@ -40,7 +40,10 @@
 // amount on every step and the error would grow linearly with range; data
 // roundings change from step to step and only accumulate as a random walk.
 #include <hip/hip_runtime.h>
+#include <mutex>
+#include <set>
 #include <type_traits>
+#include <utility>
 
 #include "pe3d_internal.h"
 
@@ -1080,18 +1083,29 @@ __global__ void scale_kernel(const C<R>* u, C<R>* p, size_t n, double hre, doubl
 }
 
 // ============================================================== launchers
+// Raise a kernel's dynamic-LDS limit once per device (thread-safe).
+static hipError_t allow_lds(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::set<std::pair<int, const void*>> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count({dev, fn})) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) done.insert({dev, fn});
+  return e;
+}
+
 template <typename S, int M>
 static hipError_t run_a(const ProbDesc& d, int koff, int lds, hipStream_t st) {
   // largest LDS any shape with this M can ask for: L = 4 lanes and nz = 3M - 1
   // (the host keeps nz <= (L-1) M - 1)
   constexpr int lds_max = pass_a_lds_bytes(int(sizeof(C<S>)), 4, 3 * M - 1, M);
   if (lds > lds_max) return hipErrorInvalidValue;
-  static bool attr = false;  // allow more than the default dynamic LDS once per kernel
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_single<S, M>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  {
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(&pass_a_single<S, M>), lds_max);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   hipLaunchKernelGGL((pass_a_single<S, M>), dim3(d.ntile_a), dim3(kPassAThreads), lds, st, d, koff);
   return hipGetLastError();
@@ -1102,12 +1116,9 @@ static hipError_t run_a_batch(const ProbDesc* d_descs, const WorkItem* items, in
                               hipStream_t st) {
   constexpr int lds_max = pass_a_lds_bytes(int(sizeof(C<S>)), 4, 3 * 17 - 1, 17);
   if (lds > lds_max) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_a_batch<S>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  {
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(&pass_a_batch<S>), lds_max);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   hipLaunchKernelGGL((pass_a_batch<S>), dim3(nitems), dim3(kPassAThreads), lds, st, d_descs, items, koff);
   return hipGetLastError();
@@ -1117,12 +1128,9 @@ template <typename S, int MM, bool EQ>
 static hipError_t run_b(const ProbDesc& d, int koff, int lds, hipStream_t st) {
   constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, MM);  // W = 64 is the largest tile
   if (lds > lds_max) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_single<S, MM, EQ>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  {
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(&pass_b_single<S, MM, EQ>), lds_max);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   hipLaunchKernelGGL((pass_b_single<S, MM, EQ>), dim3(d.ntile_b), dim3(kPassBThreads), lds, st, d, koff);
   return hipGetLastError();
@@ -1133,12 +1141,9 @@ static hipError_t run_b_batch(const ProbDesc* d_descs, const WorkItem* items, in
                               hipStream_t st) {
   constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, 16);
   if (lds > lds_max) return hipErrorInvalidValue;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pass_b_batch<S>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+  {
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(&pass_b_batch<S>), lds_max);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   hipLaunchKernelGGL((pass_b_batch<S>), dim3(nitems), dim3(kPassBThreads), lds, st, d_descs, items, koff);
   return hipGetLastError();
