@@ -371,7 +371,31 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const int span = ncols * N;
   const float invN = 1.0f / float(N);
   const C<S>* __restrict__ base = src + (size_t)m0 * N;
-  if (!ystage) {
+  // complex64 with an even column length: thread `lane` takes the pairs of
+  // entries 2 (lane + 256 q), q < (M+1)/2, with one 16-byte load each (a pair
+  // never crosses a column; the span and its base are 16-byte aligned)
+  const bool pairs = sizeof(S) == 4 && (N & 1) == 0;
+  if (!ystage && pairs) {
+    using F4 = float __attribute__((ext_vector_type(4)));
+    constexpr int MP = (M + 1) / 2;
+    const __attribute__((address_space(1))) F4* b4 = (const __attribute__((address_space(1))) F4*)base;
+    F4 v2[MP];
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+      const int e = 2 * (lane + q * kPassAThreads);
+      if (e < span) v2[q] = b4[e >> 1];
+    }
+#pragma unroll
+    for (int q = 0; q < MP; ++q) {
+      const int e = 2 * (lane + q * kPassAThreads);
+      if (e < span) {
+        const int c = cpw == 1 ? 0 : int((float(e) + 0.5f) * invN);
+        const int idx = c * CS + GA + (e - c * N);
+        buf[idx] = mk<S>(S(v2[q].x), S(v2[q].y));
+        buf[idx + 1] = mk<S>(S(v2[q].z), S(v2[q].w));
+      }
+    }
+  } else if (!ystage) {
     typename Stage<S>::T v[M];
 #pragma unroll
     for (int q = 0; q < M; ++q) {
@@ -671,7 +695,26 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     int lane_r = lane;
     asm volatile("" : "+v"(lane_r));
     C<S>* __restrict__ out = dst + (size_t)m0 * N;
-    if (cpw == 1) {
+    if (pairs) {
+      using F4 = float __attribute__((ext_vector_type(4)));
+      constexpr int MP = (M + 1) / 2;
+      __attribute__((address_space(1))) F4* o4 = (__attribute__((address_space(1))) F4*)out;
+#pragma unroll
+      for (int q = 0; q < MP; ++q) {
+        const int e = 2 * (lane_r + q * kPassAThreads);
+        if (e < span) {
+          const int c = cpw == 1 ? 0 : int((float(e) + 0.5f) * invN);
+          const int idx = c * CS + GA + (e - c * N);
+          const C<S> x0 = buf[idx], x1 = buf[idx + 1];
+          F4 w;
+          w.x = float(x0.re);
+          w.y = float(x0.im);
+          w.z = float(x1.re);
+          w.w = float(x1.im);
+          o4[e >> 1] = w;
+        }
+      }
+    } else if (cpw == 1) {
 #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
