@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--chunk", type=int, default=50, help="range steps per batched call (one graph)")
     ap.add_argument("--workload", choices=["config4", "config2"], default="config4")
     ap.add_argument("--nfreq", type=int, default=64)
+    ap.add_argument("--precision", choices=["c64", "c128"], default="c64",
+                    help="field storage (arithmetic is FP64 in both)")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -68,14 +70,16 @@ def parse():
 
 
 def problems_for(args):
+    prec = W.PREC_C128 if args.precision == "c128" else W.PREC_C64
+    store = "complex128" if prec == W.PREC_C128 else "complex64"
     if args.workload == "config4":
-        return W.config4_problems(nsteps=args.steps, nfreq=args.nfreq), (
+        return W.config4_problems(nsteps=args.steps, nfreq=args.nfreq, precision=prec), (
             f"config4: {args.nfreq} frequencies log-spaced 20-500 Hz, dz=lambda/8 (Nz 320-4096), "
             "Ntheta 256-1024, Munk-like profile over a periodic 2000-200 m wedge, fluid bottom "
-            "1700 m/s rho 1.5 0.5 dB/lambda, complex64 field, FP64 arithmetic, batched")
-    p = W.config2(nsteps=args.steps)
+            f"1700 m/s rho 1.5 0.5 dB/lambda, {store} field, FP64 arithmetic, batched")
+    p = W.config2(nsteps=args.steps, precision=prec)
     return [p], ("config2: 100 Hz, Nz=2048, Ntheta=512, Munk-like profile over a periodic wedge, "
-                 "complex64 field, FP64 arithmetic")
+                 f"{store} field, FP64 arithmetic")
 
 
 def measured_traffic(kernel_name, first_frac):
@@ -96,7 +100,7 @@ def measured_traffic(kernel_name, first_frac):
     rec = {}
     for l in txt.splitlines():
         f = l.split()
-        if len(f) == 4 and f[0] == "traffic_bytes" and kernel_name.startswith(f[1]):
+        if len(f) == 4 and f[0] == "traffic_bytes" and kernel_name == f[1]:
             rec[f[2]] = int(f[3])
     if "steady" not in rec:
         return None
@@ -225,7 +229,7 @@ def main():
     dom = max(stats, key=lambda s: s["total_ms"])
     dom_avg = dom["total_ms"] / dom["launches"]
     dom_gbs = (dom["algo_bytes"] / dom["launches"]) / (dom_avg * 1e-3) / 1e9
-    step_bytes = 32.0 * npts  # both passes, complex64
+    step_bytes = (64.0 if args.precision == "c128" else 32.0) * npts  # both passes, read + write
     roofline = dict(bound="hbm", achieved=round(dom_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(dom_gbs / HBM_PEAK_GBS, 4),
                     traffic=measured_traffic(dom["name"], first_frac),
@@ -238,7 +242,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "storage": "complex64", "data": "synthetic",
+           "storage": "complex128" if args.precision == "c128" else "complex64", "data": "synthetic",
            "config": {"workload": workload, "problems": len(probs), "grid_points": npts,
                       "graph": use_graph, "chunk_steps": args.chunk},
            "roofline": roofline}
