@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -580,7 +581,7 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 std::mutex g_pmu;
-bool g_prof = false;
+std::atomic<bool> g_prof{false};  // read on every launch without the lock
 std::vector<std::string> g_pnames;
 std::vector<ProfRec> g_precs;
 std::vector<hipEvent_t> g_epool;
@@ -606,10 +607,12 @@ int prof_name(const char* pass, int prec, int maxm) {
   return int(g_pnames.size() - 1);
 }
 
-// Launch through `fn`, bracketed by events when profiling is on.
+// Launch through `fn`, bracketed by events when profiling is on (and the
+// launch is not being captured into a graph: `allow` false).
 template <typename F>
-hipError_t prof_launch(const char* pass, int prec, int maxm, double bytes, hipStream_t st, F fn) {
-  if (!g_prof) return fn();
+hipError_t prof_launch(const char* pass, int prec, int maxm, double bytes, hipStream_t st, F fn,
+                       bool allow = true) {
+  if (!allow || !g_prof.load(std::memory_order_relaxed)) return fn();
   std::lock_guard<std::mutex> lk(g_pmu);
   ProfRec r;
   r.name = prof_name(pass, prec, maxm);
@@ -1026,7 +1029,8 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   return PE3D_OK;
 }
 
-pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
+// profile: false while capturing (no event records inside a graph)
+pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st, bool profile = true) {
   for (int k = 0; k < P.maxsteps; ++k) {
     for (auto& c : P.u) {
       int ni = c.nitems_at[k];
@@ -1037,14 +1041,14 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
             return launch_pass_a(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
-          }) != hipSuccess)
+          }, profile) != hipSuccess)
         return PE3D_EDEVICE;
     }
     for (auto& c : P.b) {
       int ni = c.nitems_at[k];
       if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
             return launch_pass_b(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
-          }) != hipSuccess)
+          }, profile) != hipSuccess)
         return PE3D_EDEVICE;
     }
   }
@@ -1056,7 +1060,7 @@ pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
 
 extern "C" pe3d_status pe3d_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_pmu);
-  g_prof = on != 0;
+  g_prof.store(on != 0);
   return PE3D_OK;
 }
 
@@ -1142,10 +1146,7 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
       if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
       pe3d_status s = PE3D_OK;
       if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
-      const bool was = g_prof;
-      g_prof = false;  // no event records inside a captured graph
-      if (s == PE3D_OK) s = enqueue_plan(*plan, cap);
-      g_prof = was;
+      if (s == PE3D_OK) s = enqueue_plan(*plan, cap, false);
       hipGraph_t g = nullptr;
       if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
       (void)hipStreamDestroy(cap);
