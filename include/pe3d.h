@@ -178,20 +178,38 @@ pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
 /* Advance n problems together (the frequency loop of Fig. 2, distributed
  * over MPI ranks in Sec. 3.2.3): problem i moves by
  * nsteps[i] >= 0 steps, its field u_devs[i] in place.  All handles must have
- * the same precision and be distinct.  Each step runs one launch per pass
- * over every problem still stepping (a device work table of (problem, tile)
- * items; the kernels take each problem's shape from its descriptor).  When
- * use_graph != 0 the whole sequence is captured once into a hipGraph, kept
- * in a library-wide cache of at most 64 plans (least recently used evicted,
- * plans of a destroyed handle dropped) under the exact argument tuple
- * (handles, steps, field pointers), and replayed on later identical calls.
- * use_graph == 2 only builds the plan and captures its graph (a later call
- * with use_graph == 1 and the same tuple replays it): nothing runs, no field
- * or step counter changes.  Results are bitwise identical to pe3d_march of
- * each problem alone.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
+ * the same precision, be distinct and live on the current device.
+ * Schedule (pe3d_set_batch_schedule): the problems are split into chains of
+ * near-equal field bytes and each chain into groups of at most group_bytes of
+ * field; a group runs through all of its steps, one launch per pass per step
+ * over every problem of the group still stepping (a device work table of
+ * (problem, tile) items; the kernels take each problem's shape from its
+ * descriptor), before the next group of its chain starts, so that its field
+ * stays in the last-level cache between the passes and the steps.  When
+ * use_graph != 0 each chain is captured once into a hipGraph, kept in a
+ * library-wide cache of at most 64 plans (least recently used evicted, plans
+ * of a destroyed handle dropped) under the exact argument tuple (handles,
+ * steps, field pointers, schedule), and replayed on later identical calls:
+ * chain 0 on `stream`, the others on streams of the plan that wait for
+ * `stream`'s prior work, and `stream` then waits for all of them.  A plan
+ * must not be replayed by two calls at once (they would share its fields).
+ * use_graph == 0 runs the chains one after another on `stream` (this is the
+ * form the profiling events time).  use_graph == 2 only builds the plan and
+ * captures its graphs (a later call with use_graph == 1 and the same tuple
+ * replays them): nothing runs, no field or step counter changes.  Results
+ * are bitwise identical to pe3d_march of each problem alone, whatever the
+ * schedule.  Errors: PE3D_EINVAL, PE3D_EDEVICE, PE3D_ENOMEM. */
 pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
                              const int32_t* nsteps, void* const* u_devs,
                              int32_t use_graph, void* stream);
+
+/* Schedule of later pe3d_march_batch plans (library-wide; plans already
+ * built keep theirs): chains in 1..4 independent streams of work, and
+ * group_bytes >= 0 the field bytes one group of a chain may hold (0: one
+ * group per chain).  Defaults 2 and 112 MiB: two chains of groups whose
+ * fields (about 2 x 108 MB for the 861 MB 64-frequency batch) fit together
+ * in MI355X's 256 MB last-level cache.  Errors: PE3D_EINVAL. */
+pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes);
 
 /* Transmission loss of a field at the handle's current step (Sec. 4.1,
  * Fig. 5): tl[m*nz + l] = -20 log10 |u| + 10 log10 r_j, in FP32, written to a

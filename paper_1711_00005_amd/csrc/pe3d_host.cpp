@@ -524,7 +524,6 @@ struct BatchPlan {
   std::vector<uintptr_t> key;
   std::vector<pe3d_handle> handles;
   int prec = 0;
-  int maxsteps = 0;
   void* d_mem = nullptr;               // descs, items, jdev pointers, adds
   ProbDesc* d_descs = nullptr;
   long long** d_jdevs = nullptr;
@@ -532,20 +531,41 @@ struct BatchPlan {
   int n = 0;
   struct Class {
     int maxm;
-    int lds = 0;                       // pass A: dynamic LDS (largest of the class)
-    WorkItem* d_items;
+    int lds = 0;                       // dynamic LDS (largest of the class)
+    WorkItem* d_items = nullptr;
+    std::vector<WorkItem> h_items;     // host copy until the image is uploaded
     std::vector<int> nitems_at;        // active items at step k (problems sorted by steps)
     std::vector<double> bytes_prefix;  // algorithmic bytes of the first i items
   };
-  std::vector<Class> a, b, u;          // depth pass, azimuth pass, depth update
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
+  // A group of problems marched through all of its steps before the next
+  // group of its chain starts (its field stays in the last-level cache).
+  struct Group {
+    int maxsteps = 0;
+    std::vector<Class> a, b, u;        // depth pass, azimuth pass, depth update
+  };
+  // Chains are independent: chain 0 runs on the caller's stream, the others
+  // on the plan's side streams (graph replay only).
+  std::vector<std::vector<Group>> chains;
+  std::vector<hipGraphExec_t> execs;
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipStream_t> side;       // chains 1.. (graph replay)
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   ~BatchPlan() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : execs) (void)hipGraphExecDestroy(e);
+    for (auto g : graphs) (void)hipGraphDestroy(g);
+    for (auto s : side) (void)hipStreamDestroy(s);
+    for (auto e : join) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
     if (d_mem) (void)hipFree(d_mem);
   }
 };
+
+// Batch schedule (pe3d_set_batch_schedule): independent chains replayed on
+// concurrent streams, and the bytes of field a group may hold.
+constexpr int kMaxChains = 4;
+std::atomic<int> g_chains{2};
+std::atomic<long long> g_group_bytes{112ll << 20};
 
 constexpr int kBatchClass = -1;  // profiling name "batch"
 
@@ -917,73 +937,152 @@ pe3d_status pe3d_pressure(pe3d_handle h, const void* u_dev, void* p_dev, void* s
 // ------------------------------------------------------------------ batch
 namespace {
 
-pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
-                       BatchPlan& P) {
-  // problems sorted by steps (descending) so that the problems still stepping
-  // at step k are a prefix of every item list
-  std::vector<int> order;
+// Partition of the stepping problems (indices into hs) into chains of
+// groups: chains balanced by field bytes (largest problem to the lightest
+// chain), each chain cut, in order of decreasing problem size, into the
+// fewest groups of at most `group_bytes` of field each (a problem larger
+// than that is a group of its own), of near-equal bytes.
+std::vector<std::vector<std::vector<int>>> batch_partition(const pe3d_handle* hs, int n,
+                                                           const int32_t* nsteps, int nchains,
+                                                           long long group_bytes) {
+  std::vector<int> ids;
   for (int i = 0; i < n; ++i)
-    if (nsteps[i] > 0) order.push_back(i);
-  // (and, among equal steps, deeper problems first: their heavier workgroups
-  // are dispatched before the light ones, which shortens the launch tail)
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    if (nsteps[a] != nsteps[b]) return nsteps[a] > nsteps[b];
-    return hs[a]->desc.nz > hs[b]->desc.nz;
-  });
+    if (nsteps[i] > 0) ids.push_back(i);
+  auto bytes_of = [&](int i) {
+    return double(hs[i]->desc.nz) * hs[i]->desc.nth * (hs[i]->prec ? 16.0 : 8.0);
+  };
+  std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return bytes_of(a) > bytes_of(b); });
+  nchains = std::max(1, std::min(nchains, int(ids.size())));
+  std::vector<std::vector<int>> ch(nchains);
+  std::vector<double> tot(nchains, 0.0);
+  for (int i : ids) {
+    int c = int(std::min_element(tot.begin(), tot.end()) - tot.begin());
+    ch[c].push_back(i);
+    tot[c] += bytes_of(i);
+  }
+  std::vector<std::vector<std::vector<int>>> out;
+  for (int c = 0; c < nchains; ++c) {
+    if (ch[c].empty()) continue;
+    int ng = 1;
+    if (group_bytes > 0) ng = std::max(1, int(std::ceil(tot[c] / double(group_bytes))));
+    ng = std::min(ng, int(ch[c].size()));
+    std::vector<std::vector<int>> gs(1);
+    double acc = 0.0;
+    for (size_t q = 0; q < ch[c].size(); ++q) {
+      const int i = ch[c][q];
+      // start a new group once more than half of this problem would lie
+      // beyond the current group's share of the chain
+      const double share = tot[c] * double(gs.size()) / ng;
+      if (!gs.back().empty() && int(gs.size()) < ng && acc + 0.5 * bytes_of(i) > share)
+        gs.emplace_back();
+      gs.back().push_back(i);
+      acc += bytes_of(i);
+    }
+    out.push_back(gs);
+  }
+  return out;
+}
+
+pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
+                       int nchains, long long group_bytes, BatchPlan& P) {
+  auto part = batch_partition(hs, n, nsteps, nchains, group_bytes);
+  // problem slots in the descriptor table, in partition order
+  std::vector<int> order;
+  for (auto& c : part)
+    for (auto& g : c) order.insert(order.end(), g.begin(), g.end());
   const int np = int(order.size());
   P.n = np;
   P.prec = hs[0]->prec;
-  P.maxsteps = np ? nsteps[order[0]] : 0;
   std::vector<ProbDesc> descs(np);
   std::vector<long long*> jdevs(np);
   std::vector<int> adds(np);
-  std::map<int, std::vector<WorkItem>> ia, ib, iu;
-  std::map<int, std::vector<int>> ia_steps, ib_steps, iu_steps;  // steps of the problem of each item
-  std::map<int, std::vector<double>> ia_bytes, ib_bytes, iu_bytes;
-  std::map<int, int> ia_lds, ib_lds;
+  std::vector<int> slot(n, -1);
   for (int p = 0; p < np; ++p) {
     pe3d_handle h = hs[order[p]];
+    slot[order[p]] = p;
     descs[p] = h->desc;
     descs[p].u = u[order[p]];
     descs[p].nsteps = nsteps[order[p]];
     jdevs[p] = h->d_j;
     adds[p] = nsteps[order[p]];
-    const ProbDesc& hd = h->desc;
-    const double esz = h->prec ? 16.0 : 8.0;
-    const int cpw = 256 / hd.lpc;
-    // one launch per pass for all problems (the batch kernels switch on the
-    // problem's shape); class key kBatchClass
-    ia_lds[kBatchClass] = std::max(ia_lds[kBatchClass], h->lds_a);
-    for (int t = 0; t < hd.ntile_a; ++t) {
-      ia[kBatchClass].push_back({p, t});
-      ia_steps[kBatchClass].push_back(nsteps[order[p]]);
-      const int ncol = std::min(cpw, hd.nth - t * cpw);
-      ia_bytes[kBatchClass].push_back(2.0 * esz * ncol * hd.nz);
-    }
-    // problems with range rows: water nodes of 256 columns per item
-    if (hd.nbr)
-      for (int t = 0; t < (hd.nth + 255) / 256; ++t) {
-        iu[kBatchClass].push_back({p, t});
-        iu_steps[kBatchClass].push_back(nsteps[order[p]]);
-        iu_bytes[kBatchClass].push_back(0.0);
+  }
+  auto make_class = [](std::vector<WorkItem>& items, std::vector<int>& steps, std::vector<double>& bytes,
+                       int lds, int maxsteps) {
+    BatchPlan::Class c;
+    c.maxm = kBatchClass;
+    c.lds = lds;
+    c.h_items = std::move(items);
+    c.bytes_prefix.assign(bytes.size() + 1, 0.0);
+    for (size_t i = 0; i < bytes.size(); ++i) c.bytes_prefix[i + 1] = c.bytes_prefix[i] + bytes[i];
+    c.nitems_at.resize(maxsteps);
+    for (int k = 0; k < maxsteps; ++k)  // steps is non-increasing: items whose problem has > k steps
+      c.nitems_at[k] =
+          int(std::lower_bound(steps.begin(), steps.end(), k, [](int a, int v) { return a > v; }) - steps.begin());
+    return c;
+  };
+  for (auto& cpart : part) {
+    std::vector<BatchPlan::Group> chain;
+    for (auto g : cpart) {
+      // within a group: problems sorted by steps (descending) so that the
+      // problems still stepping at step k are a prefix of every item list,
+      // and, among equal steps, deeper problems first (their heavier
+      // workgroups are dispatched before the light ones, which shortens the
+      // launch tail)
+      std::stable_sort(g.begin(), g.end(), [&](int a, int b) {
+        if (nsteps[a] != nsteps[b]) return nsteps[a] > nsteps[b];
+        return hs[a]->desc.nz > hs[b]->desc.nz;
+      });
+      BatchPlan::Group G;
+      G.maxsteps = nsteps[g[0]];
+      std::vector<WorkItem> ia, ib, iu;
+      std::vector<int> sa, sb, su;
+      std::vector<double> ba, bb, bu;
+      int lds_a = 0, lds_b = 0;
+      for (int i : g) {
+        pe3d_handle h = hs[i];
+        const int p = slot[i];
+        const ProbDesc& hd = h->desc;
+        const double esz = h->prec ? 16.0 : 8.0;
+        const int cpw = 256 / hd.lpc;
+        lds_a = std::max(lds_a, h->lds_a);
+        for (int t = 0; t < hd.ntile_a; ++t) {
+          ia.push_back({p, t});
+          sa.push_back(nsteps[i]);
+          const int ncol = std::min(cpw, hd.nth - t * cpw);
+          ba.push_back(2.0 * esz * ncol * hd.nz);
+        }
+        // problems with range rows: water nodes of 256 columns per item
+        if (hd.nbr)
+          for (int t = 0; t < (hd.nth + 255) / 256; ++t) {
+            iu.push_back({p, t});
+            su.push_back(nsteps[i]);
+            bu.push_back(0.0);
+          }
+        // N x 2D problems have no azimuth pass: the items of the still-stepping
+        // problems stay a prefix of the list, as the steps stay non-increasing
+        if (hd.nx2d) continue;
+        lds_b = std::max(lds_b, h->lds_b);
+        const bool pairs = pass_b_pairs(hd.td, h->prec ? 16 : 8);
+        for (int b = 0; b < hd.ntile_b; ++b) {
+          const int t = pairs ? pass_b_paired_tile(b, hd.ntile_b) : b;
+          ib.push_back({p, t});
+          sb.push_back(nsteps[i]);
+          const int nd = std::min(hd.td, hd.nz - t * hd.td);
+          bb.push_back(2.0 * esz * nd * hd.nth);
+        }
       }
-    // N x 2D problems have no azimuth pass: the items of the still-stepping
-    // problems stay a prefix of the list, as the steps stay non-increasing
-    if (hd.nx2d) continue;
-    ib_lds[kBatchClass] = std::max(ib_lds[kBatchClass], h->lds_b);
-    const bool pairs = pass_b_pairs(hd.td, h->prec ? 16 : 8);
-    for (int b = 0; b < hd.ntile_b; ++b) {
-      const int t = pairs ? pass_b_paired_tile(b, hd.ntile_b) : b;
-      ib[kBatchClass].push_back({p, t});
-      ib_steps[kBatchClass].push_back(nsteps[order[p]]);
-      const int nd = std::min(hd.td, hd.nz - t * hd.td);
-      ib_bytes[kBatchClass].push_back(2.0 * esz * nd * hd.nth);
+      if (!ia.empty()) G.a.push_back(make_class(ia, sa, ba, lds_a, G.maxsteps));
+      if (!ib.empty()) G.b.push_back(make_class(ib, sb, bb, lds_b, G.maxsteps));
+      if (!iu.empty()) G.u.push_back(make_class(iu, su, bu, 0, G.maxsteps));
+      chain.push_back(std::move(G));
     }
+    P.chains.push_back(std::move(chain));
   }
   size_t nitems = 0;
-  for (auto& kv : ia) nitems += kv.second.size();
-  for (auto& kv : ib) nitems += kv.second.size();
-  for (auto& kv : iu) nitems += kv.second.size();
+  for (auto& c : P.chains)
+    for (auto& g : c)
+      for (auto* v : {&g.a, &g.b, &g.u})
+        for (auto& k : *v) nitems += k.h_items.size();
   size_t off_desc = 0;
   size_t off_j = (off_desc + np * sizeof(ProbDesc) + 255) & ~size_t(255);
   size_t off_add = (off_j + np * sizeof(long long*) + 255) & ~size_t(255);
@@ -999,61 +1098,110 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   P.d_jdevs = reinterpret_cast<long long**>(base + off_j);
   P.d_adds = reinterpret_cast<int*>(base + off_add);
   size_t cur = off_it;
-  auto emit = [&](std::map<int, std::vector<WorkItem>>& src, std::map<int, std::vector<int>>& stp,
-                  std::map<int, std::vector<double>>& byt, std::vector<BatchPlan::Class>& dst) {
-    for (auto& kv : src) {
-      BatchPlan::Class c;
-      c.maxm = kv.first;
-      const auto& bb = byt[kv.first];
-      c.bytes_prefix.assign(bb.size() + 1, 0.0);
-      for (size_t i = 0; i < bb.size(); ++i) c.bytes_prefix[i + 1] = c.bytes_prefix[i] + bb[i];
-      c.d_items = reinterpret_cast<WorkItem*>(base + cur);
-      std::memcpy(img.data() + cur, kv.second.data(), kv.second.size() * sizeof(WorkItem));
-      cur += kv.second.size() * sizeof(WorkItem);
-      const auto& s = stp[kv.first];
-      c.nitems_at.resize(P.maxsteps);
-      for (int k = 0; k < P.maxsteps; ++k) {
-        // s is non-increasing: count items whose problem has more than k steps
-        int cnt = int(std::lower_bound(s.begin(), s.end(), k, [](int a, int v) { return a > v; }) - s.begin());
-        c.nitems_at[k] = cnt;
-      }
-      dst.push_back(c);
-    }
-  };
-  emit(ia, ia_steps, ia_bytes, P.a);
-  for (auto& c : P.a) c.lds = ia_lds[c.maxm];
-  emit(ib, ib_steps, ib_bytes, P.b);
-  for (auto& c : P.b) c.lds = ib_lds[c.maxm];
-  emit(iu, iu_steps, iu_bytes, P.u);
+  for (auto& c : P.chains)
+    for (auto& g : c)
+      for (auto* v : {&g.a, &g.b, &g.u})
+        for (auto& k : *v) {
+          k.d_items = reinterpret_cast<WorkItem*>(base + cur);
+          std::memcpy(img.data() + cur, k.h_items.data(), k.h_items.size() * sizeof(WorkItem));
+          cur += k.h_items.size() * sizeof(WorkItem);
+          std::vector<WorkItem>().swap(k.h_items);
+        }
   if (upload(P.d_mem, img.data(), total) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
 }
 
+// The launches of one chain: each group through all of its steps.
 // profile: false while capturing (no event records inside a graph)
-pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st, bool profile = true) {
-  for (int k = 0; k < P.maxsteps; ++k) {
-    for (auto& c : P.u) {
-      int ni = c.nitems_at[k];
-      if (ni > 0 && launch_depth_update(nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
-        return PE3D_EDEVICE;
+pe3d_status enqueue_chain(const BatchPlan& P, const std::vector<BatchPlan::Group>& chain, hipStream_t st,
+                          bool profile) {
+  for (const auto& g : chain)
+    for (int k = 0; k < g.maxsteps; ++k) {
+      for (auto& c : g.u) {
+        int ni = c.nitems_at[k];
+        if (ni > 0 && launch_depth_update(nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+          return PE3D_EDEVICE;
+      }
+      for (auto& c : g.a) {
+        int ni = c.nitems_at[k];
+        if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
+              return launch_pass_a(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
+            }, profile) != hipSuccess)
+          return PE3D_EDEVICE;
+      }
+      for (auto& c : g.b) {
+        int ni = c.nitems_at[k];
+        if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
+              return launch_pass_b(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
+            }, profile) != hipSuccess)
+          return PE3D_EDEVICE;
+      }
     }
-    for (auto& c : P.a) {
-      int ni = c.nitems_at[k];
-      if (ni > 0 && prof_launch("pass_a", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_a(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
-          }, profile) != hipSuccess)
-        return PE3D_EDEVICE;
-    }
-    for (auto& c : P.b) {
-      int ni = c.nitems_at[k];
-      if (ni > 0 && prof_launch("pass_b", P.prec, c.maxm, c.bytes_prefix[ni], st, [&] {
-            return launch_pass_b(P.prec, nullptr, P.d_descs, c.d_items, ni, k, c.lds, st);
-          }, profile) != hipSuccess)
-        return PE3D_EDEVICE;
-    }
-  }
-  if (launch_advance(P.d_jdevs, P.d_adds, P.n, nullptr, 0, st) != hipSuccess) return PE3D_EDEVICE;
   return PE3D_OK;
+}
+
+pe3d_status enqueue_advance(const BatchPlan& P, hipStream_t st) {
+  return launch_advance(P.d_jdevs, P.d_adds, P.n, nullptr, 0, st) == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
+}
+
+// Without a graph every chain runs on the caller's stream, one after another.
+pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
+  for (const auto& c : P.chains) {
+    pe3d_status s = enqueue_chain(P, c, st, true);
+    if (s != PE3D_OK) return s;
+  }
+  return enqueue_advance(P, st);
+}
+
+// One graph per chain, captured on a private stream; the side streams and
+// fork/join events of the replay are created with them.
+pe3d_status capture_plan(BatchPlan& P) {
+  for (const auto& c : P.chains) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
+    pe3d_status s = PE3D_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
+    if (s == PE3D_OK) s = enqueue_chain(P, c, cap, false);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
+    (void)hipStreamDestroy(cap);
+    if (g) P.graphs.push_back(g);
+    if (s != PE3D_OK) return s;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) return PE3D_EDEVICE;
+    P.execs.push_back(x);
+  }
+  const size_t nc = P.chains.size();
+  if (nc > 1 && !P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
+    return PE3D_EDEVICE;
+  while (P.side.size() + 1 < nc) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
+    P.side.push_back(s);
+  }
+  while (P.join.size() + 1 < nc) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return PE3D_EDEVICE;
+    P.join.push_back(e);
+  }
+  return PE3D_OK;
+}
+
+// Replay: chain 0 on the caller's stream, chain c >= 1 on side stream c-1
+// after the caller's prior work (fork event); the caller's stream then waits
+// for every chain (join events) and advances the step counters.
+pe3d_status replay_plan(const BatchPlan& P, hipStream_t st) {
+  const size_t nc = P.chains.size();
+  if (nc > 1 && hipEventRecord(P.fork, st) != hipSuccess) return PE3D_EDEVICE;
+  for (size_t c = 1; c < nc; ++c) {
+    if (hipStreamWaitEvent(P.side[c - 1], P.fork, 0) != hipSuccess) return PE3D_EDEVICE;
+    if (hipGraphLaunch(P.execs[c], P.side[c - 1]) != hipSuccess) return PE3D_EDEVICE;
+    if (hipEventRecord(P.join[c - 1], P.side[c - 1]) != hipSuccess) return PE3D_EDEVICE;
+  }
+  if (hipGraphLaunch(P.execs[0], st) != hipSuccess) return PE3D_EDEVICE;
+  for (size_t c = 1; c < nc; ++c)
+    if (hipStreamWaitEvent(st, P.join[c - 1], 0) != hipSuccess) return PE3D_EDEVICE;
+  return enqueue_advance(P, st);
 }
 
 }  // namespace
@@ -1094,6 +1242,13 @@ extern "C" pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, i
   return st;
 }
 
+extern "C" pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes) {
+  if (chains < 1 || chains > kMaxChains || group_bytes < 0) return PE3D_EINVAL;
+  g_chains.store(chains);
+  g_group_bytes.store(group_bytes);
+  return PE3D_OK;
+}
+
 constexpr int32_t kPrepareOnly = 2;  // pe3d_march_batch: build and capture, do not launch
 
 extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const int32_t* nsteps,
@@ -1110,8 +1265,12 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
   if (!any) return PE3D_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
 
+  const int nchains = g_chains.load();
+  const long long group_bytes = g_group_bytes.load();
   std::vector<uintptr_t> key;
-  key.reserve(3 * n + 1);
+  key.reserve(3 * n + 2);
+  key.push_back(uintptr_t(nchains));
+  key.push_back(uintptr_t(group_bytes));
   for (int i = 0; i < n; ++i) {
     key.push_back(reinterpret_cast<uintptr_t>(hs[i]));
     key.push_back(reinterpret_cast<uintptr_t>(u_devs[i]));
@@ -1132,7 +1291,7 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     if (!fresh) return PE3D_ENOMEM;
     fresh->key = key;
     fresh->handles.assign(hs, hs + n);
-    pe3d_status s = build_plan(hs, n, nsteps, u_devs, *fresh);
+    pe3d_status s = build_plan(hs, n, nsteps, u_devs, nchains, group_bytes, *fresh);
     if (s != PE3D_OK) return s;
     plan = fresh.get();
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1141,27 +1300,20 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     touch(key);
   }
   if (use_graph) {
-    if (!plan->exec) {
-      hipStream_t cap;
-      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
-      pe3d_status s = PE3D_OK;
-      if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
-      if (s == PE3D_OK) s = enqueue_plan(*plan, cap, false);
-      hipGraph_t g = nullptr;
-      if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
-      (void)hipStreamDestroy(cap);
+    if (plan->execs.empty()) {
+      pe3d_status s = capture_plan(*plan);
       if (s != PE3D_OK) {
-        if (g) (void)hipGraphDestroy(g);
+        // leave no partial capture behind: the next call captures again
+        for (auto e : plan->execs) (void)hipGraphExecDestroy(e);
+        for (auto g : plan->graphs) (void)hipGraphDestroy(g);
+        plan->execs.clear();
+        plan->graphs.clear();
         return s;
-      }
-      plan->graph = g;
-      if (hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        plan->exec = nullptr;
-        return PE3D_EDEVICE;
       }
     }
     if (use_graph == kPrepareOnly) return PE3D_OK;  // captured, not run; steps unchanged
-    if (hipGraphLaunch(plan->exec, st) != hipSuccess) return PE3D_EDEVICE;
+    pe3d_status s = replay_plan(*plan, st);
+    if (s != PE3D_OK) return s;
   } else {
     pe3d_status s = enqueue_plan(*plan, st);
     if (s != PE3D_OK) return s;

@@ -39,7 +39,8 @@ PE3D_MODE_NX2D = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
-            "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror")
+            "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror",
+            "pe3d_set_batch_schedule")
 
 
 class pe3d_env(ct.Structure):
@@ -97,9 +98,10 @@ _lib.pe3d_host_tables.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), c
 _lib.pe3d_profile_enable.argtypes = [ct.c_int32]
 _lib.pe3d_profile_read.argtypes = [ct.POINTER(pe3d_kernel_stat), ct.c_int32, ct.POINTER(ct.c_int32)]
 _lib.pe3d_strerror.argtypes = [ct.c_int]
-_lib.pe3d_strerror.restype = ct.c_char_p
-for _n in EXPORTED[:-1]:
+_lib.pe3d_set_batch_schedule.argtypes = [ct.c_int32, ct.c_int64]
+for _n in EXPORTED:
     getattr(_lib, _n).restype = ct.c_int
+_lib.pe3d_strerror.restype = ct.c_char_p
 
 
 class Pe3dError(RuntimeError):
@@ -260,6 +262,10 @@ def pe3d_march_batch(handles: Sequence[int], nsteps: Sequence[int], u_ptrs: Sequ
            "pe3d_march_batch")
 
 
+def pe3d_set_batch_schedule(chains: int, group_bytes: int) -> None:
+    _check(_lib.pe3d_set_batch_schedule(int(chains), int(group_bytes)), "pe3d_set_batch_schedule")
+
+
 def pe3d_profile_enable(on: bool) -> None:
     _check(_lib.pe3d_profile_enable(int(bool(on))), "pe3d_profile_enable")
 
@@ -357,6 +363,14 @@ def march_batch(marches: Sequence[Pe3d], nsteps, fields, use_graph: bool = True,
         nsteps = [nsteps] * len(marches)
     ptrs = [_field_ptr(u, m.nz, m.ntheta, m.precision) for m, u in zip(marches, fields)]
     pe3d_march_batch([m.h for m in marches], nsteps, ptrs, 1 if use_graph else 0, _stream_ptr(stream))
+
+
+def set_batch_schedule(chains: int = 2, group_bytes: int = 112 << 20) -> None:
+    """Schedule of later batched plans: independent chains (concurrent streams
+    on graph replay) of groups of at most group_bytes of field, each group
+    marched through all of its steps before the next (0: one group per
+    chain).  The defaults are the library's."""
+    pe3d_set_batch_schedule(chains, group_bytes)
 
 
 def prepare_batch(marches: Sequence[Pe3d], nsteps, fields, stream=None) -> None:

@@ -1,7 +1,8 @@
 """Fixed workload for hardware-counter profiling of the march kernels.
 
 Runs the 64-frequency batch (the bench workload) for a few range steps with
-direct launches (no graph), then one plain device copy of a known size (a
+direct launches (no graph), each launch over the whole batch (one chain, one
+group: the launches whose durations bench.py times with events), then one plain device copy of a known size (a
 calibration kernel for the memory-traffic counters).  Usage:
   rocprofv3 --pmc FETCH_SIZE -- python3 -m paper_1711_00005_amd.profile_driver [steps]
 """
@@ -18,6 +19,7 @@ def main():
     probs = W.config4_problems(nsteps=steps)
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]
+    P.set_batch_schedule(1, 0)
     P.march_batch(ms, 1, us, use_graph=False)   # first-step kernels of a call
     P.march_batch(ms, steps, us, use_graph=False)
     torch.cuda.synchronize()

@@ -44,6 +44,17 @@ def test_strerror(P):
     assert P.pe3d_strerror(7) == "unknown status"
 
 
+def test_batch_schedule_validation(P):
+    lib = P._lib
+    assert lib.pe3d_set_batch_schedule(0, 0) == P.PE3D_EINVAL
+    assert lib.pe3d_set_batch_schedule(5, 0) == P.PE3D_EINVAL
+    assert lib.pe3d_set_batch_schedule(2, -1) == P.PE3D_EINVAL
+    assert lib.pe3d_set_batch_schedule(4, 0) == 0
+    P.set_batch_schedule()
+    with pytest.raises(Exception):
+        P.set_batch_schedule(0)
+
+
 def test_footprint_is_tables_plus_one_field(P):
     p = W.config2()
     b = P.pe3d_footprint(p.env, p.grid, p.f_hz)

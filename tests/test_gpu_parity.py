@@ -440,6 +440,60 @@ def test_batch_mixing_range_dependent_problems(torch, P, prec):
     assert O.rel_l2(to_host(torch, plain[0]), ref) < TOL[prec]
 
 
+@pytest.fixture
+def schedule(P):
+    yield P.set_batch_schedule
+    P.set_batch_schedule()  # library defaults
+
+
+@pytest.mark.parametrize("chains,group_bytes", [(1, 0), (2, 0), (3, 1 << 20), (4, 64 << 10), (2, 112 << 20)])
+def test_batch_schedules_are_bitwise_equal(torch, P, schedule, chains, group_bytes):
+    """Every schedule (chains on concurrent streams, groups marched through
+    all of their steps in turn) gives the plain marches bit for bit, graph or
+    not.  The fields are written on the caller's stream just before the call
+    and read on it just after, with no synchronisation in between: the side
+    streams of a graph replay must wait for the first and be waited for by
+    the second."""
+    prec = W.PREC_C64
+    probs = [
+        (RANGE[0][1], W.Grid(precision=prec, **RANGE[0][2]), RANGE[0][3]),
+        (W.wedge_env(), W.Grid(nz=200, ntheta=24, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 40.0),
+        (RANGE[3][1], W.Grid(precision=prec, mode=W.MODE_NX2D, **RANGE[3][2]), RANGE[3][3]),
+        (RANGE[2][1], W.Grid(precision=prec, **RANGE[2][2]), RANGE[2][3]),
+        (W.wedge_env(), W.Grid(nz=700, ntheta=64, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 60.0),
+        (W.wedge_env(), W.Grid(nz=90, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 25.0),
+    ]
+    steps = [7, 5, 9, 12, 6, 0]
+    u0s = []
+    for env, grid, f in probs:
+        st = O.setup(env, grid, f)
+        u0s.append(to_dev(torch, O.starter(st, 0.3 * env.zmax) * (1 + 0.2 * np.sin(st.theta))[:, None], prec))
+    say("batch schedule", chains, group_bytes)
+    plain = []
+    for (env, grid, f), u0, n in zip(probs, u0s, steps):
+        m = P.Pe3d(env, grid, f)
+        u = u0.clone()
+        m.march(n, u)
+        plain.append(u)
+        m.close()
+    torch.cuda.synchronize()
+    schedule(chains, group_bytes)
+    for use_graph in (False, True):
+        ms = [P.Pe3d(env, grid, f) for env, grid, f in probs]
+        for rep in range(2):
+            for m in ms:
+                m.set_step(0)
+            us = [u0.clone() for u0 in u0s]
+            P.march_batch(ms, steps, us, use_graph=use_graph)
+            snap = [u.clone() for u in us]
+            torch.cuda.synchronize()
+            for i, (a, b) in enumerate(zip(plain, snap)):
+                assert torch.equal(a, b), f"problem {i} graph={use_graph} replay {rep}"
+            assert [m.step for m in ms] == steps
+        for m in ms:
+            m.close()
+
+
 def test_prepared_graph_runs_nothing_then_replays(torch, P):
     """Capture-only (use_graph == 2) leaves fields and step counters alone;
     the next identical call replays it and equals direct launches bitwise."""
