@@ -110,20 +110,33 @@ class Setup:
             self.bathy_r = env.bathy_r0 + env.bathy_dr * np.arange(nr, dtype=np.float64)
             self.dcol = np.stack([interp_bathy(self.theta, env.bathy_theta, rows[i])
                                   for i in range(nr)], axis=1)          # (Ntheta, nr)
-        # the medium at r_0 (the only one when the depth has no range rows)
-        self.water, self.rho, self.q, self.xl, self.xd, self.xu = self.medium(self.depth_at(self.r0))
+        # water sound speed: one profile, or (reading A25) profiles c(r_i, z)
+        # on range rows r_i = ssp_r0 + i ssp_dr, each holding from its range
+        # until the next row's (stair-step in range; the first row also
+        # before it)
+        nsr = int(getattr(env, "ssp_nr", 0))
+        nsz = len(env.ssp_z)
+        self.ssp_rows = np.asarray(env.ssp_c, dtype=np.float64).reshape(max(nsr, 1), nsz)
+        self.ssp_range_dependent = nsr >= 2
+        if self.ssp_range_dependent:
+            self.ssp_r = env.ssp_r0 + env.ssp_dr * np.arange(nsr, dtype=np.float64)
+        self.any_range = self.range_dependent or self.ssp_range_dependent
+        # the medium at r_0 (the only one when nothing depends on range)
+        self.water, self.rho, self.q, self.xl, self.xd, self.xu = self.medium(
+            self.depth_at(self.r0), self.ssp_row_at(self.r0))
         self._xcache = {}
         # Eq. (4): delta = i k0 dr; 1 + (1/4 +- delta/4) X = I + beta_pm X
         self.beta_p = (1.0 + 1j * self.k0 * self.dr) / 4.0
         self.beta_m = (1.0 - 1j * self.k0 * self.dr) / 4.0
 
-    def medium(self, depth: np.ndarray):
-        """Medium and depth operator for water depths D_m of the columns
-        (readings A7, A8, A9): water iff z_l <= D_m.  Returns water, rho,
-        q = n^2 - 1 and the diagonals xl, xd, xu of X, each (Ntheta, Nz)."""
+    def medium(self, depth: np.ndarray, ssp_row: int = 0):
+        """Medium and depth operator for water depths D_m of the columns and
+        the water profile of range row `ssp_row` (readings A7, A8, A9, A25):
+        water iff z_l <= D_m.  Returns water, rho, q = n^2 - 1 and the
+        diagonals xl, xd, xu of X, each (Ntheta, Nz)."""
         env = self.env
         water = self.z[None, :] <= depth[:, None]
-        cw = interp_ssp(self.z, env.ssp_z, env.ssp_c)
+        cw = interp_ssp(self.z, env.ssp_z, self.ssp_rows[ssp_row])
         c = np.where(water, cw[None, :], env.c_b)
         rho = np.where(water, env.rho_w, env.rho_b).astype(np.float64)
         att = np.where(water, env.atten_w, env.atten_b)
@@ -152,16 +165,25 @@ class Setup:
             return interp_bathy(self.theta, self.env.bathy_theta, self.env.bathy_depth)
         return np.array([np.interp(r, self.bathy_r, self.dcol[m]) for m in range(self.nth)])
 
+    def ssp_row_at(self, r: float) -> int:
+        """Water profile row in force at range r (reading A25): the last row
+        whose range is <= r (a library search over the row ranges), row 0
+        before the first."""
+        if not self.ssp_range_dependent:
+            return 0
+        return max(int(np.searchsorted(self.ssp_r, r, side="right")) - 1, 0)
+
     def x_at(self, j: int):
         """Diagonals (xl, xd, xu) of X for the step j -> j+1: the medium at
         r_{j+1} on both sides of Eq. (4) (reading A3: Fig. 2 advances r, then
         updates both matrices)."""
-        if not self.range_dependent:
+        if not self.any_range:
             return self.xl, self.xd, self.xu
         if j not in self._xcache:
             if len(self._xcache) > 64:
                 self._xcache.clear()
-            self._xcache[j] = self.medium(self.depth_at(self.r(j + 1)))[3:]
+            r = self.r(j + 1)
+            self._xcache[j] = self.medium(self.depth_at(r), self.ssp_row_at(r))[3:]
         return self._xcache[j]
 
     def r(self, j: int) -> float:

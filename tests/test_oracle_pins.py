@@ -458,3 +458,60 @@ def test_depth_is_linear_in_range_between_rows():
     assert np.array_equal(st.depth_at(150.0), db) and np.array_equal(st.depth_at(1e6), db)
     assert np.allclose(st.depth_at(125.0), 0.5 * (da + db), rtol=1e-14, atol=1e-12)
     assert np.allclose(st.depth_at(110.0), 0.8 * da + 0.2 * db, rtol=1e-14, atol=1e-12)
+
+
+# --------------------------------------------------------------- range-dependent water (reading A25)
+def test_equal_water_rows_reduce_to_range_independent():
+    base = W.random_env(31, floor=W.FLOOR_RIGID)
+    rd = dataclasses.replace(base, ssp_c=base.ssp_c * 4, ssp_nr=4, ssp_r0=5.0, ssp_dr=20.0)
+    g = W.Grid(nz=40, ntheta=9, theta0=0.1, width=W.TWO_PI, dr=7.0, precision=W.PREC_C128)
+    u0 = W.random_field(9, 40, seed=5)
+    a = O.march(O.setup(base, g, 45.0), u0, 0, 25)
+    b = O.march(O.setup(rd, g, 45.0), u0, 0, 25)
+    assert np.array_equal(a, b)
+
+
+def test_water_rows_are_a_stair_step_in_range():
+    """A profile holds from its row's range until the next row's: with rows
+    at 0, 30, 60 m and dr = 5 m the step j -> j+1 (medium at r_{j+1} =
+    5 (j+1)) uses row 0 for j = 0..4, row 1 from j = 5 (r_6 = 30 exactly,
+    the row's own range) to j = 10, and row 2 (the last) from j = 11 on.  The
+    march equals range-independent marches of each profile over those steps,
+    composed."""
+    base = W.random_env(32)
+    nz_s = len(base.ssp_z)
+    rng = np.random.default_rng(4)
+    rows = rng.uniform(1470.0, 1560.0, (3, nz_s))
+    rd = dataclasses.replace(base, ssp_c=tuple(rows.ravel()), ssp_nr=3, ssp_r0=0.0, ssp_dr=30.0)
+    g = W.Grid(nz=36, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=5.0, precision=W.PREC_C128)
+    u0 = W.random_field(8, 36, seed=7)
+    got = O.march(O.setup(rd, g, 50.0), u0, 0, 16)
+    u = u0
+    for row, j0, j1 in ((0, 0, 5), (1, 5, 11), (2, 11, 16)):
+        seg = O.setup(dataclasses.replace(base, ssp_c=tuple(rows[row])), g, 50.0)
+        u = O.march(seg, u, j0, j1 - j0)
+    assert np.array_equal(got, u)
+    # and the three profiles really differ in their effect
+    alone = O.march(O.setup(dataclasses.replace(base, ssp_c=tuple(rows[0])), g, 50.0), u0, 0, 16)
+    assert O.rel_l2(alone, got) > 1e-3
+
+
+def test_water_rows_with_depth_rows():
+    """Water rows and depth rows together: the step j -> j+1 takes the depth
+    interpolated at r_{j+1} and the profile in force there, each as when
+    alone."""
+    e = W.random_ssp_range_env(33, nr=4, row_dr=25.0, depth_rows=4)
+    g = W.Grid(nz=44, ntheta=10, theta0=0.0, width=W.TWO_PI, dr=6.0, precision=W.PREC_C128)
+    st = O.setup(e, g, 55.0)
+    u = u0 = W.random_field(10, 44, seed=8)
+    for j in range(14):
+        r = st.r(j + 1)
+        row = min(int(r // 25.0), 3)
+        depth_rows = np.asarray(e.bathy_depth).reshape(e.bathy_nr, -1)
+        # a range-independent setup with this step's profile and depth
+        dcol = st.depth_at(r)
+        sj = O.setup(dataclasses.replace(e, ssp_c=tuple(st.ssp_rows[row]), ssp_nr=0, bathy_nr=0,
+                                         bathy_depth=tuple(depth_rows[0])), g, 55.0)
+        sj.water, sj.rho, sj.q, sj.xl, sj.xd, sj.xu = sj.medium(dcol)
+        u = O.step(sj, u, j)
+    assert np.array_equal(O.march(st, u0, 0, 14), u)

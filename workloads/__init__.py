@@ -43,6 +43,10 @@ class Env:
     depth: bathy_nr >= 2 rows at ranges bathy_r0 + i*bathy_dr, bathy_depth
     then holding bathy_nr rows of len(bathy_theta) samples (row-major); D is
     linear in r between rows and constant beyond the first and last.
+    Range-dependent water: ssp_nr >= 2 profiles at ranges ssp_r0 + i*ssp_dr,
+    ssp_c then holding ssp_nr rows of len(ssp_z) speeds (row-major); each
+    row holds from its range until the next row's (stair-step), row 0 also
+    before it.
     """
     c0: float
     ssp_z: tuple
@@ -59,6 +63,9 @@ class Env:
     bathy_nr: int = 0
     bathy_r0: float = 0.0
     bathy_dr: float = 0.0
+    ssp_nr: int = 0
+    ssp_r0: float = 0.0
+    ssp_dr: float = 0.0
 
 
 @dataclass(frozen=True)
@@ -289,6 +296,49 @@ def random_range_env(seed: int, zmax: float = 300.0, nr: int = 6, row_dr: float 
     d = rng.uniform(0.05 * zmax, 0.98 * zmax, (nr, nbathy))
     return replace(base, bathy_depth=tuple(map(float, d.ravel())), bathy_nr=nr,
                    bathy_r0=float(r0), bathy_dr=float(row_dr))
+
+
+def random_ssp_range_env(seed: int, zmax: float = 300.0, nr: int = 5, row_dr: float = 30.0,
+                         r0: float = 0.0, depth_rows: int = 0,
+                         floor: int = FLOOR_PRESSURE_RELEASE, nbathy: int = 5) -> Env:
+    """random_env (or random_range_env with depth_rows rows) with nr random
+    water profiles on the same sample depths (1470..1560 m/s) at ranges
+    r0 + i*row_dr."""
+    if depth_rows >= 2:
+        base = random_range_env(seed, zmax=zmax, nr=depth_rows, row_dr=row_dr * 0.7, r0=r0,
+                                floor=floor, nbathy=nbathy)
+    else:
+        base = random_env(seed, zmax=zmax, floor=floor, nbathy=nbathy)
+    rng = np.random.default_rng(seed + 104729)
+    c = rng.uniform(1470.0, 1560.0, (nr, len(base.ssp_z)))
+    return replace(base, ssp_c=tuple(map(float, c.ravel())), ssp_nr=nr, ssp_r0=float(r0),
+                   ssp_dr=float(row_dr))
+
+
+def front_env(rmax: float = 60000.0, row_dr: float = 1000.0, axis0: float = 1000.0,
+              axis1: float = 600.0, c_min0: float = 1490.0, c_min1: float = 1500.0,
+              zmax: float = 3000.0, ssp_dz: float = 10.0) -> Env:
+    """The wedge of wedge_env under a range-dependent Munk-like water column:
+    the sound channel's axis rises from axis0 to axis1 and its minimum speed
+    goes from c_min0 to c_min1 linearly over rmax (an ocean front), given as
+    profiles every row_dr metres (stair-step in range between them)."""
+    base = wedge_env(zmax=zmax, ssp_dz=ssp_dz)
+    nr = int(math.ceil(rmax / row_dr)) + 1
+    rows = []
+    for i in range(nr):
+        t = min(i * row_dr / rmax, 1.0)
+        z, c = munk_samples(zmax=zmax, dz=ssp_dz, c_min=c_min0 + t * (c_min1 - c_min0),
+                            z_axis=axis0 + t * (axis1 - axis0))
+        rows.extend(c)
+    return replace(base, ssp_c=tuple(map(float, rows)), ssp_nr=nr, ssp_r0=0.0, ssp_dr=float(row_dr))
+
+
+def config2_front(nsteps: int = 1000, precision: int = PREC_C64) -> Problem:
+    """The config-2 grid over the wedge under the range-dependent water of
+    front_env (a profile every 1 km)."""
+    grid = Grid(nz=2048, ntheta=512, theta0=0.0, width=TWO_PI, dr=10.0,
+                precision=precision)
+    return Problem(front_env(), grid, 100.0, 100.0, nsteps, "config2_front")
 
 
 def with_grid(p: Problem, **kw) -> Problem:
