@@ -419,12 +419,15 @@ def nx2d_report(P, nsteps=2000, every=500):
 def range_report(P, nsteps=1000):
     """GPU time per step of the config-2 grid (Nz 2048, Ntheta 512, 100 Hz,
     complex64, plain march, HIP events over nsteps after a warm-up) over the
-    range-independent wedge and over the range- and azimuth-dependent sloping
-    bottom (per-step water-node update + the same two passes)."""
+    range-independent wedge, over the range- and azimuth-dependent sloping
+    bottom (per-step water-node update + the same two passes) and under the
+    range-dependent water of an ocean front (a profile row every 1 km: the
+    per-step row selection + the same two passes with that row's tables)."""
     import torch
     res = {}
     for name, p in (("wedge_range_independent", W.config2(nsteps=nsteps)),
-                    ("slope_range_dependent", W.config2_slope(nsteps=nsteps))):
+                    ("slope_range_dependent", W.config2_slope(nsteps=nsteps)),
+                    ("front_range_dependent_water", W.config2_front(nsteps=nsteps))):
         m = P.Pe3d(p.env, p.grid, p.f_hz)
         u = m.starter(p.zs)
         m.march(5, u.clone())
@@ -440,9 +443,13 @@ def range_report(P, nsteps=1000):
                          pt_steps_per_s=p.points / (msps * 1e-3))
         m.close()
     res.update(workload="config2 grid: periodic wedge vs slope_env (d0 400 m, 3 deg plane slope "
-                        "clipped to 30-2500 m, rows every 250 m), complex64, plain march",
+                        "clipped to 30-2500 m, rows every 250 m) vs front_env (the wedge under a Munk "
+                        "profile whose axis rises 1000 -> 600 m and minimum speed 1490 -> 1500 m/s "
+                        "over 60 km, a row every 1 km), complex64, plain march",
                slowdown_range_dependent=round(res["slope_range_dependent"]["ms_per_step"]
-                                              / res["wedge_range_independent"]["ms_per_step"], 3))
+                                              / res["wedge_range_independent"]["ms_per_step"], 3),
+               slowdown_range_dependent_water=round(res["front_range_dependent_water"]["ms_per_step"]
+                                                    / res["wedge_range_independent"]["ms_per_step"], 3))
     log(f"range report: {res}")
     return res
 

@@ -83,6 +83,15 @@ typedef enum { PE3D_MODE_3D = 0, PE3D_MODE_NX2D = 1 } pe3d_mode;
  * multiply-add) and constant before the first and after the last row.  The
  * step j -> j+1 uses the medium at r_{j+1} on both sides of Eq. (4).
  * n_bathy_r == 0 or 1: range independent, bathy_depth holds n_bathy samples.
+ * Range-dependent water n(r, z) (Eq. (2); the same matrix update): n_ssp_r
+ * >= 2 profiles at ranges ssp_r0 + i*ssp_dr (ssp_dr > 0), ssp_c then holding
+ * n_ssp_r rows of n_ssp speeds (row-major) on the common depths ssp_z; a
+ * row holds from its range until the next row's (stair-step in range), row
+ * 0 also before it, and the step j -> j+1 uses the last row whose range is
+ * <= r_{j+1} (correctly rounded FP64 comparisons).  The depth factorisation
+ * of every row is built at create time (one block of tables per row; see
+ * pe3d_footprint).  n_ssp_r == 0 or 1: one profile of n_ssp speeds.  Water
+ * rows and depth rows may be combined.
  * The arrays are copied by pe3d_create; the caller may free them after. */
 typedef struct {
   double c0;                  /* reference sound speed, k0 = 2 pi f / c0   */
@@ -98,6 +107,8 @@ typedef struct {
   double bathy_r0, bathy_dr;  /* range of the first row, row spacing      */
   double zmax;
   int32_t floor;              /* pe3d_floor */
+  int32_t n_ssp_r;            /* water-profile rows of ssp_c (0 or 1: one) */
+  double ssp_r0, ssp_dr;      /* range of the first row, row spacing       */
 } pe3d_env;
 
 /* Computational grid.  Depth nodes z_l = l*dz, l = 1..nz, with
@@ -157,7 +168,8 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
 pe3d_status pe3d_destroy(pe3d_handle h);
 
 /* Device bytes pe3d_create would allocate for these arguments (coefficient
- * tables + scratch field), excluding the caller's field.  Host only. */
+ * tables, one block per water-profile row, + scratch field), excluding the
+ * caller's field.  Host only. */
 pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid,
                            const pe3d_freq* freq, size_t* bytes);
 
@@ -269,6 +281,7 @@ pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, int32_t* n);
  *             k-1 and k+1; row k+1: k+2 and k), the multiplier that
  *             eliminates that previous row, and the two entries of the
  *             inverse interface 2x2 block giving the row's value (own, other).
+ * With water-profile rows, the tables of row 0.
  * Same validation and errors as pe3d_create (minus device errors). */
 pe3d_status pe3d_host_tables(const pe3d_env* env, const pe3d_grid* grid, const pe3d_freq* freq,
                              double* qw, double* pw, double* pb, int32_t* kcol, double* blk);

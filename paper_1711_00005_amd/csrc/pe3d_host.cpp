@@ -76,10 +76,14 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (!is_fin(f->f_hz) || f->f_hz <= 0.0) return PE3D_EINVAL;
   if (!is_fin(e->c0) || e->c0 <= 0.0) return PE3D_EINVAL;
   if (e->n_ssp < 1 || !e->ssp_z || !e->ssp_c) return PE3D_EINVAL;
+  if (e->n_ssp_r < 0 || e->n_ssp_r > 100000) return PE3D_EINVAL;
+  if (e->n_ssp_r >= 2 && (!is_fin(e->ssp_r0) || !is_fin(e->ssp_dr) || e->ssp_dr <= 0.0)) return PE3D_EINVAL;
   for (int i = 0; i < e->n_ssp; ++i) {
-    if (!is_fin(e->ssp_z[i]) || !is_fin(e->ssp_c[i]) || e->ssp_c[i] <= 0.0) return PE3D_EINVAL;
+    if (!is_fin(e->ssp_z[i])) return PE3D_EINVAL;
     if (i > 0 && !(e->ssp_z[i] > e->ssp_z[i - 1])) return PE3D_EINVAL;
   }
+  for (long long i = 0; i < (long long)e->n_ssp * std::max(e->n_ssp_r, 1); ++i)
+    if (!is_fin(e->ssp_c[i]) || e->ssp_c[i] <= 0.0) return PE3D_EINVAL;
   if (!is_fin(e->rho_w) || e->rho_w <= 0.0 || !is_fin(e->atten_w) || e->atten_w < 0.0) return PE3D_EINVAL;
   if (!is_fin(e->c_b) || e->c_b <= 0.0 || !is_fin(e->rho_b) || e->rho_b <= 0.0 ||
       !is_fin(e->atten_b) || e->atten_b < 0.0)
@@ -189,6 +193,8 @@ struct Built {
   std::vector<double> dcol;             // [NT][nbr] column depths at the range rows
   int nbr = 0;                          // range rows (0: range independent)
   double br0 = 0, bdr = 0;
+  int nsr = 0;                          // water-profile rows (0: one profile)
+  double sr0 = 0, sdr = 0;
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
   int bconv[2] = {0, 0};   // first row of each chain's converged tail
   cd gtail[2], ctail[2];   // the tail's Gh and RHS diagonal / nbmh
@@ -311,6 +317,9 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   b.nbr = e.n_bathy_r >= 2 ? e.n_bathy_r : 0;
   b.br0 = e.bathy_r0;
   b.bdr = e.bathy_dr;
+  b.nsr = e.n_ssp_r >= 2 ? e.n_ssp_r : 0;
+  b.sr0 = e.ssp_r0;
+  b.sdr = e.ssp_dr;
   b.nw.resize(NT);
   b.k.resize(NT);
   if (b.nbr) b.dcol.assign((size_t)NT * b.nbr, 0.0);
@@ -476,18 +485,31 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   return PE3D_OK;
 }
 
-size_t table_bytes(const Built& b) {
-  const size_t csz = 16;  // coefficient tables are FP64 in both precisions
-  size_t n = 0;
-  n += 2 * 2 * (size_t)b.ma * b.lt * csz;        // tabG, tabC
-  n += 2 * (size_t)(b.ma + 1) * b.lpc * csz;    // tabP
-  n += (size_t)(b.N + 1) * 12 * csz;            // rec, by water count
-  n += (size_t)b.NT * b.nbr * sizeof(double);   // dcol (range rows only)
-  n += (size_t)b.NT * sizeof(int);              // nwcol
-  n = (n + 255) & ~size_t(255);
-  n += 256;                                     // step counter
-  return n;
+// Device image of a handle: one block of depth-pass tables per water row
+// (tabG, tabC, tabP, the interface records, RowK), then the column depths at
+// the depth rows, the water nodes per column, the current water row and the
+// step counter.  Coefficient tables are FP64 in both precisions.
+struct Layout {
+  size_t o_G, o_C, o_P, o_rec, o_rk, row_bytes;  // within a row block
+  size_t o_dc, o_k, o_srow, o_j, total;          // in the image
+};
+Layout layout(const Built& b) {
+  const size_t csz = 16;
+  Layout y;
+  y.o_G = 0;
+  y.o_C = y.o_G + 2 * (size_t)b.ma * b.lt * csz;
+  y.o_P = y.o_C + 2 * (size_t)b.ma * b.lt * csz;
+  y.o_rec = y.o_P + 2 * (size_t)(b.ma + 1) * b.lpc * csz;
+  y.o_rk = y.o_rec + (size_t)(b.N + 1) * 12 * csz;
+  y.row_bytes = (y.o_rk + sizeof(RowK) + 255) & ~size_t(255);
+  y.o_dc = y.row_bytes * (size_t)std::max(b.nsr, 1);
+  y.o_k = y.o_dc + (size_t)b.NT * b.nbr * sizeof(double);
+  y.o_srow = y.o_k + (size_t)b.NT * sizeof(int);
+  y.o_j = (y.o_srow + sizeof(int) + 255) & ~size_t(255);
+  y.total = y.o_j + 256;
+  return y;
 }
+size_t table_bytes(const Built& b) { return layout(b).total; }
 size_t field_bytes(const Built& b) { return (size_t)b.N * b.NT * (b.prec ? 16 : 8); }
 
 template <typename R>
@@ -686,6 +708,7 @@ pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3
   b.NT = grid->ntheta;
   b.prec = grid->precision;
   b.nbr = env->n_bathy_r >= 2 ? env->n_bathy_r : 0;
+  b.nsr = env->n_ssp_r >= 2 ? env->n_ssp_r : 0;
   st = choose_shapes(b);
   if (st != PE3D_OK) return st;
   *bytes = table_bytes(b) + field_bytes(b);
@@ -727,26 +750,45 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   Built b;
   st = build(*env, *grid, *freq, b);
   if (st != PE3D_OK) return st;
+  // the depth-pass tables of every further water row (the same grid, shapes
+  // and columns; only the water profile differs)
+  std::vector<Built> more;
+  for (int i = 1; i < b.nsr; ++i) {
+    pe3d_env er = *env;
+    er.ssp_c = env->ssp_c + (size_t)i * env->n_ssp;
+    more.emplace_back();
+    st = build(er, *grid, *freq, more.back());
+    if (st != PE3D_OK) return st;
+  }
 
   // host image of the coefficient tables (FP64 in both precisions)
-  const size_t csz = 16;
-  const size_t tb = table_bytes(b);
+  const Layout y = layout(b);
+  const size_t tb = y.total;
   std::vector<unsigned char> img(tb, 0);
-  const size_t o_G = 0, o_C = o_G + b.tabG.size() * csz, o_P = o_C + b.tabC.size() * csz;
-  const size_t o_rec = o_P + b.tabP.size() * csz;
-  const size_t o_dc = o_rec + (size_t)(b.N + 1) * 12 * csz;
-  const size_t o_k = o_dc + b.dcol.size() * sizeof(double);
-  const size_t o_j = tb - 256;
-  std::vector<cd> recflat;
-  recflat.reserve((size_t)(b.N + 1) * 12);
-  for (auto& a : b.rec)
-    for (auto& z : a) recflat.push_back(z);
-  pack<double>(b.tabG, img, o_G);
-  pack<double>(b.tabC, img, o_C);
-  pack<double>(b.tabP, img, o_P);
-  pack<double>(recflat, img, o_rec);
-  if (!b.dcol.empty()) std::memcpy(img.data() + o_dc, b.dcol.data(), b.dcol.size() * sizeof(double));
-  std::memcpy(img.data() + o_k, b.nw.data(), b.NT * sizeof(int));
+  for (int i = 0; i < std::max(b.nsr, 1); ++i) {
+    const Built& t = i == 0 ? b : more[i - 1];
+    const size_t ob = (size_t)i * y.row_bytes;
+    std::vector<cd> recflat;
+    recflat.reserve((size_t)(t.N + 1) * 12);
+    for (auto& a : t.rec)
+      for (auto& z : a) recflat.push_back(z);
+    pack<double>(t.tabG, img, ob + y.o_G);
+    pack<double>(t.tabC, img, ob + y.o_C);
+    pack<double>(t.tabP, img, ob + y.o_P);
+    pack<double>(recflat, img, ob + y.o_rec);
+    RowK rk;
+    std::memset(&rk, 0, sizeof rk);
+    for (int ch = 0; ch < 2; ++ch) {
+      rk.bconv[ch] = t.bconv[ch];
+      rk.gt_re[ch] = t.gtail[ch].real();
+      rk.gt_im[ch] = t.gtail[ch].imag();
+      rk.ct_re[ch] = t.ctail[ch].real();
+      rk.ct_im[ch] = t.ctail[ch].imag();
+    }
+    std::memcpy(img.data() + ob + y.o_rk, &rk, sizeof rk);
+  }
+  if (!b.dcol.empty()) std::memcpy(img.data() + y.o_dc, b.dcol.data(), b.dcol.size() * sizeof(double));
+  std::memcpy(img.data() + y.o_k, b.nw.data(), b.NT * sizeof(int));
 
   pe3d_handle h = new (std::nothrow) pe3d_handle_s();
   if (!h) return PE3D_ENOMEM;
@@ -775,7 +817,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     return PE3D_EDEVICE;
   }
   unsigned char* base = static_cast<unsigned char*>(h->d_tables);
-  h->d_j = reinterpret_cast<long long*>(base + o_j);
+  h->d_j = reinterpret_cast<long long*>(base + y.o_j);
   h->bytes = tb + field_bytes(b);
   h->r0 = grid->r0;
   h->dr = grid->dr;
@@ -793,15 +835,21 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.ma = b.ma;
   d.ntile_a = b.ntile_a;
   d.lt = b.lt;
-  d.tabG = base + o_G;
-  d.tabC = base + o_C;
-  d.tabP = base + o_P;
-  d.rec = base + o_rec;
-  d.nwcol = reinterpret_cast<int*>(base + o_k);
-  d.dcol = b.nbr ? reinterpret_cast<const double*>(base + o_dc) : nullptr;
+  d.tabG = base + y.o_G;
+  d.tabC = base + y.o_C;
+  d.tabP = base + y.o_P;
+  d.rec = base + y.o_rec;
+  d.rowk = base + y.o_rk;
+  d.nwcol = reinterpret_cast<int*>(base + y.o_k);
+  d.dcol = b.nbr ? reinterpret_cast<const double*>(base + y.o_dc) : nullptr;
   d.nbr = b.nbr;
   d.br0 = b.br0;
   d.bdr = b.bdr;
+  d.nsr = b.nsr;
+  d.sr0 = b.sr0;
+  d.sdr = b.sdr;
+  d.row_stride = (long long)y.row_bytes;
+  d.srow = reinterpret_cast<int*>(base + y.o_srow);
   d.h = b.h;
   d.qb_re = b.qb.real();
   d.qb_im = b.qb.imag();
@@ -811,13 +859,6 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.bm_im = b.bm.imag();
   d.cbs_re = b.cbs.real();
   d.cbs_im = b.cbs.imag();
-  for (int ch = 0; ch < 2; ++ch) {
-    d.bconv[ch] = b.bconv[ch];
-    d.gt_re[ch] = b.gtail[ch].real();
-    d.gt_im[ch] = b.gtail[ch].imag();
-    d.ct_re[ch] = b.ctail[ch].real();
-    d.ct_im[ch] = b.ctail[ch].imag();
-  }
   d.wb = b.wb;
   d.nc = b.nc;
   d.td = b.td;
@@ -891,7 +932,8 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   d.nsteps = nsteps;
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
-    if (d.nbr && launch_depth_update(&d, nullptr, nullptr, 0, k, st) != hipSuccess) return PE3D_EDEVICE;
+    if ((d.nbr || d.nsr) && launch_medium_update(&d, nullptr, nullptr, 0, k, st) != hipSuccess)
+      return PE3D_EDEVICE;
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
           return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
         }) != hipSuccess)
@@ -1051,9 +1093,10 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
           const int ncol = std::min(cpw, hd.nth - t * cpw);
           ba.push_back(2.0 * esz * ncol * hd.nz);
         }
-        // problems with range rows: water nodes of 256 columns per item
-        if (hd.nbr)
-          for (int t = 0; t < (hd.nth + 255) / 256; ++t) {
+        // problems with range rows: water nodes of 256 columns per item (depth
+        // rows), the water row in item 0 (water rows)
+        if (hd.nbr || hd.nsr)
+          for (int t = 0; t < (hd.nbr ? (hd.nth + 255) / 256 : 1); ++t) {
             iu.push_back({p, t});
             su.push_back(nsteps[i]);
             bu.push_back(0.0);
@@ -1119,7 +1162,7 @@ pe3d_status enqueue_chain(const BatchPlan& P, const std::vector<BatchPlan::Group
     for (int k = 0; k < g.maxsteps; ++k) {
       for (auto& c : g.u) {
         int ni = c.nitems_at[k];
-        if (ni > 0 && launch_depth_update(nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
+        if (ni > 0 && launch_medium_update(nullptr, P.d_descs, c.d_items, ni, k, st) != hipSuccess)
           return PE3D_EDEVICE;
       }
       for (auto& c : g.a) {

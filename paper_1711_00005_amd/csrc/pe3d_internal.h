@@ -48,8 +48,16 @@ struct ProbDesc {
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
   double cbs_re, cbs_im;  // beta_+ h / nbmh, off-diagonal of the scaled depth RHS
-  int bconv[2];         // per chain: rows >= bconv hold the tail values below
-  double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
+  const void* rowk;     // RowK of the row block (below)
+  // range-dependent water: nsr >= 2 profile rows at ranges sr0 + i sdr, one
+  // block of tables (tabG, tabC, tabP, rec, rowk) per row, row_stride bytes
+  // apart from the row-0 pointers above; *srow is the row of the current
+  // step (written by the medium update before every depth pass).  nsr == 0:
+  // one block, srow unused.
+  int nsr;
+  double sr0, sdr;
+  long long row_stride;
+  int* srow;
   // azimuth pass (pass B): W lanes per depth line, NC <= W chunks of M azimuths
   int wb;               // W, lanes per depth line (power of two, 1..64)
   int nc;               // NC = ceil(nth / M)
@@ -62,6 +70,13 @@ struct ProbDesc {
   int nx2d;             // N x 2D mode (Y = 0): pass A writes the caller's field on
                         //   the last step, the first step reads it unchanged, and
                         //   pass B is not launched
+};
+
+// Per-row constants of the depth pass: per chain, rows >= bconv hold the
+// converged tail's Gh (gt) and RHS diagonal / nbmh (ct).
+struct RowK {
+  int bconv[2];
+  double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
 };
 
 struct WorkItem {
@@ -96,9 +111,10 @@ int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pas
 hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                          int nitems, int koff, int lds, hipStream_t st);
 int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
-// water nodes at r_{j+1} of every column of problems with range rows (single:
-// one problem; else nitems items of 256 columns each)
-hipError_t launch_depth_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+// the medium of the step at r_{j+1} for problems with range rows: the water
+// nodes of every column (depth rows) and the water-profile row (water rows)
+// (single: one problem; else nitems items of 256 columns each)
+hipError_t launch_medium_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                                int nitems, int koff, hipStream_t st);
 hipError_t launch_advance(long long* const* jdevs_dev, const int* adds_dev, int n,
                           long long* jsingle, int add, hipStream_t st);

@@ -192,7 +192,7 @@ __device__ __forceinline__ double sigma_of(const ProbDesc& d, long long j) {
   return d.dr / (4.0 * d.k0 * r * r * d.dth * d.dth);
 }
 // Water nodes of column m at range r_{j+1} when the depth has range rows
-// (the per-step matrix update of Fig. 2; depth_update writes them for the
+// (the per-step matrix update of Fig. 2; the medium update writes them for the
 // depth pass): D(r) between the column's depths at
 // the rows r_i = br0 + i bdr (slope * (r - r_i) + D_i inside an interval, D_i
 // at a node, the end values outside), then #{l = 1..nz : l dz <= D}.  Every
@@ -363,6 +363,15 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // the column's water nodes (they set the lane roles) are read first, so
   // that their latency overlaps the staging
   const int nw_early = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
+  // with water rows, the step's row selects the block of tables (uniform)
+  const long long roff =
+      d.nsr ? (long long)(*(const __attribute__((address_space(1))) int*)d.srow) * d.row_stride : 0;
+  const char* const tabG = (const char*)d.tabG + roff;
+  const char* const tabC = (const char*)d.tabC + roff;
+  const char* const tabP = (const char*)d.tabP + roff;
+  const char* const trec = (const char*)d.rec + roff;
+  const __attribute__((address_space(1))) RowK* const rk =
+      (const __attribute__((address_space(1))) RowK*)((const char*)d.rowk + roff);
   for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
     const int c = i / (2 * GA);
     const int g = i - c * 2 * GA;
@@ -477,7 +486,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   }
 
   // ---- lane role: the column's water nodes nw (at r_{j+1}, written by
-  //      depth_update before this launch, when the depth depends on range)
+  //      the medium update before this launch, when the depth depends on range)
   //      set its interface row k and record
   const int nw = nw_early;
   const int k = min(max(nw - 1, 0), N - 2);
@@ -514,15 +523,15 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // them (wtab false) runs the sweeps with the constants instead of reads
   // (the tables hold the same values, so both forms give the same numbers).
   const int jlo = (top || bot) ? max(sc - tc * M, 0) : M;
-  const int jhi = (top || bot) ? min(max(d.bconv[tb] + sc - tc * M, jlo), M) : M;
+  const int jhi = (top || bot) ? min(max(rk->bconv[tb] + sc - tc * M, jlo), M) : M;
   const bool wtab = __ballot(jlo < jhi) != 0;
   auto G_at = [&](auto tab, int j, const D& after) {
     if constexpr (decltype(tab)::value) {
       unsigned o = offb[j];
       asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(d.tabG, o);
+      return gload_b(tabG, o);
     } else {
-      D v = j < jlo ? zero<double>() : mk<double>(d.gt_re[tb], d.gt_im[tb]);
+      D v = j < jlo ? zero<double>() : mk<double>(rk->gt_re[tb], rk->gt_im[tb]);
       asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));  // same order as the reads
       return v;
     }
@@ -531,21 +540,21 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     if constexpr (decltype(tab)::value) {
       unsigned o = offb[j];
       asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(d.tabC, o);
+      return gload_b(tabC, o);
     } else {
-      D v = j < jlo ? zero<double>() : mk<double>(d.ct_re[tb], d.ct_im[tb]);
+      D v = j < jlo ? zero<double>() : mk<double>(rk->ct_re[tb], rk->ct_im[tb]);
       asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));
       return v;
     }
   };
   // the head lanes' interface coefficients: RHS diagonal, previous and next
   // coefficient, elimination multiplier, then the two inverse entries
-  const unsigned hoff = unsigned(nw * 12 + (bot ? 6 : 0)) * 16u;  // byte offset in d.rec
-  auto hrec = [&](int q) { return gload_b(d.rec, hoff + unsigned(q) * 16u); };
+  const unsigned hoff = unsigned(nw * 12 + (bot ? 6 : 0)) * 16u;  // byte offset in the records
+  auto hrec = [&](int q) { return gload_b(trec, hoff + unsigned(q) * 16u); };
 
   const D cbs = mk<double>(d.cbs_re, d.cbs_im);
   D tp = zero<double>();
-  if (top || bot) tp = gload_b(d.tabP, unsigned((tb * (M + 1) + sc) * L + tc) * 16u);
+  if (top || bot) tp = gload_b(tabP, unsigned((tb * (M + 1) + sc) * L + tc) * 16u);
   __syncthreads();
 
   // Table values are prefetched PF slots ahead.
@@ -626,7 +635,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   auto G2_at = [&](int j, const D& after) {
     unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
     asm volatile("" : "+v"(o) : "v"(after.re));
-    return gload_b(d.tabG, o);
+    return gload_b(tabG, o);
   };
   {
     D yh = cin;
@@ -1069,16 +1078,30 @@ __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_batch(co
 // Water nodes of every column at r_{j+1}, j = the problem's step counter +
 // koff, for a problem whose depth has range rows: one thread per column,
 // launched before the depth pass of the step.
-__global__ void depth_update_single(ProbDesc d, int koff) {
-  const int m = blockIdx.x * 256 + threadIdx.x;
-  if (m < d.nth) d.nwcol[m] = water_nodes_at(d, m, *d.jdev + koff);
+// Water-profile row in force at r_{j+1}: the last row whose range
+// sr0 + i sdr (correctly rounded, as in a plain evaluation) is <= r_{j+1},
+// row 0 before the first; a first guess, then exact comparisons.
+__device__ __forceinline__ int ssp_row_at(const ProbDesc& d, long long j) {
+  const double r = __dadd_rn(d.r0, __dmul_rn(double(j + 1), d.dr));
+  auto node = [&](int i) { return __dadd_rn(d.sr0, __dmul_rn(double(i), d.sdr)); };
+  const int nr = d.nsr;
+  int i = int(fmin(fmax(floor(__ddiv_rn(__dsub_rn(r, d.sr0), d.sdr)), 0.0), double(nr - 1)));
+  while (i > 0 && node(i) > r) --i;
+  while (i < nr - 1 && node(i + 1) <= r) ++i;
+  return i;
 }
-__global__ void depth_update_batch(const ProbDesc* __restrict__ descs, const WorkItem* __restrict__ items,
-                                   int koff) {
+
+__device__ __forceinline__ void medium_update(const ProbDesc& d, int tile, int koff) {
+  const long long j = *d.jdev + koff;
+  const int m = tile * 256 + threadIdx.x;
+  if (d.nbr && m < d.nth) d.nwcol[m] = water_nodes_at(d, m, j);
+  if (d.nsr && tile == 0 && threadIdx.x == 0) *d.srow = ssp_row_at(d, j);
+}
+__global__ void medium_update_single(ProbDesc d, int koff) { medium_update(d, blockIdx.x, koff); }
+__global__ void medium_update_batch(const ProbDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                    int koff) {
   const WorkItem it = items[blockIdx.x];
-  const ProbDesc& d = descs[it.prob];
-  const int m = it.tile * 256 + threadIdx.x;
-  if (m < d.nth) d.nwcol[m] = water_nodes_at(d, m, *d.jdev + koff);
+  medium_update(descs[it.prob], it.tile, koff);
 }
 
 __global__ void advance_kernel(long long* const* jdevs, const int* adds, int n, long long* js,
@@ -1244,12 +1267,13 @@ hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_des
                    : run_b_batch<double>(d_descs, items, nitems, koff, lds, st);
 }
 
-hipError_t launch_depth_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
+hipError_t launch_medium_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                                int nitems, int koff, hipStream_t st) {
   if (single)
-    hipLaunchKernelGGL(depth_update_single, dim3((single->nth + 255) / 256), dim3(256), 0, st, *single, koff);
+    hipLaunchKernelGGL(medium_update_single, dim3(single->nbr ? (single->nth + 255) / 256 : 1), dim3(256), 0, st,
+                       *single, koff);
   else
-    hipLaunchKernelGGL(depth_update_batch, dim3(nitems), dim3(256), 0, st, d_descs, items, koff);
+    hipLaunchKernelGGL(medium_update_batch, dim3(nitems), dim3(256), 0, st, d_descs, items, koff);
   return hipGetLastError();
 }
 

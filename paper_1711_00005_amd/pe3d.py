@@ -51,7 +51,8 @@ class pe3d_env(ct.Structure):
                 ("n_bathy", ct.c_int32),
                 ("bathy_theta", ct.POINTER(ct.c_double)), ("bathy_depth", ct.POINTER(ct.c_double)),
                 ("n_bathy_r", ct.c_int32), ("bathy_r0", ct.c_double), ("bathy_dr", ct.c_double),
-                ("zmax", ct.c_double), ("floor", ct.c_int32)]
+                ("zmax", ct.c_double), ("floor", ct.c_int32),
+                ("n_ssp_r", ct.c_int32), ("ssp_r0", ct.c_double), ("ssp_dr", ct.c_double)]
 
 
 class pe3d_grid(ct.Structure):
@@ -127,13 +128,22 @@ def _darr(vals):
 def make_env(env):
     """ctypes pe3d_env from any object with the Env attributes; returns the
     struct and the arrays it points to (keep both alive across the call)."""
+    # the C side reads ssp_c and bathy_depth as (rows x samples) arrays
+    nsr = max(int(getattr(env, "ssp_nr", 0)), 1)
+    nbr = max(int(getattr(env, "bathy_nr", 0)), 1)
+    if len(env.ssp_c) != nsr * len(env.ssp_z):
+        raise ValueError(f"ssp_c holds {len(env.ssp_c)} speeds, expected {nsr} x {len(env.ssp_z)}")
+    if len(env.bathy_depth) != nbr * len(env.bathy_theta):
+        raise ValueError(f"bathy_depth holds {len(env.bathy_depth)} depths, expected {nbr} x "
+                         f"{len(env.bathy_theta)}")
     keep = [_darr(env.ssp_z), _darr(env.ssp_c), _darr(env.bathy_theta), _darr(env.bathy_depth)]
     s = pe3d_env(c0=env.c0, n_ssp=len(env.ssp_z), ssp_z=keep[0], ssp_c=keep[1],
                  rho_w=env.rho_w, atten_w=env.atten_w, c_b=env.c_b, rho_b=env.rho_b,
                  atten_b=env.atten_b, n_bathy=len(env.bathy_theta), bathy_theta=keep[2],
                  bathy_depth=keep[3], n_bathy_r=int(getattr(env, "bathy_nr", 0)),
                  bathy_r0=float(getattr(env, "bathy_r0", 0.0)), bathy_dr=float(getattr(env, "bathy_dr", 0.0)),
-                 zmax=env.zmax, floor=int(env.floor))
+                 zmax=env.zmax, floor=int(env.floor), n_ssp_r=int(getattr(env, "ssp_nr", 0)),
+                 ssp_r0=float(getattr(env, "ssp_r0", 0.0)), ssp_dr=float(getattr(env, "ssp_dr", 0.0)))
     return s, keep
 
 

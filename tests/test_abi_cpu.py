@@ -91,6 +91,38 @@ def test_create_rejects_invalid_arguments_without_a_device(P):
     assert _status(P, env, sec) != P.PE3D_EINVAL
 
 
+def test_water_rows_are_validated(P):
+    from dataclasses import replace
+    env = W.random_ssp_range_env(5, nr=3)
+    g = W.Grid(nz=64, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    assert _status(P, env, g) != P.PE3D_EINVAL
+    c = list(env.ssp_c)
+    bad = [replace(env, ssp_dr=0.0), replace(env, ssp_dr=float("nan")), replace(env, ssp_r0=float("inf")),
+           replace(env, ssp_c=tuple(c[:-1] + [float("nan")])), replace(env, ssp_c=tuple(c[:5] + [-1.0] + c[6:]))]
+    for e in bad:
+        assert _status(P, e, g) == P.PE3D_EINVAL, e
+    e = replace(env, ssp_nr=-1, ssp_c=tuple(c[:len(env.ssp_z)]))
+    assert _status(P, e, g) == P.PE3D_EINVAL
+    # the binding refuses arrays whose length does not match the row count
+    with pytest.raises(ValueError):
+        _status(P, replace(env, ssp_c=tuple(c[:-1])), g)
+    with pytest.raises(ValueError):
+        _status(P, replace(W.random_range_env(5, nr=3), bathy_nr=4), g)
+
+
+def test_footprint_counts_one_table_block_per_water_row(P):
+    from dataclasses import replace
+    g = W.Grid(nz=2048, ntheta=512, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    one = W.wedge_env()
+    fp = {}
+    for nr in (1, 2, 5):
+        e = replace(one, ssp_c=one.ssp_c * nr, ssp_nr=nr if nr > 1 else 0, ssp_r0=0.0, ssp_dr=1000.0)
+        fp[nr] = P.pe3d_footprint(e, g, 100.0)
+    block = fp[2] - fp[1]
+    assert 0 < block < 2 * 1024 * 1024
+    assert fp[5] - fp[1] == 4 * block
+
+
 def test_create_reports_unsupported_sizes(P):
     env = W.wedge_env()
     assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED

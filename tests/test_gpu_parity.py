@@ -385,6 +385,84 @@ def test_config4_batch_matches_oracle_on_samples(torch, P):
         m.close()
 
 
+# ---------------------------------------------------------------- range-dependent water
+WATER = [
+    # name, env, grid kwargs, f, steps of the successive calls
+    ("wr_periodic", W.random_ssp_range_env(51, nr=5, row_dr=20.0),
+     dict(nz=60, ntheta=12, theta0=0.0, width=W.TWO_PI, dr=5.0), 40.0, (3, 14)),
+    ("wr_sector_r0", W.random_ssp_range_env(52, nr=4, row_dr=15.0, r0=30.0, floor=W.FLOOR_RIGID),
+     dict(nz=45, ntheta=7, theta0=1.0, width=1.0, dr=4.0, r0=22.0), 50.0, (1, 8, 12)),
+    ("wr_with_depth_rows", W.random_ssp_range_env(53, nr=6, row_dr=12.0, depth_rows=5),
+     dict(nz=70, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=4.0), 45.0, (7, 10)),
+    ("wr_multi_tile", W.random_ssp_range_env(54, zmax=600.0, nr=4, row_dr=30.0),
+     dict(nz=300, ntheta=70, theta0=0.3, width=W.TWO_PI, dr=10.0), 60.0, (4, 5)),
+]
+
+
+@pytest.mark.parametrize("mode", [W.MODE_3D, W.MODE_NX2D])
+@pytest.mark.parametrize("prec", [W.PREC_C128, W.PREC_C64])
+@pytest.mark.parametrize("case", WATER, ids=[c[0] for c in WATER])
+def test_range_dependent_water_matches_oracle(torch, P, case, prec, mode):
+    """Water profiles on range rows (a stair-step in range): every step uses
+    the row in force at r_{j+1}, also when r_{j+1} is a row's range exactly;
+    the march is split over several calls."""
+    name, env, gk, f, calls = case
+    grid = W.Grid(precision=prec, mode=mode, **gk)
+    st = O.setup(env, grid, f)
+    rows = {st.ssp_row_at(st.r(j + 1)) for j in range(sum(calls))}
+    assert len(rows) >= 3, rows  # the march crosses rows
+    th = st.theta[:, None]
+    u0 = O.starter(st, 0.3 * env.zmax) * (1 + 0.3 * np.cos(th)) + 0.05 * W.random_field(1, grid.nz, _seed(name))
+    say("range-dependent water", name, prec, mode)
+    m = P.Pe3d(env, grid, f)
+    u = to_dev(torch, u0, prec)
+    for n in calls:
+        m.march(n, u)
+    torch.cuda.synchronize()
+    ref = O.march(st, u0, 0, sum(calls))
+    assert O.rel_l2(to_host(torch, u), ref) < TOL[prec], name
+    m.close()
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_equal_water_rows_are_bitwise_range_independent(torch, P, prec):
+    base = W.wedge_env()
+    rd = dataclasses.replace(base, ssp_c=base.ssp_c * 3, ssp_nr=3, ssp_r0=0.0, ssp_dr=20.0)
+    grid = W.Grid(nz=400, ntheta=64, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec)
+    st = O.setup(base, grid, 60.0)
+    u0 = to_dev(torch, O.starter(st, 100.0), prec)
+    say("equal water rows", prec)
+    out = []
+    for env in (base, rd):
+        m = P.Pe3d(env, grid, 60.0)
+        u = u0.clone()
+        m.march(9, u)
+        out.append(u)
+        m.close()
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_full_size_front_matches_oracle(torch, P, prec):
+    """The config-2 grid (Nz 2048, Ntheta 512) over the wedge under the
+    range-dependent water of an ocean front (a profile every 1 km), started
+    at r0 = 980 m: the second step reaches the 1 km row exactly and the
+    march continues on it; 4 steps against the oracle over the whole field."""
+    p = W.config2_front(nsteps=4, precision=prec)
+    grid = dataclasses.replace(p.grid, r0=980.0)
+    st = O.setup(p.env, grid, p.f_hz)
+    assert [st.ssp_row_at(st.r(j + 1)) for j in range(4)] == [0, 1, 1, 1]
+    u0 = O.starter(st, p.zs)
+    say("full-size front", prec)
+    m = P.Pe3d(p.env, grid, p.f_hz)
+    u = to_dev(torch, u0, prec)
+    m.march(4, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, 4)) < TOL[prec]
+    m.close()
+
+
 @pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
 def test_full_size_sloping_bottom_matches_oracle(torch, P, prec):
     """The config-2 grid (Nz 2048, Ntheta 512) over the range-dependent
@@ -462,8 +540,10 @@ def test_batch_schedules_are_bitwise_equal(torch, P, schedule, chains, group_byt
         (RANGE[2][1], W.Grid(precision=prec, **RANGE[2][2]), RANGE[2][3]),
         (W.wedge_env(), W.Grid(nz=700, ntheta=64, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 60.0),
         (W.wedge_env(), W.Grid(nz=90, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=10.0, precision=prec), 25.0),
+        (WATER[2][1], W.Grid(precision=prec, **WATER[2][2]), WATER[2][3]),
+        (WATER[0][1], W.Grid(precision=prec, mode=W.MODE_NX2D, **WATER[0][2]), WATER[0][3]),
     ]
-    steps = [7, 5, 9, 12, 6, 0]
+    steps = [7, 5, 9, 12, 6, 0, 11, 8]
     u0s = []
     for env, grid, f in probs:
         st = O.setup(env, grid, f)
