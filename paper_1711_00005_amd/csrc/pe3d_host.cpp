@@ -486,11 +486,11 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
 }
 
 // Device image of a handle: one block of depth-pass tables per water row
-// (tabG, tabC, tabP, the interface records, RowK), then the column depths at
+// (tabG, tabC, tabP, the interface records), then the column depths at
 // the depth rows, the water nodes per column, the current water row and the
 // step counter.  Coefficient tables are FP64 in both precisions.
 struct Layout {
-  size_t o_G, o_C, o_P, o_rec, o_rk, row_bytes;  // within a row block
+  size_t o_G, o_C, o_P, o_rec, row_bytes;  // within a row block
   size_t o_dc, o_k, o_srow, o_j, total;          // in the image
 };
 Layout layout(const Built& b) {
@@ -500,8 +500,7 @@ Layout layout(const Built& b) {
   y.o_C = y.o_G + 2 * (size_t)b.ma * b.lt * csz;
   y.o_P = y.o_C + 2 * (size_t)b.ma * b.lt * csz;
   y.o_rec = y.o_P + 2 * (size_t)(b.ma + 1) * b.lpc * csz;
-  y.o_rk = y.o_rec + (size_t)(b.N + 1) * 12 * csz;
-  y.row_bytes = (y.o_rk + sizeof(RowK) + 255) & ~size_t(255);
+  y.row_bytes = (y.o_rec + (size_t)(b.N + 1) * 12 * csz + 255) & ~size_t(255);
   y.o_dc = y.row_bytes * (size_t)std::max(b.nsr, 1);
   y.o_k = y.o_dc + (size_t)b.NT * b.nbr * sizeof(double);
   y.o_srow = y.o_k + (size_t)b.NT * sizeof(int);
@@ -776,16 +775,6 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     pack<double>(t.tabC, img, ob + y.o_C);
     pack<double>(t.tabP, img, ob + y.o_P);
     pack<double>(recflat, img, ob + y.o_rec);
-    RowK rk;
-    std::memset(&rk, 0, sizeof rk);
-    for (int ch = 0; ch < 2; ++ch) {
-      rk.bconv[ch] = t.bconv[ch];
-      rk.gt_re[ch] = t.gtail[ch].real();
-      rk.gt_im[ch] = t.gtail[ch].imag();
-      rk.ct_re[ch] = t.ctail[ch].real();
-      rk.ct_im[ch] = t.ctail[ch].imag();
-    }
-    std::memcpy(img.data() + ob + y.o_rk, &rk, sizeof rk);
   }
   if (!b.dcol.empty()) std::memcpy(img.data() + y.o_dc, b.dcol.data(), b.dcol.size() * sizeof(double));
   std::memcpy(img.data() + y.o_k, b.nw.data(), b.NT * sizeof(int));
@@ -839,7 +828,6 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.tabC = base + y.o_C;
   d.tabP = base + y.o_P;
   d.rec = base + y.o_rec;
-  d.rowk = base + y.o_rk;
   d.nwcol = reinterpret_cast<int*>(base + y.o_k);
   d.dcol = b.nbr ? reinterpret_cast<const double*>(base + y.o_dc) : nullptr;
   d.nbr = b.nbr;
@@ -850,6 +838,18 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.sdr = b.sdr;
   d.row_stride = (long long)y.row_bytes;
   d.srow = reinterpret_cast<int*>(base + y.o_srow);
+  // tail constants: the bottom chain's are the same in every water row (the
+  // bottom half-space does not depend on the water profile); the water
+  // chain's differ between rows, so with water rows the depth pass reads its
+  // tables throughout (a tail row starts at nz - 1, past the last chain row)
+  for (int ch = 0; ch < 2; ++ch) {
+    d.bconv[ch] = b.bconv[ch];
+    d.gt_re[ch] = b.gtail[ch].real();
+    d.gt_im[ch] = b.gtail[ch].imag();
+    d.ct_re[ch] = b.ctail[ch].real();
+    d.ct_im[ch] = b.ctail[ch].imag();
+  }
+  if (b.nsr) d.bconv[0] = b.N - 1;
   d.h = b.h;
   d.qb_re = b.qb.real();
   d.qb_im = b.qb.imag();

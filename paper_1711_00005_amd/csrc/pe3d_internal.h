@@ -48,12 +48,15 @@ struct ProbDesc {
   double bp_re, bp_im;  // beta_+ = (1 + i k0 dr)/4
   double bm_re, bm_im;  // beta_- = (1 - i k0 dr)/4
   double cbs_re, cbs_im;  // beta_+ h / nbmh, off-diagonal of the scaled depth RHS
-  const void* rowk;     // RowK of the row block (below)
+  int bconv[2];         // per chain: rows >= bconv hold the tail values below
+  double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
   // range-dependent water: nsr >= 2 profile rows at ranges sr0 + i sdr, one
-  // block of tables (tabG, tabC, tabP, rec, rowk) per row, row_stride bytes
-  // apart from the row-0 pointers above; *srow is the row of the current
-  // step (written by the medium update before every depth pass).  nsr == 0:
-  // one block, srow unused.
+  // block of tables (tabG, tabC, tabP, rec) per row, row_stride bytes apart
+  // from the row-0 pointers above; *srow is the row of the current step
+  // (written by the medium update before every depth pass).  The bottom
+  // chain (chain 1) is the same in every row; the water chain's tail
+  // constants are not used (bconv[0] = nz - 1).  nsr == 0: one block, srow
+  // unused.
   int nsr;
   double sr0, sdr;
   long long row_stride;
@@ -70,13 +73,6 @@ struct ProbDesc {
   int nx2d;             // N x 2D mode (Y = 0): pass A writes the caller's field on
                         //   the last step, the first step reads it unchanged, and
                         //   pass B is not launched
-};
-
-// Per-row constants of the depth pass: per chain, rows >= bconv hold the
-// converged tail's Gh (gt) and RHS diagonal / nbmh (ct).
-struct RowK {
-  int bconv[2];
-  double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
 };
 
 struct WorkItem {

@@ -370,8 +370,6 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const char* const tabC = (const char*)d.tabC + roff;
   const char* const tabP = (const char*)d.tabP + roff;
   const char* const trec = (const char*)d.rec + roff;
-  const __attribute__((address_space(1))) RowK* const rk =
-      (const __attribute__((address_space(1))) RowK*)((const char*)d.rowk + roff);
   for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
     const int c = i / (2 * GA);
     const int g = i - c * 2 * GA;
@@ -523,7 +521,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // them (wtab false) runs the sweeps with the constants instead of reads
   // (the tables hold the same values, so both forms give the same numbers).
   const int jlo = (top || bot) ? max(sc - tc * M, 0) : M;
-  const int jhi = (top || bot) ? min(max(rk->bconv[tb] + sc - tc * M, jlo), M) : M;
+  const int jhi = (top || bot) ? min(max(d.bconv[tb] + sc - tc * M, jlo), M) : M;
   const bool wtab = __ballot(jlo < jhi) != 0;
   auto G_at = [&](auto tab, int j, const D& after) {
     if constexpr (decltype(tab)::value) {
@@ -531,7 +529,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       asm volatile("" : "+v"(o) : "v"(after.re));
       return gload_b(tabG, o);
     } else {
-      D v = j < jlo ? zero<double>() : mk<double>(rk->gt_re[tb], rk->gt_im[tb]);
+      D v = j < jlo ? zero<double>() : mk<double>(d.gt_re[tb], d.gt_im[tb]);
       asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));  // same order as the reads
       return v;
     }
@@ -542,7 +540,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       asm volatile("" : "+v"(o) : "v"(after.re));
       return gload_b(tabC, o);
     } else {
-      D v = j < jlo ? zero<double>() : mk<double>(rk->ct_re[tb], rk->ct_im[tb]);
+      D v = j < jlo ? zero<double>() : mk<double>(d.ct_re[tb], d.ct_im[tb]);
       asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));
       return v;
     }
