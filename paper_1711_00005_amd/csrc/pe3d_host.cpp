@@ -487,11 +487,11 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
 
 // Device image of a handle: one block of depth-pass tables per water row
 // (tabG, tabC, tabP, the interface records), then the column depths at
-// the depth rows, the water nodes per column, the current water row and the
-// step counter.  Coefficient tables are FP64 in both precisions.
+// the depth rows, the water nodes per column, the table pointers of the
+// current step and the step counter.  Coefficient tables are FP64 in both precisions.
 struct Layout {
   size_t o_G, o_C, o_P, o_rec, row_bytes;  // within a row block
-  size_t o_dc, o_k, o_srow, o_j, total;          // in the image
+  size_t o_dc, o_k, o_cur, o_j, total;           // in the image
 };
 Layout layout(const Built& b) {
   const size_t csz = 16;
@@ -503,8 +503,8 @@ Layout layout(const Built& b) {
   y.row_bytes = (y.o_rec + (size_t)(b.N + 1) * 12 * csz + 255) & ~size_t(255);
   y.o_dc = y.row_bytes * (size_t)std::max(b.nsr, 1);
   y.o_k = y.o_dc + (size_t)b.NT * b.nbr * sizeof(double);
-  y.o_srow = y.o_k + (size_t)b.NT * sizeof(int);
-  y.o_j = (y.o_srow + sizeof(int) + 255) & ~size_t(255);
+  y.o_cur = (y.o_k + (size_t)b.NT * sizeof(int) + 63) & ~size_t(63);
+  y.o_j = (y.o_cur + sizeof(TabPtrs) + 255) & ~size_t(255);
   y.total = y.o_j + 256;
   return y;
 }
@@ -799,6 +799,16 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     delete h;
     return PE3D_ENOMEM;
   }
+  {
+    // the current step's tables start as row 0's (device addresses)
+    unsigned char* dbase = static_cast<unsigned char*>(h->d_tables);
+    TabPtrs t0;
+    t0.tabG = dbase + y.o_G;
+    t0.tabC = dbase + y.o_C;
+    t0.tabP = dbase + y.o_P;
+    t0.rec = dbase + y.o_rec;
+    std::memcpy(img.data() + y.o_cur, &t0, sizeof t0);
+  }
   if (upload(h->d_tables, img.data(), tb) != hipSuccess) {
     (void)hipFree(h->d_tables);
     (void)hipFree(h->d_scr);
@@ -837,7 +847,7 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
   d.sr0 = b.sr0;
   d.sdr = b.sdr;
   d.row_stride = (long long)y.row_bytes;
-  d.srow = reinterpret_cast<int*>(base + y.o_srow);
+  d.cur = reinterpret_cast<TabPtrs*>(base + y.o_cur);
   // tail constants: the bottom chain's are the same in every water row (the
   // bottom half-space does not depend on the water profile); the water
   // chain's differ between rows, so with water rows the depth pass reads its

@@ -11,6 +11,14 @@ struct alignas(2 * sizeof(R)) cplx {
   R re, im;
 };
 
+// The depth-pass tables of the current step (see ProbDesc::cur).
+struct TabPtrs {
+  const void* tabG;
+  const void* tabC;
+  const void* tabP;
+  const void* rec;
+};
+
 // Everything a kernel needs to march one problem.  Plain data; passed by
 // value as a kernel argument (single-problem launches) or stored in a device
 // array (batched launches).
@@ -52,15 +60,15 @@ struct ProbDesc {
   double gt_re[2], gt_im[2], ct_re[2], ct_im[2];
   // range-dependent water: nsr >= 2 profile rows at ranges sr0 + i sdr, one
   // block of tables (tabG, tabC, tabP, rec) per row, row_stride bytes apart
-  // from the row-0 pointers above; *srow is the row of the current step
-  // (written by the medium update before every depth pass).  The bottom
-  // chain (chain 1) is the same in every row; the water chain's tail
-  // constants are not used (bconv[0] = nz - 1).  nsr == 0: one block, srow
-  // unused.
+  // from the row-0 pointers above.  The depth pass reads the tables of the
+  // current step through *cur (the medium update points it at the step's
+  // row before every depth pass; it holds the row-0 pointers from create
+  // time on).  The bottom chain (chain 1) is the same in every row; the
+  // water chain's tail constants are not used (bconv[0] = nz - 1).
   int nsr;
   double sr0, sdr;
   long long row_stride;
-  int* srow;
+  TabPtrs* cur;
   // azimuth pass (pass B): W lanes per depth line, NC <= W chunks of M azimuths
   int wb;               // W, lanes per depth line (power of two, 1..64)
   int nc;               // NC = ceil(nth / M)

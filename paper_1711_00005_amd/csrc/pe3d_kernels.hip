@@ -363,13 +363,13 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // the column's water nodes (they set the lane roles) are read first, so
   // that their latency overlaps the staging
   const int nw_early = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
-  // with water rows, the step's row selects the block of tables (uniform)
-  const long long roff =
-      d.nsr ? (long long)(*(const __attribute__((address_space(1))) int*)d.srow) * d.row_stride : 0;
-  const char* const tabG = (const char*)d.tabG + roff;
-  const char* const tabC = (const char*)d.tabC + roff;
-  const char* const tabP = (const char*)d.tabP + roff;
-  const char* const trec = (const char*)d.rec + roff;
+  // the tables of this step's water row (uniform scalar loads)
+  const __attribute__((address_space(4))) TabPtrs* const tcur =
+      (const __attribute__((address_space(4))) TabPtrs*)d.cur;
+  const void* const tabG = tcur->tabG;
+  const void* const tabC = tcur->tabC;
+  const void* const tabP = tcur->tabP;
+  const void* const trec = tcur->rec;
   for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
     const int c = i / (2 * GA);
     const int g = i - c * 2 * GA;
@@ -1093,7 +1093,15 @@ __device__ __forceinline__ void medium_update(const ProbDesc& d, int tile, int k
   const long long j = *d.jdev + koff;
   const int m = tile * 256 + threadIdx.x;
   if (d.nbr && m < d.nth) d.nwcol[m] = water_nodes_at(d, m, j);
-  if (d.nsr && tile == 0 && threadIdx.x == 0) *d.srow = ssp_row_at(d, j);
+  if (d.nsr && tile == 0 && threadIdx.x == 0) {
+    const long long off = (long long)ssp_row_at(d, j) * d.row_stride;
+    TabPtrs t;
+    t.tabG = (const char*)d.tabG + off;
+    t.tabC = (const char*)d.tabC + off;
+    t.tabP = (const char*)d.tabP + off;
+    t.rec = (const char*)d.rec + off;
+    *d.cur = t;
+  }
 }
 __global__ void medium_update_single(ProbDesc d, int koff) { medium_update(d, blockIdx.x, koff); }
 __global__ void medium_update_batch(const ProbDesc* __restrict__ descs, const WorkItem* __restrict__ items,
