@@ -284,7 +284,7 @@ template <bool UP>
 __device__ __forceinline__ D scan_excl(D A, D B, int t, int L, D* tot) {
   const int w = L < 64 ? L : 64;
   const int tw = t & (w - 1);
-#pragma unroll
+  #pragma unroll
   for (int dd = 1; dd < 64; dd <<= 1) {
     if (dd < w) {
       const D ap = UP ? shfl_up(A, dd, w) : shfl_down(A, dd, w);
@@ -387,12 +387,12 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     constexpr int MP = (M + 1) / 2;
     const __attribute__((address_space(1))) F4* b4 = (const __attribute__((address_space(1))) F4*)base;
     F4 v2[MP];
-#pragma unroll
+    #pragma unroll
     for (int q = 0; q < MP; ++q) {
       const int e = 2 * (lane + q * kPassAThreads);
       if (e < span) v2[q] = b4[e >> 1];
     }
-#pragma unroll
+    #pragma unroll
     for (int q = 0; q < MP; ++q) {
       const int e = 2 * (lane + q * kPassAThreads);
       if (e < span) {
@@ -404,14 +404,14 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     }
   } else if (!ystage) {
     typename Stage<S>::T v[M];
-#pragma unroll
+    #pragma unroll
     for (int q = 0; q < M; ++q) {
       const int e = lane + q * kPassAThreads;
       if (e < span) v[q] = stage_load(base, e);
     }
     // LDS index of span entry e (column c = e / N, row e - c N): c CS + GA + e - c N
     if (cpw == 1) {
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane + q * kPassAThreads;
         if (e < span) buf[GA + e] = stage_val(v[q]);
@@ -419,7 +419,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     } else if (N >= kPassAThreads) {
       // e advances by 256 <= N per entry: the column advances by at most one
       int r = lane, idx = GA + lane;
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         if (lane + q * kPassAThreads < span) buf[idx] = stage_val(v[q]);
         r += kPassAThreads;
@@ -430,7 +430,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         }
       }
     } else {
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane + q * kPassAThreads;
         if (e < span) {
@@ -448,7 +448,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
 #pragma unroll 1
     for (int q0 = 0; q0 < M; q0 += QG) {
       typename Stage<S>::T vc[QG], vl[QG], vr[QG];
-#pragma unroll
+      #pragma unroll
       for (int qq = 0; qq < QG; ++qq) {
         const int e = lane + (q0 + qq) * kPassAThreads;
         if (q0 + qq < M && e < span) {
@@ -466,7 +466,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
           vr[qq] = stage_load(src, (size_t)min(mr, NT - 1) * N + r);
         }
       }
-#pragma unroll
+      #pragma unroll
       for (int qq = 0; qq < QG; ++qq) {
         const int e = lane + (q0 + qq) * kPassAThreads;
         if (q0 + qq < M && e < span) {
@@ -507,7 +507,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   {
     const int lo = tb * M * LT + (M - sc) * LT + tc;  // slot j < sc
     const int hi = tb * M * LT + tc + 1 - sc * LT;    // slot j >= sc
-#pragma unroll
+    #pragma unroll
     for (int j = 0; j < M; ++j) offb[j] = unsigned((j < sc ? lo : hi) + j * LT) * 16u;
   }
   // A prefetch is issued only after the current slot's value `after` exists:
@@ -563,10 +563,16 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      yh_out = tp yh_in + E
   const C<S>* col = buf + cw * CS + GA;
   D Rv[M];
+  // GREG: the lane's multipliers stay in registers from the RHS sweep to the
+  // elimination and back substitution (no further table reads); otherwise
+  // those sweeps read the table again (fewer registers: complex64 with
+  // M >= 15 keeps 3 waves per SIMD that way)
+  constexpr bool GREG = sizeof(S) == 8 || M <= 13;
+  D Gv[GREG ? M : 1];
   D E = zero<double>();
   auto phase1 = [&](auto tab) {
     D gq[PF], cq[PF];
-#pragma unroll
+    #pragma unroll
     for (int j = 0; j < PF; ++j)
       if (j < M) {
         gq[j] = G_at(tab, j, E);
@@ -579,10 +585,11 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     // orders the read after the previous slot's value and is applied to the
     // index, not to a pointer, so the read stays an LDS read
     int rn = row0;
-#pragma unroll
+    #pragma unroll
     for (int j = 0; j < M; ++j) {
       const D g = gq[j % PF];
       const D cdv = cq[j % PF];
+      if constexpr (GREG) Gv[j] = g;
       rn += dir;
       asm volatile("" : "+v"(rn) : "v"(E.re));
       const D wn = to_d(col[rn]);
@@ -626,39 +633,63 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   //      slot's term once the interface value is known.
   D X = zero<double>();
   D pr = one<double>();  // Gh_0 ... Gh_{j-1}
-  // The elimination sweep reads the table in every wavefront; a lane that
-  // needs no entry reads the chain's tail row or a zero row instead (the same
-  // address for many lanes, fewer cache lines per read).
-  const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
-  auto G2_at = [&](int j, const D& after) {
-    unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
-    asm volatile("" : "+v"(o) : "v"(after.re));
-    return gload_b(tabG, o);
-  };
-  {
-    D yh = cin;
-    D gq[PF];
-#pragma unroll
-    for (int j = 0; j < PF; ++j)
-      if (j < M) gq[j] = G2_at(j, yh);
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const D g = gq[j % PF];
-      if (j == M - 1) {
-        D cf = one<double>();
-        if (head) cf = hrec(3);
-        const D y = fma(cf, yh, Rv[j]);
-        Rv[j] = head ? y : mul(g, y);
-        if (!head) X = fma(pr, Rv[j], X);
-      } else {
-        yh = mul(g, add(Rv[j], yh));
-        Rv[j] = yh;
-        X = fma(pr, yh, X);
-        pr = mul(pr, g);
-        // keep the accumulation in slot order (not batched up over the sweep)
-        asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+  if constexpr (GREG) {
+    {
+      D yh = cin;
+      #pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const D g = Gv[j];
+        if (j == M - 1) {
+          D cf = one<double>();
+          if (head) cf = hrec(3);
+          const D y = fma(cf, yh, Rv[j]);
+          Rv[j] = head ? y : mul(g, y);
+          if (!head) X = fma(pr, Rv[j], X);
+        } else {
+          yh = mul(g, add(Rv[j], yh));
+          Rv[j] = yh;
+          X = fma(pr, yh, X);
+          pr = mul(pr, g);
+          // keep the accumulation in slot order (not batched up over the sweep)
+          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+        }
       }
-      if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
+    }
+  } else {
+    // The elimination sweep reads the table in every wavefront; a lane that
+    // needs no entry reads the chain's tail row or a zero row instead (the same
+    // address for many lanes, fewer cache lines per read).
+    const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
+    auto G2_at = [&](int j, const D& after) {
+      unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
+      asm volatile("" : "+v"(o) : "v"(after.re));
+      return gload_b(tabG, o);
+    };
+    {
+      D yh = cin;
+      D gq[PF];
+      #pragma unroll
+      for (int j = 0; j < PF; ++j)
+        if (j < M) gq[j] = G2_at(j, yh);
+      #pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const D g = gq[j % PF];
+        if (j == M - 1) {
+          D cf = one<double>();
+          if (head) cf = hrec(3);
+          const D y = fma(cf, yh, Rv[j]);
+          Rv[j] = head ? y : mul(g, y);
+          if (!head) X = fma(pr, Rv[j], X);
+        } else {
+          yh = mul(g, add(Rv[j], yh));
+          Rv[j] = yh;
+          X = fma(pr, yh, X);
+          pr = mul(pr, g);
+          // keep the accumulation in slot order (not batched up over the sweep)
+          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+        }
+        if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
+      }
     }
   }
   // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
@@ -674,28 +705,43 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // ---- phase 3: back substitution with the exact carry, written to the column
   //      buffer (the input was last read before the interface barrier; zero
   //      slots and idle lanes write guard rows only)
-  auto phase3 = [&](auto tab) {
-    D x = xin;
-    D gq[PF];
-#pragma unroll
-    for (int jj = 0; jj < PF; ++jj)
-      if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
-    C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
-#pragma unroll
-    for (int jj = 0; jj < M; ++jj) {
-      const int j = M - 1 - jj;
-      const D g = gq[jj % PF];
-      if (j == M - 1 && head) x = Rv[j];
-      else x = fma(g, x, Rv[j]);
-      *p = from_d<S>(x);
-      p -= dir;
-      if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
+  if constexpr (GREG) {
+    {
+      D x = xin;
+      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
+      #pragma unroll
+      for (int jj = 0; jj < M; ++jj) {
+        const int j = M - 1 - jj;
+        if (j == M - 1 && head) x = Rv[j];
+        else x = fma(Gv[j], x, Rv[j]);
+        *p = from_d<S>(x);
+        p -= dir;
+      }
     }
-  };
-  if (wtab)
-    phase3(std::true_type{});
-  else
-    phase3(std::false_type{});
+  } else {
+    auto phase3 = [&](auto tab) {
+      D x = xin;
+      D gq[PF];
+      #pragma unroll
+      for (int jj = 0; jj < PF; ++jj)
+        if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
+      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
+      #pragma unroll
+      for (int jj = 0; jj < M; ++jj) {
+        const int j = M - 1 - jj;
+        const D g = gq[jj % PF];
+        if (j == M - 1 && head) x = Rv[j];
+        else x = fma(g, x, Rv[j]);
+        *p = from_d<S>(x);
+        p -= dir;
+        if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
+      }
+    };
+    if (wtab)
+      phase3(std::true_type{});
+    else
+      phase3(std::false_type{});
+  }
   __syncthreads();
   {
     // the staging addresses are recomputed here rather than kept live
@@ -706,7 +752,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       using F4 = float __attribute__((ext_vector_type(4)));
       constexpr int MP = (M + 1) / 2;
       __attribute__((address_space(1))) F4* o4 = (__attribute__((address_space(1))) F4*)out;
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < MP; ++q) {
         const int e = 2 * (lane_r + q * kPassAThreads);
         if (e < span) {
@@ -722,14 +768,14 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         }
       }
     } else if (cpw == 1) {
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
         if (e < span) gstore(out, unsigned(e), buf[GA + e]);
       }
     } else if (N >= kPassAThreads) {
       int r = lane_r, idx = GA + lane_r;
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
         if (e < span) gstore(out, unsigned(e), buf[idx]);
@@ -741,7 +787,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
         }
       }
     } else {
-#pragma unroll
+      #pragma unroll
       for (int q = 0; q < M; ++q) {
         const int e = lane_r + q * kPassAThreads;
         if (e < span) {
@@ -764,7 +810,7 @@ __global__ PE3D_PASS_A_ATTR void pass_a_single(ProbDesc d, int koff) {
 // Batched launch over work items of problems with any M: each workgroup takes
 // the body specialised for its problem's M (a uniform branch).
 template <typename S>
-__global__ PE3D_PASS_A_ATTR __attribute__((amdgpu_waves_per_eu(3))) void pass_a_batch(const ProbDesc* __restrict__ descs,
+__global__ PE3D_PASS_A_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 2 : 3))) void pass_a_batch(const ProbDesc* __restrict__ descs,
                                               const WorkItem* __restrict__ items, int koff) {
   extern __shared__ __align__(16) unsigned char smem_a[];
   const WorkItem it = items[blockIdx.x];
@@ -852,7 +898,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   {
     const unsigned o0 = unsigned(sc0 * M * N + szc);
     C<S> v[MM];
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < slen) v[i] = gload(src, o0 + unsigned(i * N));
     // the step constants are computed while the loads are in flight
@@ -876,7 +922,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       }
     }
     C<S>* Ts = tl + sc0 * CST + sdl * DS;
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < slen) Ts[i] = szok ? v[i] : zero<S>();
   }
@@ -904,7 +950,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     if (c < NC - 1) nxe = to_d(T[CST]);
     else nxe = periodic ? to_d(tl[dl * DS]) : zero<double>();
     D b = vat(0);
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i) {
       if (EQ || i < len) {
         const D nx = (EQ ? (i + 1 < MM) : (i + 1 < len)) ? vat(i + 1 < MM ? i + 1 : i) : nxe;
@@ -921,7 +967,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   {
     D Sv = (c < NC - 1) ? E : zero<double>();
     D lv = K->rM;  // rho^(M dd)
-#pragma unroll
+    #pragma unroll
     for (int l = 0; l < 6; ++l) {
       const int dd = 1 << l;
       if (dd < W) {
@@ -939,7 +985,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     D prev = shfl_up(Sv, 1, W);
     if (c == 0) prev = zero<double>();
     D y = fma(sPowC[c < kPassBPow ? c : 0], y0, prev);
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
         y = fma(rho, y, xr[i]);
@@ -950,12 +996,12 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   //      carries scanned downward over the chunks
   {
     D X = zero<double>();
-#pragma unroll
+    #pragma unroll
     for (int i = MM - 1; i >= 0; --i)
       if (EQ || i < len) X = fma(rho, X, xr[i]);
     D Sv = (c < NC) ? X : zero<double>();
     D lv = K->rM;
-#pragma unroll
+    #pragma unroll
     for (int l = 0; l < 6; ++l) {
       const int dd = 1 << l;
       if (dd < W) {
@@ -969,7 +1015,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     D x;
     if (c >= NC - 1) x = xN;
     else x = fma(mul(sPowC[NC - 2 - c], K->rL), xN, nxt);
-#pragma unroll
+    #pragma unroll
     for (int i = MM - 1; i >= 0; --i)
       if (EQ || i < len) {
         x = fma(rho, x, xr[i]);
@@ -981,7 +1027,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   //      rank-one correction of the first row,
   //      e_m -= Kc (rho^m - rho^{2NT-m}),  Kc = rho^3 x_0 / (1 - rho^{2NT+2})
   if (periodic) {
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
         T[i] = from_d<S>(fma(rho, xr[i], vat(i)));
@@ -993,7 +1039,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     D pa = mul(Kc, sPowC[c < kPassBPow ? c : 0]);
     D pb = mul(Kc, sPowS[c < kPassBPow ? c : 0]);
     const D rinv = K->rinv;
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
         const D e = sub(mul(rho, xr[i]), sub(pa, pb));
@@ -1016,7 +1062,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     else ur = periodic ? to_d(tl[dl * DS]) : zero<double>();
     const double s1 = K->s1;
     D a = ul, b = vat(0);
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
         const D nx = (EQ ? (i + 1 < MM) : (i + 1 < len)) ? vat(i + 1 < MM ? i + 1 : i) : ur;
@@ -1034,7 +1080,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     asm volatile("" : "+v"(sc0r));  // recomputed here rather than kept live through the solve
     const unsigned o0 = unsigned(sc0r * M * N + szc);
     const C<S>* Ts = tl + sc0r * CST + sdl * DS;
-#pragma unroll
+    #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < slen) gstore(dst, o0 + unsigned(i * N), Ts[i]);
   }
