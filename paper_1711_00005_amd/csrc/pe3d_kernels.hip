@@ -88,6 +88,25 @@ __device__ __forceinline__ C<R> shfl_down(C<R> v, int d, int w) {
   return mk<R>(__shfl_down(v.re, d, w), __shfl_down(v.im, d, w));
 }
 
+// Lane moves inside a wavefront through DPP (a VALU operand modifier, no LDS
+// round trip).  CTRL is a DPP control: row_shr:n 0x110+n and row_shl:n
+// 0x100+n (lane i reads lane i-n / i+n of its row of 16), row_bcast:15 0x142
+// and row_bcast:31 0x143 (lane 15 of a row / lane 31 to the rows after it),
+// wave_shr:1 0x138 and wave_shl:1 0x130 (lane i reads lane i-1 / i+1 of the
+// wavefront).  Lanes whose source falls outside the pattern, or whose row is
+// not in ROWMASK, read 0.
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(v)), CTRL, ROWMASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(v >> 32)), CTRL, ROWMASK, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)unsigned(hi) << 32) | unsigned(lo)));
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ C<double> dpp(C<double> v) {
+  return mk<double>(dpp_f64<CTRL, ROWMASK>(v.re), dpp_f64<CTRL, ROWMASK>(v.im));
+}
+
 template <typename R>
 __device__ __forceinline__ C<R> from_d(C<double> z) { return mk<R>(R(z.re), R(z.im)); }
 template <typename R>
@@ -279,24 +298,45 @@ constexpr int kPassAThreads = 256;
 
 // Exclusive scan of the affine lane maps x -> A x + B within a column:
 // UP: lane t receives the composition of lanes 0..t-1 applied to 0; DOWN:
-// of lanes L-1..t+1.  tot: LDS scratch, 2 complex per wavefront.
+// of lanes L-1..t+1.  Inside a wavefront: an inclusive scan within each row
+// of 16 lanes by DPP row shifts (segments of w < 16 lanes lie inside one row),
+// then across rows (UP: DPP row broadcasts of lane 15 and lane 31; DOWN: the
+// first lane of the next row and lane 32 by shuffles), then a DPP shift by
+// one lane.  Columns wider than a wavefront combine the wavefront totals
+// through LDS.  tot: LDS scratch, 2 complex per wavefront.
 template <bool UP>
 __device__ __forceinline__ D scan_excl(D A, D B, int t, int L, D* tot) {
   const int w = L < 64 ? L : 64;
   const int tw = t & (w - 1);
-  #pragma unroll
-  for (int dd = 1; dd < 64; dd <<= 1) {
-    if (dd < w) {
-      const D ap = UP ? shfl_up(A, dd, w) : shfl_down(A, dd, w);
-      const D bq = UP ? shfl_up(B, dd, w) : shfl_down(B, dd, w);
-      if (UP ? (tw >= dd) : (tw + dd < w)) {
-        B = fma(A, bq, B);
-        A = mul(A, ap);
-      }
+  const int h = threadIdx.x & 63;
+  const int pr = h & 15;
+  // the lane's map composed after the neighbour's (ap, bq)
+  auto comb = [&](const D& ap, const D& bq, bool take) {
+    if (take) {
+      B = fma(A, bq, B);
+      A = mul(A, ap);
     }
+  };
+  if (UP) {
+    if (w > 1) comb(dpp<0x111>(A), dpp<0x111>(B), tw >= 1 && pr >= 1);
+    if (w > 2) comb(dpp<0x112>(A), dpp<0x112>(B), tw >= 2 && pr >= 2);
+    if (w > 4) comb(dpp<0x114>(A), dpp<0x114>(B), tw >= 4 && pr >= 4);
+    if (w > 8) comb(dpp<0x118>(A), dpp<0x118>(B), tw >= 8 && pr >= 8);
+    if (w > 16) comb(dpp<0x142, 0xA>(A), dpp<0x142, 0xA>(B), (h & 16) != 0);
+    if (w > 32) comb(dpp<0x143, 0xC>(A), dpp<0x143, 0xC>(B), (h & 32) != 0);
+  } else {
+    if (w > 1) comb(dpp<0x101>(A), dpp<0x101>(B), tw + 1 < w && pr + 1 < 16);
+    if (w > 2) comb(dpp<0x102>(A), dpp<0x102>(B), tw + 2 < w && pr + 2 < 16);
+    if (w > 4) comb(dpp<0x104>(A), dpp<0x104>(B), tw + 4 < w && pr + 4 < 16);
+    if (w > 8) comb(dpp<0x108>(A), dpp<0x108>(B), tw + 8 < w && pr + 8 < 16);
+    if (w > 16) {
+      const int src = (h | 15) + 1;  // first lane of the next row (used by even rows)
+      comb(shfl_idx(A, src, 64), shfl_idx(B, src, 64), (h & 16) == 0);
+    }
+    if (w > 32) comb(shfl_idx(A, 32, 64), shfl_idx(B, 32, 64), (h & 32) == 0);
   }
-  D ea = UP ? shfl_up(A, 1, w) : shfl_down(A, 1, w);
-  D eb = UP ? shfl_up(B, 1, w) : shfl_down(B, 1, w);
+  D ea = UP ? dpp<0x138>(A) : dpp<0x130>(A);
+  D eb = UP ? dpp<0x138>(B) : dpp<0x130>(B);
   if (UP ? (tw == 0) : (tw == w - 1)) {
     ea = one<double>();
     eb = zero<double>();
