@@ -1004,17 +1004,39 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     }
   }
   // ---- forward chunk carries: inclusive scan over chunks 0..NC-2 (length M)
+  // (inside rows of 16 lanes by DPP row shifts, multipliers rho^(M dd); then
+  // from lane 15 / lane 31 by DPP row broadcasts, multiplier rho^(M dist))
+  const int h = tid & 63;
+  const int pr = h & 15;
   {
     D Sv = (c < NC - 1) ? E : zero<double>();
     D lv = K->rM;  // rho^(M dd)
-    #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      const int dd = 1 << l;
-      if (dd < W) {
-        const D up = shfl_up(Sv, dd, W);
-        if (c >= dd) Sv = fma(lv, up, Sv);
-        lv = mul(lv, lv);
-      }
+    if (W > 1) {
+      const D up = dpp<0x111>(Sv);
+      if (c >= 1 && pr >= 1) Sv = fma(lv, up, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 2) {
+      const D up = dpp<0x112>(Sv);
+      if (c >= 2 && pr >= 2) Sv = fma(lv, up, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 4) {
+      const D up = dpp<0x114>(Sv);
+      if (c >= 4 && pr >= 4) Sv = fma(lv, up, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 8) {
+      const D up = dpp<0x118>(Sv);
+      if (c >= 8 && pr >= 8) Sv = fma(lv, up, Sv);
+    }
+    if (W > 16) {
+      const D up = dpp<0x142, 0xA>(Sv);
+      if (h & 16) Sv = fma(sPowC[pr + 1], up, Sv);
+    }
+    if (W > 32) {
+      const D up = dpp<0x143, 0xC>(Sv);
+      if (h & 32) Sv = fma(sPowC[(h & 31) + 1], up, Sv);
     }
     D y0 = zero<double>();  // y_{-1} = y_{NT-1} (periodic)
     if (periodic) {
@@ -1022,7 +1044,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       const D El = shfl_idx(E, seg + NC - 1, 64);
       y0 = mul(fma(K->rL, Sl, El), K->winv);
     }
-    D prev = shfl_up(Sv, 1, W);
+    D prev = dpp<0x138>(Sv);
     if (c == 0) prev = zero<double>();
     D y = fma(sPowC[c < kPassBPow ? c : 0], y0, prev);
     #pragma unroll
@@ -1041,17 +1063,35 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
       if (EQ || i < len) X = fma(rho, X, xr[i]);
     D Sv = (c < NC) ? X : zero<double>();
     D lv = K->rM;
-    #pragma unroll
-    for (int l = 0; l < 6; ++l) {
-      const int dd = 1 << l;
-      if (dd < W) {
-        const D dn = shfl_down(Sv, dd, W);
-        if (c + dd < W) Sv = fma(lv, dn, Sv);
-        lv = mul(lv, lv);
-      }
+    if (W > 1) {
+      const D dn = dpp<0x101>(Sv);
+      if (c + 1 < W && pr + 1 < 16) Sv = fma(lv, dn, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 2) {
+      const D dn = dpp<0x102>(Sv);
+      if (c + 2 < W && pr + 2 < 16) Sv = fma(lv, dn, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 4) {
+      const D dn = dpp<0x104>(Sv);
+      if (c + 4 < W && pr + 4 < 16) Sv = fma(lv, dn, Sv);
+      lv = mul(lv, lv);
+    }
+    if (W > 8) {
+      const D dn = dpp<0x108>(Sv);
+      if (c + 8 < W && pr + 8 < 16) Sv = fma(lv, dn, Sv);
+    }
+    if (W > 16) {  // from the first lane of the next row
+      const D dn = shfl_idx(Sv, (h | 15) + 1, 64);
+      if ((h & 16) == 0) Sv = fma(sPowC[16 - pr], dn, Sv);
+    }
+    if (W > 32) {  // from lane 32
+      const D dn = shfl_idx(Sv, 32, 64);
+      if ((h & 32) == 0) Sv = fma(sPowC[32 - h], dn, Sv);
     }
     const D xN = periodic ? mul(shfl_idx(Sv, seg, 64), K->winv) : zero<double>();  // x_NT = x_0
-    D nxt = shfl_down(Sv, 1, W);
+    D nxt = dpp<0x130>(Sv);
     D x;
     if (c >= NC - 1) x = xN;
     else x = fma(mul(sPowC[NC - 2 - c], K->rL), xN, nxt);
