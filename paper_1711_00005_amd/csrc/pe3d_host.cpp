@@ -668,8 +668,17 @@ hipError_t prof_launch(const char* pass, int prec, int maxm, double bytes, hipSt
   return e;
 }
 
+// A plan's graphs, streams and device tables may still be in use by
+// enqueued work, so the device is drained before a plan is freed.
 void drop_plans_of(pe3d_handle h) {
   std::lock_guard<std::mutex> lk(g_mu);
+  bool any = false;
+  for (auto& kv : g_plans) {
+    auto& hs = kv.second->handles;
+    any = any || std::find(hs.begin(), hs.end(), h) != hs.end();
+  }
+  if (!any) return;
+  (void)hipDeviceSynchronize();
   for (auto it = g_plans.begin(); it != g_plans.end();) {
     auto& hs = it->second->handles;
     if (std::find(hs.begin(), hs.end(), h) != hs.end()) {

@@ -574,6 +574,35 @@ def test_batch_schedules_are_bitwise_equal(torch, P, schedule, chains, group_byt
             m.close()
 
 
+def test_plan_cache_eviction_and_handle_destruction(torch, P):
+    """More distinct batched calls than the plan cache holds (64), with
+    graphs, evict the oldest plans while their handles live on; destroying a
+    handle drops its plans; every call still equals the plain march."""
+    env = W.wedge_env()
+    grids = [W.Grid(nz=64 + 8 * i, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=10.0) for i in range(3)]
+    ms = [P.Pe3d(env, g, 40.0) for g in grids]
+    ref = [P.Pe3d(env, g, 40.0) for g in grids]
+    us = [m.starter(60.0) for m in ms]
+    rs = [m.starter(60.0) for m in ref]
+    say("plan cache eviction")
+    for call in range(70):
+        steps = [1 + call % 5, 1 + (call // 5) % 7, 1 + call % 3]
+        P.march_batch(ms, steps, us, use_graph=True)
+        for m, r, n in zip(ref, rs, steps):
+            m.march(n, r)
+    torch.cuda.synchronize()
+    for a, b in zip(us, rs):
+        assert torch.equal(a, b)
+    ms[1].close()
+    P.march_batch([ms[0], ms[2]], [2, 3], [us[0], us[2]], use_graph=True)
+    ref[0].march(2, rs[0])
+    ref[2].march(3, rs[2])
+    torch.cuda.synchronize()
+    assert torch.equal(us[0], rs[0]) and torch.equal(us[2], rs[2])
+    for m in [ms[0], ms[2]] + ref:
+        m.close()
+
+
 def test_prepared_graph_runs_nothing_then_replays(torch, P):
     """Capture-only (use_graph == 2) leaves fields and step counters alone;
     the next identical call replays it and equals direct launches bitwise."""
