@@ -204,9 +204,9 @@ pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
  * steps, field pointers, schedule), and replayed on later identical calls:
  * chain 0 on `stream`, the others on streams of the plan that wait for
  * `stream`'s prior work, and `stream` then waits for all of them.  A plan
- * must not be replayed by two calls at once (they would share its fields).
- * use_graph == 0 runs the chains one after another on `stream` (this is the
- * form the profiling events time).  use_graph == 2 only builds the plan and
+ * must not be run by two calls at once (they would share its fields and
+ * streams).  use_graph == 0 enqueues the same launches directly, on the same
+ * streams.  use_graph == 2 only builds the plan and
  * captures its graphs (a later call with use_graph == 1 and the same tuple
  * replays them): nothing runs, no field or step counter changes.  Results
  * are bitwise identical to pe3d_march of each problem alone, whatever the
@@ -254,7 +254,8 @@ pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info);
  * pe3d_march and by pe3d_march_batch with use_graph == 0 is bracketed by a
  * pair of HIP events recorded on the launch stream, together with the
  * launch's algorithmic bytes (the field read once and written once over the
- * columns or depth lines the launch covers).  pe3d_profile_read waits for
+ * columns or depth lines the launch covers); with more than one chain in the
+ * batch schedule the chains' launches overlap in time.  pe3d_profile_read waits for
  * those events, writes up to `cap` per-kernel aggregates (in first-launch
  * order) to `stats`, sets *n to the number of distinct kernels, and clears the
  * record.  Not thread-safe against concurrent marching calls. */

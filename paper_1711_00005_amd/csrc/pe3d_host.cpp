@@ -1206,33 +1206,8 @@ pe3d_status enqueue_advance(const BatchPlan& P, hipStream_t st) {
   return launch_advance(P.d_jdevs, P.d_adds, P.n, nullptr, 0, st) == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
 }
 
-// Without a graph every chain runs on the caller's stream, one after another.
-pe3d_status enqueue_plan(const BatchPlan& P, hipStream_t st) {
-  for (const auto& c : P.chains) {
-    pe3d_status s = enqueue_chain(P, c, st, true);
-    if (s != PE3D_OK) return s;
-  }
-  return enqueue_advance(P, st);
-}
-
-// One graph per chain, captured on a private stream; the side streams and
-// fork/join events of the replay are created with them.
-pe3d_status capture_plan(BatchPlan& P) {
-  for (const auto& c : P.chains) {
-    hipStream_t cap;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
-    pe3d_status s = PE3D_OK;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
-    if (s == PE3D_OK) s = enqueue_chain(P, c, cap, false);
-    hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
-    (void)hipStreamDestroy(cap);
-    if (g) P.graphs.push_back(g);
-    if (s != PE3D_OK) return s;
-    hipGraphExec_t x = nullptr;
-    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) return PE3D_EDEVICE;
-    P.execs.push_back(x);
-  }
+// The plan's side streams and fork/join events (created once; chains >= 1).
+pe3d_status ensure_side(BatchPlan& P) {
   const size_t nc = P.chains.size();
   if (nc > 1 && !P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
     return PE3D_EDEVICE;
@@ -1249,21 +1224,58 @@ pe3d_status capture_plan(BatchPlan& P) {
   return PE3D_OK;
 }
 
-// Replay: chain 0 on the caller's stream, chain c >= 1 on side stream c-1
-// after the caller's prior work (fork event); the caller's stream then waits
-// for every chain (join events) and advances the step counters.
-pe3d_status replay_plan(const BatchPlan& P, hipStream_t st) {
+// Chain 0 on the caller's stream, chain c >= 1 on side stream c-1 after the
+// caller's prior work (fork event); the caller's stream then waits for every
+// chain (join events) and advances the step counters.  run(c, stream)
+// enqueues chain c.
+template <typename F>
+pe3d_status fork_join(const BatchPlan& P, hipStream_t st, F run) {
   const size_t nc = P.chains.size();
   if (nc > 1 && hipEventRecord(P.fork, st) != hipSuccess) return PE3D_EDEVICE;
   for (size_t c = 1; c < nc; ++c) {
     if (hipStreamWaitEvent(P.side[c - 1], P.fork, 0) != hipSuccess) return PE3D_EDEVICE;
-    if (hipGraphLaunch(P.execs[c], P.side[c - 1]) != hipSuccess) return PE3D_EDEVICE;
+    pe3d_status s = run(c, P.side[c - 1]);
+    if (s != PE3D_OK) return s;
     if (hipEventRecord(P.join[c - 1], P.side[c - 1]) != hipSuccess) return PE3D_EDEVICE;
   }
-  if (hipGraphLaunch(P.execs[0], st) != hipSuccess) return PE3D_EDEVICE;
+  pe3d_status s = run(0, st);
+  if (s != PE3D_OK) return s;
   for (size_t c = 1; c < nc; ++c)
     if (hipStreamWaitEvent(st, P.join[c - 1], 0) != hipSuccess) return PE3D_EDEVICE;
   return enqueue_advance(P, st);
+}
+
+// Direct launches, on the same streams as a graph replay.
+pe3d_status enqueue_plan(BatchPlan& P, hipStream_t st) {
+  pe3d_status s = ensure_side(P);
+  if (s != PE3D_OK) return s;
+  return fork_join(P, st, [&](size_t c, hipStream_t cs) { return enqueue_chain(P, P.chains[c], cs, true); });
+}
+
+// One graph per chain, captured on a private stream.
+pe3d_status capture_plan(BatchPlan& P) {
+  for (const auto& c : P.chains) {
+    hipStream_t cap;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
+    pe3d_status s = PE3D_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
+    if (s == PE3D_OK) s = enqueue_chain(P, c, cap, false);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
+    (void)hipStreamDestroy(cap);
+    if (g) P.graphs.push_back(g);
+    if (s != PE3D_OK) return s;
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) return PE3D_EDEVICE;
+    P.execs.push_back(x);
+  }
+  return ensure_side(P);
+}
+
+pe3d_status replay_plan(const BatchPlan& P, hipStream_t st) {
+  return fork_join(P, st, [&](size_t c, hipStream_t cs) {
+    return hipGraphLaunch(P.execs[c], cs) == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
+  });
 }
 
 }  // namespace
