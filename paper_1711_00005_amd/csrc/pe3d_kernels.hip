@@ -427,11 +427,13 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
     constexpr int MP = (M + 1) / 2;
     const __attribute__((address_space(1))) F4* b4 = (const __attribute__((address_space(1))) F4*)base;
     F4 v2[MP];
+    __builtin_amdgcn_s_setprio(2);  // issue the staging loads at raised priority
     #pragma unroll
     for (int q = 0; q < MP; ++q) {
       const int e = 2 * (lane + q * kPassAThreads);
       if (e < span) v2[q] = b4[e >> 1];
     }
+    __builtin_amdgcn_s_setprio(0);
     #pragma unroll
     for (int q = 0; q < MP; ++q) {
       const int e = 2 * (lane + q * kPassAThreads);
@@ -938,9 +940,13 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   {
     const unsigned o0 = unsigned(sc0 * M * N + szc);
     C<S> v[MM];
+    // the staging loads issue at raised wave priority, so that every
+    // wavefront's loads are in flight before the arithmetic of others
+    __builtin_amdgcn_s_setprio(2);
     #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < slen) v[i] = gload(src, o0 + unsigned(i * N));
+    __builtin_amdgcn_s_setprio(0);
     // the step constants are computed while the loads are in flight
     // ---- step constants (wavefront 0; read by all after the staging barrier)
     if (tid < 64) {
