@@ -598,7 +598,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   __syncthreads();
 
   // Table values are prefetched PF slots ahead.
-  constexpr int PF = 4;
+  constexpr int PF = 6;
 
   // ---- phase 1: Rt = [I + beta_+ X] w / nbmh along the chain (sliding
   //      window), local elimination with zero carry -> the lane's map
