@@ -170,6 +170,7 @@ LIMITS = [
     ("max_nth_c64", W.PREC_C64, dict(nz=20, ntheta=1024, theta0=0.0, width=W.TWO_PI, dr=10.0), 50.0),
     ("max_nth_c128", W.PREC_C128, dict(nz=20, ntheta=1024, theta0=0.0, width=W.TWO_PI, dr=10.0), 50.0),
     ("ragged_c64", W.PREC_C64, dict(nz=1999, ntheta=777, theta0=0.1, width=W.TWO_PI, dr=10.0), 100.0),
+    ("max_nz_c128_4096", W.PREC_C128, dict(nz=4096, ntheta=4, theta0=0.0, width=W.TWO_PI, dr=10.0), 100.0),
 ]
 
 
@@ -441,6 +442,35 @@ def test_equal_water_rows_are_bitwise_range_independent(torch, P, prec):
         m.close()
     torch.cuda.synchronize()
     assert torch.equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_water_profile_per_range_step(torch, P, prec):
+    """A water profile that varies continuously in range, given as one row
+    per range step (rows at r0 + i dr): the step j -> j+1 takes the profile
+    at r_{j+1} exactly, i.e. the matrix update of every step with the medium
+    interpolated to its range, each row's factorisation built at create
+    time.  Against the oracle marching the same medium."""
+    base = W.random_env(61, zmax=400.0)
+    nsteps, dr = 40, 6.0
+    z = np.asarray(base.ssp_z)
+    ca = np.asarray(base.ssp_c)
+    cb = ca[::-1].copy() + 15.0
+    r = dr * np.arange(nsteps + 1)
+    rows = ca[None, :] + (r / r[-1])[:, None] * (cb - ca)[None, :]
+    env = dataclasses.replace(base, ssp_c=tuple(rows.ravel()), ssp_nr=nsteps + 1, ssp_r0=0.0, ssp_dr=dr)
+    grid = W.Grid(nz=90, ntheta=16, theta0=0.0, width=W.TWO_PI, dr=dr, precision=prec)
+    st = O.setup(env, grid, 45.0)
+    assert [st.ssp_row_at(st.r(j + 1)) for j in range(nsteps)] == list(range(1, nsteps + 1))
+    u0 = O.starter(st, 120.0) * (1 + 0.2 * np.cos(st.theta))[:, None]
+    say("water profile per range step", prec)
+    m = P.Pe3d(env, grid, 45.0)
+    u = to_dev(torch, u0, prec)
+    m.march(17, u)
+    m.march(nsteps - 17, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, nsteps)) < TOL[prec]
+    m.close()
 
 
 @pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
