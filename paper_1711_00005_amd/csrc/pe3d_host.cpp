@@ -1232,16 +1232,23 @@ template <typename F>
 pe3d_status fork_join(const BatchPlan& P, hipStream_t st, F run) {
   const size_t nc = P.chains.size();
   if (nc > 1 && hipEventRecord(P.fork, st) != hipSuccess) return PE3D_EDEVICE;
-  for (size_t c = 1; c < nc; ++c) {
-    if (hipStreamWaitEvent(P.side[c - 1], P.fork, 0) != hipSuccess) return PE3D_EDEVICE;
-    pe3d_status s = run(c, P.side[c - 1]);
-    if (s != PE3D_OK) return s;
-    if (hipEventRecord(P.join[c - 1], P.side[c - 1]) != hipSuccess) return PE3D_EDEVICE;
+  pe3d_status s = PE3D_OK;
+  size_t joined = 1;  // side chains whose join event is recorded
+  for (size_t c = 1; c < nc && s == PE3D_OK; ++c) {
+    if (hipStreamWaitEvent(P.side[c - 1], P.fork, 0) != hipSuccess) {
+      s = PE3D_EDEVICE;
+      break;
+    }
+    s = run(c, P.side[c - 1]);
+    // the join is recorded even after a failed enqueue, so that the caller's
+    // stream never runs ahead of work already on a side stream
+    if (hipEventRecord(P.join[c - 1], P.side[c - 1]) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
+    joined = c + 1;
   }
-  pe3d_status s = run(0, st);
+  if (s == PE3D_OK) s = run(0, st);
+  for (size_t c = 1; c < joined; ++c)
+    if (hipStreamWaitEvent(st, P.join[c - 1], 0) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
   if (s != PE3D_OK) return s;
-  for (size_t c = 1; c < nc; ++c)
-    if (hipStreamWaitEvent(st, P.join[c - 1], 0) != hipSuccess) return PE3D_EDEVICE;
   return enqueue_advance(P, st);
 }
 
