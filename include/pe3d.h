@@ -199,11 +199,14 @@ pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream);
  * descriptor), before the next group of its chain starts, so that its field
  * stays in the last-level cache between the passes and the steps.  When
  * use_graph != 0 each chain is captured once into a hipGraph, kept in a
- * library-wide cache of at most 64 plans (least recently used evicted, plans
- * of a destroyed handle dropped) under the exact argument tuple (handles,
- * steps, field pointers, schedule), and replayed on later identical calls:
- * chain 0 on `stream`, the others on streams of the plan that wait for
- * `stream`'s prior work, and `stream` then waits for all of them.  A plan
+ * library-wide cache of at most 64 plans (least recently used evicted and
+ * freed once the work they enqueued has finished, without waiting for the
+ * device; plans of a destroyed handle dropped) under the exact argument
+ * tuple (handles, steps, field pointers, schedule), and replayed on later
+ * identical calls:
+ * chain 0 on `stream`, the others on library streams of the device that
+ * wait for `stream`'s prior work, and `stream` then waits for all of them.
+ * Batched calls from several threads are serialised while they enqueue.  A plan
  * must not be run by two calls at once (they would share its fields and
  * streams).  use_graph == 0 enqueues the same launches directly, on the same
  * streams.  use_graph == 2 only builds the plan and

@@ -565,19 +565,20 @@ struct BatchPlan {
     std::vector<Class> a, b, u;        // depth pass, azimuth pass, depth update
   };
   // Chains are independent: chain 0 runs on the caller's stream, the others
-  // on the plan's side streams (graph replay only).
+  // on the device's side streams (shared by all plans of the device).
   std::vector<std::vector<Group>> chains;
   std::vector<hipGraphExec_t> execs;
   std::vector<hipGraph_t> graphs;
-  std::vector<hipStream_t> side;       // chains 1.. (graph replay)
+  std::vector<hipStream_t> side;       // chains 1.. (not owned)
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  hipEvent_t done = nullptr;           // recorded after the plan's latest use
   ~BatchPlan() {
     for (auto e : execs) (void)hipGraphExecDestroy(e);
     for (auto g : graphs) (void)hipGraphDestroy(g);
-    for (auto s : side) (void)hipStreamDestroy(s);
     for (auto e : join) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
+    if (done) (void)hipEventDestroy(done);
     if (d_mem) (void)hipFree(d_mem);
   }
 };
@@ -604,16 +605,35 @@ void touch(const std::vector<uintptr_t>& key) {
   g_lru.push_front(key);
 }
 
-// Caller holds g_mu.  A plan's device tables may still be read by enqueued
-// work, so the device is drained before the oldest plan is freed.
-void evict_if_full() {
-  if (g_plans.size() < kMaxPlans) return;
-  (void)hipDeviceSynchronize();
-  while (g_plans.size() >= kMaxPlans && !g_lru.empty()) {
-    g_plans.erase(g_lru.back());
-    g_lru.pop_back();
+// Evicted plans wait here until the work they enqueued has finished (their
+// `done` event), so that eviction never waits for the device.
+std::vector<std::unique_ptr<BatchPlan>> g_graveyard;
+
+// Caller holds g_mu.
+void reap() {
+  for (auto it = g_graveyard.begin(); it != g_graveyard.end();) {
+    const hipEvent_t e = (*it)->done;
+    if (!e || hipEventQuery(e) != hipErrorNotReady) it = g_graveyard.erase(it);
+    else ++it;
   }
 }
+
+// Caller holds g_mu.
+void evict_if_full() {
+  while (g_plans.size() >= kMaxPlans && !g_lru.empty()) {
+    auto it = g_plans.find(g_lru.back());
+    if (it != g_plans.end()) {
+      g_graveyard.push_back(std::move(it->second));
+      g_plans.erase(it);
+    }
+    g_lru.pop_back();
+  }
+  reap();
+}
+
+// Side streams per device (default priority, non-blocking), created on first
+// use and kept until the process ends.  Caller holds g_mu.
+std::map<int, std::vector<hipStream_t>> g_side_streams;
 
 // ------------------------------------------------------------------ profiling
 struct ProfRec {
@@ -679,6 +699,7 @@ void drop_plans_of(pe3d_handle h) {
   }
   if (!any) return;
   (void)hipDeviceSynchronize();
+  g_graveyard.clear();
   for (auto it = g_plans.begin(); it != g_plans.end();) {
     auto& hs = it->second->handles;
     if (std::find(hs.begin(), hs.end(), h) != hs.end()) {
@@ -1206,15 +1227,22 @@ pe3d_status enqueue_advance(const BatchPlan& P, hipStream_t st) {
   return launch_advance(P.d_jdevs, P.d_adds, P.n, nullptr, 0, st) == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
 }
 
-// The plan's side streams and fork/join events (created once; chains >= 1).
+// The plan's side streams (from the device's pool) and fork/join events
+// (created once; chains >= 1).  Caller holds g_mu.
 pe3d_status ensure_side(BatchPlan& P) {
   const size_t nc = P.chains.size();
   if (nc > 1 && !P.fork && hipEventCreateWithFlags(&P.fork, hipEventDisableTiming) != hipSuccess)
     return PE3D_EDEVICE;
-  while (P.side.size() + 1 < nc) {
-    hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
-    P.side.push_back(s);
+  if (P.side.size() + 1 < nc) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PE3D_EDEVICE;
+    auto& pool = g_side_streams[dev];
+    while (pool.size() + 1 < nc) {
+      hipStream_t s;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
+      pool.push_back(s);
+    }
+    P.side.assign(pool.begin(), pool.begin() + (nc - 1));
   }
   while (P.join.size() + 1 < nc) {
     hipEvent_t e;
@@ -1357,25 +1385,24 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     key.push_back(reinterpret_cast<uintptr_t>(u_devs[i]));
     key.push_back(uintptr_t(uint32_t(nsteps[i])));
   }
+  // The plan cache, the graveyard and the side streams are shared: one
+  // batched call at a time enqueues (the device work itself stays async).
+  std::lock_guard<std::mutex> lk(g_mu);
+  reap();
   BatchPlan* plan = nullptr;
-  std::unique_ptr<BatchPlan> fresh;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_plans.find(key);
-    if (it != g_plans.end()) {
-      plan = it->second.get();
-      touch(key);
-    }
-  }
-  if (!plan) {
-    fresh.reset(new (std::nothrow) BatchPlan());
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    plan = it->second.get();
+    touch(key);
+  } else {
+    std::unique_ptr<BatchPlan> fresh(new (std::nothrow) BatchPlan());
     if (!fresh) return PE3D_ENOMEM;
     fresh->key = key;
     fresh->handles.assign(hs, hs + n);
     pe3d_status s = build_plan(hs, n, nsteps, u_devs, nchains, group_bytes, *fresh);
     if (s != PE3D_OK) return s;
+    if (hipEventCreateWithFlags(&fresh->done, hipEventDisableTiming) != hipSuccess) return PE3D_EDEVICE;
     plan = fresh.get();
-    std::lock_guard<std::mutex> lk(g_mu);
     evict_if_full();
     g_plans[key] = std::move(fresh);
     touch(key);
@@ -1399,6 +1426,7 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     pe3d_status s = enqueue_plan(*plan, st);
     if (s != PE3D_OK) return s;
   }
+  if (hipEventRecord(plan->done, st) != hipSuccess) return PE3D_EDEVICE;
   for (int i = 0; i < n; ++i) hs[i]->j += nsteps[i];
   return PE3D_OK;
 }
