@@ -151,3 +151,19 @@ def test_interface_records_solve_every_column(P, name, env, grid, f):
         dense = np.diag(A_d) + np.diag(A_l[1:], -1) + np.diag(A_u[:-1], 1)
         ref = np.linalg.solve(dense, R)
         assert np.linalg.norm(v - ref) / np.linalg.norm(ref) < 1e-12, (name, m, k)
+
+
+def test_water_rows_keep_row_zero_tables_and_are_validated_per_row(P):
+    """With water-profile rows the exported tables are row 0's, equal to a
+    single-profile environment of that row; every row is built (and its
+    pivots checked) at create time, so an invalid later row is refused."""
+    base = W.random_env(71)
+    rows = [tuple(base.ssp_c), tuple(c + 20.0 for c in base.ssp_c), tuple(c - 15.0 for c in base.ssp_c)]
+    env = dataclasses.replace(base, ssp_c=sum(rows, ()), ssp_nr=3, ssp_r0=0.0, ssp_dr=50.0)
+    grid = W.Grid(nz=64, ntheta=8, theta0=0.0, width=W.TWO_PI, dr=5.0)
+    a = P.pe3d_host_tables(env, grid, 40.0)
+    b = P.pe3d_host_tables(base, grid, 40.0)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    bad = dataclasses.replace(env, ssp_c=rows[0] + rows[1] + tuple([0.0] * len(base.ssp_z)))
+    assert P.pe3d_create_status(bad, grid, 40.0) == P.PE3D_EINVAL
