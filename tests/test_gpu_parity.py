@@ -364,13 +364,14 @@ def test_range_dependent_depth_matches_oracle(torch, P, case, prec, mode):
     m.close()
 
 
-def test_config4_batch_matches_oracle_on_samples(torch, P):
-    """The 64-frequency batch at full size (107,589,632 points, complex64) in
-    the launch configuration bench.py times (one batched call replaying a
-    graph): 2 steps, then the smallest, two middle and the largest problems
-    against the oracle over their whole fields."""
-    probs = W.config4_problems(nsteps=2)
-    say("config4 batch, 64 problems")
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_config4_batch_matches_oracle_on_samples(torch, P, prec):
+    """The 64-frequency batch at full size (107,589,632 points) in the launch
+    configuration bench.py times (one batched call replaying the graphs of
+    the default schedule): 2 steps, then the smallest, two middle and the
+    largest problems against the oracle over their whole fields."""
+    probs = W.config4_problems(nsteps=2, precision=prec)
+    say("config4 batch, 64 problems", prec)
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]
     P.march_batch(ms, 2, us, use_graph=True)
@@ -381,7 +382,7 @@ def test_config4_batch_matches_oracle_on_samples(torch, P):
         ref = O.march(st, O.starter(st, p.zs), 0, 2)
         err = O.rel_l2(to_host(torch, us[i]), ref)
         say("config4 problem", i, p.grid.nz, p.grid.ntheta, err)
-        assert err < TOL[W.PREC_C64], (i, err)
+        assert err < TOL[prec], (i, err)
     for m in ms:
         m.close()
 
