@@ -562,7 +562,7 @@ struct BatchPlan {
   // group of its chain starts (its field stays in the last-level cache).
   struct Group {
     int maxsteps = 0;
-    std::vector<Class> a, b, u;        // depth pass, azimuth pass, depth update
+    std::vector<Class> a, b, u;        // depth pass, azimuth pass, medium update
   };
   // Chains are independent: chain 0 runs on the caller's stream, the others
   // on the device's side streams (shared by all plans of the device).
@@ -972,7 +972,9 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   d.nsteps = nsteps;
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   for (int k = 0; k < nsteps; ++k) {
-    if ((d.nbr || d.nsr) && launch_medium_update(&d, nullptr, nullptr, 0, k, st) != hipSuccess)
+    // the medium of step k: launched for the first step, and for every step
+    // of an N x 2D march; a 3D march's azimuth pass writes it for the next
+    if ((d.nbr || d.nsr) && (k == 0 || d.nx2d) && launch_medium_update(&d, nullptr, nullptr, 0, k, st) != hipSuccess)
       return PE3D_EDEVICE;
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
           return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
@@ -1134,7 +1136,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
           ba.push_back(2.0 * esz * ncol * hd.nz);
         }
         // problems with range rows: water nodes of 256 columns per item (depth
-        // rows), the water row in item 0 (water rows)
+        // rows), the water row in item 0 (water rows), before every step
         if (hd.nbr || hd.nsr)
           for (int t = 0; t < (hd.nbr ? (hd.nth + 255) / 256 : 1); ++t) {
             iu.push_back({p, t});
