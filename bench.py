@@ -68,6 +68,8 @@ def parse():
                     help="also compare the N x 2D (Y = 0) mode with the 3D march on the config-2 wedge")
     ap.add_argument("--range-report", action="store_true",
                     help="also time the config-2 grid over the range-dependent sloping bottom")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose every problem's kernel lanes by timing its shape alone (tune.py) first")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-range-scale", type=float, default=0.25)
     return ap.parse_args()
@@ -182,6 +184,20 @@ def main():
     torch.cuda.set_device(0)
     npts = sum(p.points for p in probs)
     log(f"workload: {len(probs)} problems, {npts} points")
+    tuned = None
+    if args.tune:
+        from paper_1711_00005_amd import tune as T
+        t0 = time.perf_counter()
+        cache = {}
+        for i, p in enumerate(probs):
+            key = (p.grid.nz, p.grid.ntheta, p.grid.precision)
+            if key not in cache:
+                cache[key] = T.tune(p.env, p.grid, p.f_hz)[0]
+            g = cache[key]
+            probs[i] = dataclasses.replace(p, grid=dataclasses.replace(
+                p.grid, depth_lanes=g.depth_lanes, azimuth_lanes=g.azimuth_lanes))
+        tuned = dict(shapes=len(cache), seconds=round(time.perf_counter() - t0, 2))
+        log(f"tuned {len(cache)} shapes in {tuned['seconds']} s")
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]
     torch.cuda.synchronize()
@@ -258,7 +274,7 @@ def main():
            "storage": "complex128" if args.precision == "c128" else "complex64", "data": "synthetic",
            "config": {"workload": workload, "problems": len(probs), "grid_points": npts,
                       "graph": use_graph, "chunk_steps": args.chunk, "chains": args.chains,
-                      "group_mib": args.group_mib},
+                      "group_mib": args.group_mib, "tuned_lanes": tuned},
            "roofline": roofline}
 
     # ---- plain per-frequency march on the same batch

@@ -119,13 +119,23 @@ typedef struct {
  * theta_m = theta0 - width/2 + (m+1) dtheta and zero field on the two edge
  * azimuths.  The march starts at range r0 with range step dr (the range loop of Fig. 2):
  * r_j = r0 + j*dr.  mode selects the azimuthal coupling (pe3d_mode; a
- * zero-initialised grid is the full 3D march). */
+ * zero-initialised grid is the full 3D march).  depth_lanes and
+ * azimuth_lanes override the kernels' shape for this problem (tuning; the
+ * results agree with the default shape to rounding); a value the sizes do
+ * not allow gives PE3D_EUNSUPPORTED, one that is not a power of two in range
+ * PE3D_EINVAL. */
 typedef struct {
   int32_t nz, ntheta;
   double theta0, width;
   double dr, r0;
   int32_t precision;          /* pe3d_precision */
   int32_t mode;               /* pe3d_mode */
+  int32_t depth_lanes;        /* 0: the library's choice; else the lanes per
+                                 depth column of the depth pass, a power of
+                                 two 4..256 giving <= 17 rows per lane */
+  int32_t azimuth_lanes;      /* 0: the library's choice; else the lanes per
+                                 depth line of the azimuth pass, a power of
+                                 two 1..64 giving <= 16 azimuths per lane */
 } pe3d_grid;
 
 typedef struct { double f_hz; } pe3d_freq;

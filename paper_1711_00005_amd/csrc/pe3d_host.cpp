@@ -108,6 +108,8 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (!is_fin(g->dr) || g->dr <= 0.0 || !is_fin(g->r0) || g->r0 < 0.0) return PE3D_EINVAL;
   if (g->precision != PE3D_C64 && g->precision != PE3D_C128) return PE3D_EINVAL;
   if (g->mode != PE3D_MODE_3D && g->mode != PE3D_MODE_NX2D) return PE3D_EINVAL;
+  auto pow2_in = [](int v, int lo, int hi) { return v == 0 || (v >= lo && v <= hi && (v & (v - 1)) == 0); };
+  if (!pow2_in(g->depth_lanes, 4, 256) || !pow2_in(g->azimuth_lanes, 1, 64)) return PE3D_EINVAL;
   if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   if (g->precision == PE3D_C128 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   return PE3D_OK;
@@ -195,6 +197,7 @@ struct Built {
   double br0 = 0, bdr = 0;
   int nsr = 0;                          // water-profile rows (0: one profile)
   double sr0 = 0, sdr = 0;
+  int la_req = 0, lb_req = 0;           // requested lanes (0: the rule)
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
   int bconv[2] = {0, 0};   // first row of each chain's converged tail
   cd gtail[2], ctail[2];   // the tail's Gh and RHS diagonal / nbmh
@@ -210,13 +213,14 @@ pe3d_status choose_shapes(Built& b) {
   // rows per lane, rounded up to an odd number (conflict-free LDS strides),
   // at most 17; nz <= (L-1) M - 1 leaves room for the two chains' leading
   // zero slots in every column
-  int L = 4, M = 0;
+  int L = b.la_req ? b.la_req : 4, M = 0;
   for (;; L *= 2) {
     if (L > 256) return PE3D_EUNSUPPORTED;
     M = (N + 1 + L - 2) / (L - 1);
     if (M % 2 == 0) ++M;
     if (M < 3) M = 3;
     if (M <= 17) break;
+    if (b.la_req) return PE3D_EUNSUPPORTED;  // the requested lanes need > 17 rows each
   }
   b.lpc = L;
   b.ma = M;
@@ -231,6 +235,10 @@ pe3d_status choose_shapes(Built& b) {
   int W = 1;
   while ((NT + W - 1) / W > 16) W *= 2;
   if (W > 64) return PE3D_EUNSUPPORTED;
+  if (b.lb_req) {
+    if (b.lb_req < W) return PE3D_EUNSUPPORTED;  // > 16 azimuths per lane
+    W = b.lb_req;
+  }
   const int mb = (NT + W - 1) / W;
   b.wb = W;
   b.mb = mb;
@@ -252,6 +260,8 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   b.N = N;
   b.NT = NT;
   b.prec = g.precision;
+  b.la_req = g.depth_lanes;
+  b.lb_req = g.azimuth_lanes;
   b.rigid = e.floor == PE3D_FLOOR_RIGID;
   b.periodic = is_periodic(g.width);
   b.k0 = 2.0 * kPi * f.f_hz / e.c0;
@@ -738,6 +748,8 @@ pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3
   b.prec = grid->precision;
   b.nbr = env->n_bathy_r >= 2 ? env->n_bathy_r : 0;
   b.nsr = env->n_ssp_r >= 2 ? env->n_ssp_r : 0;
+  b.la_req = grid->depth_lanes;
+  b.lb_req = grid->azimuth_lanes;
   st = choose_shapes(b);
   if (st != PE3D_OK) return st;
   *bytes = table_bytes(b) + field_bytes(b);

@@ -58,7 +58,8 @@ class pe3d_env(ct.Structure):
 class pe3d_grid(ct.Structure):
     _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("theta0", ct.c_double),
                 ("width", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
-                ("precision", ct.c_int32), ("mode", ct.c_int32)]
+                ("precision", ct.c_int32), ("mode", ct.c_int32),
+                ("depth_lanes", ct.c_int32), ("azimuth_lanes", ct.c_int32)]
 
 
 class pe3d_freq(ct.Structure):
@@ -151,7 +152,9 @@ def make_grid(grid):
     return pe3d_grid(nz=int(grid.nz), ntheta=int(grid.ntheta), theta0=float(grid.theta0),
                      width=float(grid.width), dr=float(grid.dr), r0=float(getattr(grid, "r0", 0.0)),
                      precision=int(getattr(grid, "precision", PE3D_C64)),
-                     mode=int(getattr(grid, "mode", PE3D_MODE_3D)))
+                     mode=int(getattr(grid, "mode", PE3D_MODE_3D)),
+                     depth_lanes=int(getattr(grid, "depth_lanes", 0)),
+                     azimuth_lanes=int(getattr(grid, "azimuth_lanes", 0)))
 
 
 def _stream_ptr(stream) -> Optional[int]:

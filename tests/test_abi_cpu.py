@@ -123,6 +123,22 @@ def test_footprint_counts_one_table_block_per_water_row(P):
     assert fp[5] - fp[1] == 4 * block
 
 
+def test_kernel_lanes_overrides_are_validated(P):
+    env = W.wedge_env()
+    g = dict(nz=300, ntheta=70, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    for la, lb in ((0, 0), (32, 0), (256, 0), (0, 8), (0, 64), (64, 16)):
+        assert _status(P, env, W.Grid(depth_lanes=la, azimuth_lanes=lb, **g)) not in (
+            P.PE3D_EINVAL, P.PE3D_EUNSUPPORTED), (la, lb)
+    for la, lb in ((3, 0), (512, 0), (0, 3), (0, 128), (-4, 0)):
+        assert _status(P, env, W.Grid(depth_lanes=la, azimuth_lanes=lb, **g)) == P.PE3D_EINVAL, (la, lb)
+    # 16 lanes for 300 depths would need 21 rows per lane; 4 azimuth lanes 18 azimuths each
+    for la, lb in ((16, 0), (0, 4)):
+        assert _status(P, env, W.Grid(depth_lanes=la, azimuth_lanes=lb, **g)) == P.PE3D_EUNSUPPORTED, (la, lb)
+    b0 = P.pe3d_footprint(env, W.Grid(**g), 40.0)
+    b1 = P.pe3d_footprint(env, W.Grid(depth_lanes=256, **g), 40.0)
+    assert b0 > 0 and b1 > 0
+
+
 def test_create_reports_unsupported_sizes(P):
     env = W.wedge_env()
     assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED

@@ -186,6 +186,46 @@ def test_size_limits_match_oracle(torch, P, case):
 
 
 # ---------------------------------------------------------------- state and batching
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+@pytest.mark.parametrize("lanes", [(0, 0), (64, 0), (256, 0), (0, 32), (0, 64), (128, 64)])
+def test_kernel_lanes_overrides_match_oracle(torch, P, prec, lanes):
+    """Every kernel shape the sizes allow gives the oracle's field (the lanes
+    only split the same recurrences differently)."""
+    env = W.wedge_env()
+    grid = W.Grid(nz=300, ntheta=70, theta0=0.3, width=W.TWO_PI, dr=10.0, precision=prec,
+                  depth_lanes=lanes[0], azimuth_lanes=lanes[1])
+    st = O.setup(env, grid, 60.0)
+    u0 = O.starter(st, 100.0) * (1 + 0.2 * np.cos(st.theta))[:, None]
+    say("kernel lanes", lanes, prec)
+    m = P.Pe3d(env, grid, 60.0)
+    if lanes[0]:
+        assert m.info().pass_a_lanes == lanes[0]
+    u = to_dev(torch, u0, prec)
+    m.march(4, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, 4)) < TOL[prec]
+    m.close()
+
+
+def test_tune_returns_a_shape_that_matches_oracle(torch, P):
+    from paper_1711_00005_amd import tune as T
+    env = W.wedge_env()
+    grid = W.Grid(nz=700, ntheta=384, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    say("tune")
+    best, tim = T.tune(env, grid, 80.0, steps=3, reps=1)
+    la, lb = T.candidates(grid)
+    assert best.depth_lanes in la and best.azimuth_lanes in lb
+    assert set(tim["depth_lanes_ms"]) == set(la) and set(tim["azimuth_lanes_ms"]) == set(lb)
+    st = O.setup(env, best, 80.0)
+    u0 = O.starter(st, 100.0)
+    m = P.Pe3d(env, best, 80.0)
+    u = to_dev(torch, u0, W.PREC_C64)
+    m.march(3, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, 3)) < TOL[W.PREC_C64]
+    m.close()
+
+
 def test_resume_is_bitwise(torch, P):
     env = W.wedge_env()
     grid = W.Grid(nz=200, ntheta=24, theta0=0.0, width=W.TWO_PI, dr=10.0)

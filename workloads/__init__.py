@@ -73,7 +73,9 @@ class Grid:
     """Computational grid.  width == 2*pi means the full circle (periodic in
     azimuth); a smaller width is a sector centred on theta0 with zero field on
     the two edge azimuths.  The march starts at range r0.  mode MODE_NX2D
-    drops the azimuth operator (Y = 0): N independent 2D marches."""
+    drops the azimuth operator (Y = 0): N independent 2D marches.
+    depth_lanes / azimuth_lanes: kernel shape of the GPU path (0: its own
+    choice; a tuning knob that changes nothing but rounding)."""
     nz: int
     ntheta: int
     theta0: float
@@ -82,6 +84,8 @@ class Grid:
     r0: float = 0.0
     precision: int = PREC_C64
     mode: int = MODE_3D
+    depth_lanes: int = 0
+    azimuth_lanes: int = 0
 
 
 @dataclass(frozen=True)
