@@ -983,6 +983,18 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
   d.u = u_dev;
   d.nsteps = nsteps;
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
+  if (d.nx2d && !d.nbr && !d.nsr) {
+    // N x 2D over a fixed medium: the columns march through every step of
+    // the call inside one launch, in LDS (the same arithmetic and roundings
+    // as one launch per step); algorithmic bytes: the field in and out once
+    if (prof_launch("pass_a_nx2d", h->prec, h->maxm_a, fbytes, st, [&] {
+          return launch_pass_a_multi(h->prec, d, h->lds_a, st);
+        }) != hipSuccess)
+      return PE3D_EDEVICE;
+    if (launch_advance(nullptr, nullptr, 0, h->d_j, nsteps, st) != hipSuccess) return PE3D_EDEVICE;
+    h->j += nsteps;
+    return PE3D_OK;
+  }
   for (int k = 0; k < nsteps; ++k) {
     // the medium of step k: launched for the first step, and for every step
     // of an N x 2D march; a 3D march's azimuth pass writes it for the next

@@ -112,6 +112,9 @@ __host__ __device__ inline bool pass_b_pairs(int td, int value_bytes) { return t
 hipError_t launch_pass_a(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                          int nitems, int koff, int lds, hipStream_t st);
 int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pass A workgroup
+// every step of a call of one N x 2D problem without range rows in one launch
+// (d.nsteps steps, the caller's field d.u in and out)
+hipError_t launch_pass_a_multi(int prec, const ProbDesc& d, int lds, hipStream_t st);
 hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                          int nitems, int koff, int lds, hipStream_t st);
 int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
