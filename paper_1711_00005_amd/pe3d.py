@@ -22,6 +22,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_1711_00005_amd.build_lib` "
         "(the PE march has no CPU fallback)")
 
+# torch first: its wheel carries a HIP runtime of its own, and with the
+# library (linked against the system's runtime) loaded before it, torch's
+# device initialisation finds no GPU.  Loaded after torch, the library shares
+# the process's runtime with the tensors it is handed.
+import torch  # noqa: E402,F401
+
 _lib = ct.CDLL(LIB_PATH)
 
 PE3D_OK = 0

@@ -71,7 +71,12 @@ def tune(env, grid, f_hz: float, steps: int = 6, reps: int = 2) -> Tuple[object,
     la, lb = candidates(grid)
     ta = {L: _time(env, dataclasses.replace(grid, depth_lanes=L, azimuth_lanes=lb[0]), f_hz, steps, reps)[0]
           for L in la}
-    tb = {W: _time(env, dataclasses.replace(grid, depth_lanes=la[0], azimuth_lanes=W), f_hz, steps, reps)[1]
-          for W in lb}
-    best = dataclasses.replace(grid, depth_lanes=min(ta, key=ta.get), azimuth_lanes=min(tb, key=tb.get))
+    # an N x 2D march has no azimuth pass: its lanes keep the rule's choice
+    # (and its depth pass over a fixed medium is one launch per call, timed
+    # as a whole: the same steps for every candidate)
+    tb = {} if getattr(grid, "mode", 0) == P.PE3D_MODE_NX2D else {
+        W: _time(env, dataclasses.replace(grid, depth_lanes=la[0], azimuth_lanes=W), f_hz, steps, reps)[1]
+        for W in lb}
+    best = dataclasses.replace(grid, depth_lanes=min(ta, key=ta.get),
+                               azimuth_lanes=min(tb, key=tb.get) if tb else 0)
     return best, {"depth_lanes_ms": ta, "azimuth_lanes_ms": tb}

@@ -226,6 +226,28 @@ def test_tune_returns_a_shape_that_matches_oracle(torch, P):
     m.close()
 
 
+def test_tune_nx2d_times_the_depth_pass_only(torch, P):
+    """The tuner of an N x 2D shape searches the depth lanes only (there is
+    no azimuth pass) and its choice matches the oracle."""
+    from paper_1711_00005_amd import tune as T
+    env = W.wedge_env()
+    grid = W.Grid(nz=700, ntheta=96, theta0=0.0, width=W.TWO_PI, dr=10.0, mode=W.MODE_NX2D)
+    say("tune nx2d")
+    best, tim = T.tune(env, grid, 80.0, steps=4, reps=1)
+    la, _ = T.candidates(grid)
+    assert best.depth_lanes in la and best.azimuth_lanes == 0 and best.mode == W.MODE_NX2D
+    assert set(tim["depth_lanes_ms"]) == set(la) and tim["azimuth_lanes_ms"] == {}
+    assert all(v > 0 for v in tim["depth_lanes_ms"].values())
+    st = O.setup(env, best, 80.0)
+    u0 = O.starter(st, 100.0)
+    m = P.Pe3d(env, best, 80.0)
+    u = to_dev(torch, u0, W.PREC_C64)
+    m.march(4, u)
+    torch.cuda.synchronize()
+    assert O.rel_l2(to_host(torch, u), O.march(st, u0, 0, 4)) < TOL[W.PREC_C64]
+    m.close()
+
+
 def test_resume_is_bitwise(torch, P):
     env = W.wedge_env()
     grid = W.Grid(nz=200, ntheta=24, theta0=0.0, width=W.TWO_PI, dr=10.0)
