@@ -158,3 +158,25 @@ def test_null_handles_are_rejected(P):
     with pytest.raises(P.Pe3dError):
         P.pe3d_get_step(None)
     P.pe3d_destroy(None)
+
+
+def test_tuner_candidates_are_the_shapes_the_library_accepts(P):
+    """tune.candidates lists exactly the lane counts that pe3d_create accepts
+    for a shape: every candidate passes validation, and the next smaller
+    power of two is refused as unsupported (checked without a device)."""
+    from dataclasses import replace
+    from paper_1711_00005_amd import tune as T
+    env = W.wedge_env()
+    for nz, nth in ((64, 8), (300, 70), (700, 384), (2048, 512), (4096, 1024), (320, 17)):
+        g = W.Grid(nz=nz, ntheta=nth, theta0=0.0, width=W.TWO_PI, dr=10.0)
+        la, lb = T.candidates(g)
+        assert la and la[-1] == 256 and lb and lb[-1] == 64, (nz, nth)
+        for L in la:
+            assert _status(P, env, replace(g, depth_lanes=L)) not in (P.PE3D_EINVAL, P.PE3D_EUNSUPPORTED), (nz, L)
+        for Wl in lb:
+            assert _status(P, env, replace(g, azimuth_lanes=Wl)) not in (
+                P.PE3D_EINVAL, P.PE3D_EUNSUPPORTED), (nth, Wl)
+        if la[0] > 4:
+            assert _status(P, env, replace(g, depth_lanes=la[0] // 2)) == P.PE3D_EUNSUPPORTED, (nz, la)
+        if lb[0] > 1:
+            assert _status(P, env, replace(g, azimuth_lanes=lb[0] // 2)) == P.PE3D_EUNSUPPORTED, (nth, lb)
