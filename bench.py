@@ -72,6 +72,8 @@ def parse():
                     help="choose every problem's kernel lanes by timing its shape alone (tune.py) first")
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-range-scale", type=float, default=0.25)
+    ap.add_argument("--serve-chunk", type=int, default=20,
+                    help="range steps every resident request advances per served iteration")
     ap.add_argument("--serve-budget-gib", type=float, default=1.0,
                     help="HBM admission budget of the served stream (fields + tables of resident requests)")
     return ap.parse_args()
@@ -325,11 +327,11 @@ def main():
                                                       r.problem.name)) for r in tr]
         log(f"serve: {len(tr)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
-        sch = Scheduler(Pe3dBackend(), budget, 20)
+        sch = Scheduler(Pe3dBackend(), budget, args.serve_chunk)
         t0 = time.perf_counter()
         recs = sch.run(tr)
         rep = report(recs, time.perf_counter() - t0)
-        rep.update(rate_hz=200.0, budget_bytes=budget, chunk_steps=20, max_resident=sch.max_resident,
+        rep.update(rate_hz=200.0, budget_bytes=budget, chunk_steps=args.serve_chunk, max_resident=sch.max_resident,
                    range_scale=args.serve_range_scale,
                    trace="config5 seed 0: f~U(20,400) Hz, zs~U(10,500) m, width in {30,90,360} deg, "
                          "range~U(2,20) km scaled by range_scale, Nz=clamp(ceil64(6.4 f),128,4096), "
