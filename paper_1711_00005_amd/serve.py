@@ -125,12 +125,20 @@ class Pe3dBackend(Backend):
 class Scheduler:
     def __init__(self, backend: Backend, budget_bytes: int, chunk_steps: int = 20,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, log: Optional[Callable] = None):
+                 sleep: Callable[[float], None] = time.sleep, log: Optional[Callable] = None,
+                 backlog_chunk_steps: Optional[int] = None):
+        """backlog_chunk_steps: steps per iteration while requests wait for
+        admission (the budget is full), so that an overloaded loop pays its
+        per-iteration cost less often; None keeps chunk_steps throughout."""
         if budget_bytes <= 0 or chunk_steps <= 0:
             raise ValueError("budget and chunk size must be positive")
+        if backlog_chunk_steps is not None and backlog_chunk_steps < chunk_steps:
+            raise ValueError("the backlog chunk must be at least the chunk")
         self.backend = backend
         self.budget = int(budget_bytes)
         self.K = int(chunk_steps)
+        self.Kb = int(backlog_chunk_steps) if backlog_chunk_steps is not None else self.K
+        self.backlog_iterations = 0
         self.clock = clock
         self.sleep = sleep
         self.log = log
@@ -181,7 +189,9 @@ class Scheduler:
                         self.sleep(wait)
                 continue
             marching = list(resident)
-            steps = [min(self.K, x[2]) for x in marching]
+            K = self.Kb if waiting else self.K
+            self.backlog_iterations += K != self.K
+            steps = [min(K, x[2]) for x in marching]
             self.backend.march([x[1] for x in marching], steps)
             # while the device works: admit and set up new arrivals (next iteration)
             admit()
@@ -247,6 +257,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget-gib", type=float, default=1.0)
     ap.add_argument("--chunk", type=int, default=20)
+    ap.add_argument("--backlog-chunk", type=int, default=100,
+                    help="steps per iteration while requests wait for admission")
     ap.add_argument("--range-scale", type=float, default=1.0,
                     help="multiply every request's range (and step count) by this factor")
     a = ap.parse_args(argv)
@@ -257,12 +269,14 @@ def main(argv=None):
                                      max(1, int(math.ceil(r.problem.nsteps * a.range_scale))),
                                      r.problem.name)) for r in trace]
     sch = Scheduler(Pe3dBackend(), int(a.budget_gib * 2**30), a.chunk,
-                    log=lambda s: print("[serve]", s, file=sys.stderr, flush=True))
+                    log=lambda s: print("[serve]", s, file=sys.stderr, flush=True),
+                    backlog_chunk_steps=a.backlog_chunk)
     t0 = time.perf_counter()
     recs = sch.run(trace)
     out = report(recs, time.perf_counter() - t0)
     out.update(iterations=sch.iterations, max_resident=sch.max_resident,
                max_used_bytes=sch.max_used, budget_bytes=sch.budget, chunk_steps=sch.K,
+               backlog_chunk_steps=sch.Kb, backlog_iterations=sch.backlog_iterations,
                rate_hz=a.rate, range_scale=a.range_scale)
     print(json.dumps(out), flush=True)
 

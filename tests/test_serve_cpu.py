@@ -107,6 +107,33 @@ def test_oversized_request_is_rejected_and_failures_are_flagged():
     assert rep["rejected"] == 1 and rep["failed"] == 1 and rep["done"] == len(tr) - 2
 
 
+def test_backlog_chunk_applies_only_while_requests_wait():
+    """With the budget full, iterations advance backlog_chunk_steps; once
+    nothing waits, chunk_steps again; every request still advances exactly
+    its own steps."""
+    clk = VirtualClock()
+    be = TimedBackend(clk, rate=2e3)
+    tr = small_trace(20, seed=3)
+    budget = 3 * max(r.problem.points for r in tr) * 16
+    sch = Scheduler(be, budget, 3, clock=clk, sleep=clk.sleep, backlog_chunk_steps=9)
+    steps_seen = []
+    march = be.march
+
+    def spy(states, nsteps):
+        steps_seen.append(max(nsteps))
+        march(states, nsteps)
+    be.march = spy
+    recs = sch.run(tr)
+    assert all(r.status == "done" for r in recs)
+    assert all(r.summary["steps"] == r.steps for r in recs)
+    assert sch.backlog_iterations > 0 and max(steps_seen) == 9
+    assert 0 < sch.backlog_iterations < sch.iterations
+    with pytest.raises(ValueError):
+        Scheduler(be, budget, 5, backlog_chunk_steps=4)
+    plain = Scheduler(TimedBackend(VirtualClock()), budget, 3)
+    assert plain.Kb == plain.K == 3
+
+
 def test_latency_percentiles():
     clk = VirtualClock()
     recs = Scheduler(TimedBackend(clk, rate=1e5), 10**9, 4, clock=clk, sleep=clk.sleep).run(small_trace(30, 5))
