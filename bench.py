@@ -76,6 +76,8 @@ def parse():
                     help="range steps every resident request advances per served iteration")
     ap.add_argument("--serve-backlog-chunk", type=int, default=100,
                     help="range steps per served iteration while requests wait for admission")
+    ap.add_argument("--serve-graph", action="store_true",
+                    help="replay every served iteration as a captured HIP graph")
     ap.add_argument("--serve-budget-gib", type=float, default=1.0,
                     help="HBM admission budget of the served stream (fields + tables of resident requests)")
     return ap.parse_args()
@@ -329,13 +331,14 @@ def main():
                                                       r.problem.name)) for r in tr]
         log(f"serve: {len(tr)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
-        sch = Scheduler(Pe3dBackend(), budget, args.serve_chunk,
+        sch = Scheduler(Pe3dBackend(use_graph=args.serve_graph), budget, args.serve_chunk,
                         backlog_chunk_steps=args.serve_backlog_chunk)
         t0 = time.perf_counter()
         recs = sch.run(tr)
         rep = report(recs, time.perf_counter() - t0)
         rep.update(rate_hz=200.0, budget_bytes=budget, chunk_steps=args.serve_chunk,
-                   backlog_chunk_steps=sch.Kb, backlog_iterations=sch.backlog_iterations, max_resident=sch.max_resident,
+                   backlog_chunk_steps=sch.Kb, backlog_iterations=sch.backlog_iterations,
+                   graph=args.serve_graph, max_resident=sch.max_resident,
                    range_scale=args.serve_range_scale,
                    trace="config5 seed 0: f~U(20,400) Hz, zs~U(10,500) m, width in {30,90,360} deg, "
                          "range~U(2,20) km scaled by range_scale, Nz=clamp(ceil64(6.4 f),128,4096), "
