@@ -408,6 +408,102 @@ def test_pressure_hankel_factor_textbook_values():
         O.pressure(st, one, 0)
 
 
+def _tl_plant_20logr(st, u, j):
+    with np.errstate(divide="ignore"):
+        return -20.0 * np.log10(np.abs(u)) + 20.0 * math.log10(st.r(j))
+
+
+def _tl_plant_sign(st, u, j):
+    with np.errstate(divide="ignore"):
+        return 20.0 * np.log10(np.abs(u)) + 10.0 * math.log10(st.r(j))
+
+
+def _tl_hankel_defect(tlfun):
+    """Largest deviation of tl(u) + 20 log10|p| from its large-argument
+    constant.  The pressure p = u H0^(1)(k0 r_j) is pinned above to the
+    tables; with |H0^(1)(x)|^2 = 2/(pi x) (1 - 1/(8 x^2) + O(x^-4))
+    (A&S 9.2.28) the loss of the envelope, -20 log10|u| + 10 log10 r (Tappert
+    factor ~ r^-1/2, Sec. 2.1), differs from the loss of the pressure,
+    -20 log10|p|, by 10 log10(2 / (pi k0)) + 10 log10(1 - 1/(8 x^2)) + O(x^-4),
+    whatever u is."""
+    env = W.isovelocity_env()
+    grid = W.Grid(nz=16, ntheta=5, theta0=0.0, width=W.TWO_PI, dr=25.0, precision=W.PREC_C128)
+    st = O.setup(env, grid, 60.0)
+    u = W.random_field(5, 16, seed=11)
+    worst = 0.0
+    for j in (200, 1000, 4000, 20000):
+        x = st.k0 * st.r(j)
+        assert x > 1e3
+        lhs = O.tl(st, u, j) + 20.0 * np.log10(np.abs(O.pressure(st, u, j)))
+        const = 10.0 * math.log10(2.0 / (math.pi * st.k0)) + 10.0 * math.log10(1.0 - 1.0 / (8.0 * x * x))
+        worst = max(worst, float(np.abs(lhs - const).max()))
+    return worst
+
+
+def test_tl_is_the_pressure_loss_up_to_the_hankel_constant():
+    assert _tl_hankel_defect(O.tl) < 1e-9
+
+
+@pytest.mark.parametrize("plant", [_tl_plant_20logr, _tl_plant_sign])
+def test_tl_pin_catches_planted_mistakes(plant, monkeypatch):
+    monkeypatch.setattr(O, "tl", plant)
+    assert _tl_hankel_defect(O.tl) > 1.0
+
+
+# --------------------------------------------------------------- depth grid vs the continuous waveguide
+def _lowest_x_eigenvalues(st, k):
+    n = st.nz
+    a = np.diag(st.xd[0]) + np.diag(st.xl[0, 1:], -1) + np.diag(st.xu[0, :-1], 1)
+    ev = np.linalg.eigvals(a)
+    return np.sort(ev.real)[::-1][:k]
+
+
+def _waveguide_defect(floor, nz, plant_extra_nodes=0):
+    """Largest relative distance of the 4 highest eigenvalues of the oracle's
+    X from the continuous ones, over the second-order bound; a plant moves
+    the grid to dz = zmax / (Nz + conventional offset + plant_extra_nodes)."""
+    zmax = 200.0
+    env = dataclasses.replace(W.isovelocity_env(depth=zmax, c=1500.0), floor=floor)
+    grid = W.Grid(nz=nz, ntheta=3, theta0=0.0, width=W.TWO_PI, dr=5.0, precision=W.PREC_C128)
+    st = O.setup(env, grid, 25.0)
+    if plant_extra_nodes:
+        st.dz = zmax / (nz + (0 if floor == W.FLOOR_RIGID else 1) + plant_extra_nodes)
+        st.z = st.dz * np.arange(1, nz + 1)
+        st.water, st.rho, st.q, st.xl, st.xd, st.xu = st.medium(st.depth_at(st.r0))
+    k = np.arange(1, 5)
+    kz = ((k - 0.5) if floor == W.FLOOR_RIGID else k) * math.pi / zmax
+    cont = -(kz / st.k0) ** 2
+    rel = np.abs(_lowest_x_eigenvalues(st, 4) - cont) / np.abs(cont)
+    # second order: (kz dz)^2 / 12 relative
+    return float(np.max(rel / (0.2 * (kz * zmax / nz) ** 2)))
+
+
+@pytest.mark.parametrize("floor", [W.FLOOR_RIGID, W.FLOOR_PRESSURE_RELEASE])
+@pytest.mark.parametrize("extra", [1, -1])
+def test_waveguide_pin_catches_a_shifted_floor(floor, extra):
+    assert _waveguide_defect(floor, 200, plant_extra_nodes=extra) > 1.0
+
+
+@pytest.mark.parametrize("floor", [W.FLOOR_RIGID, W.FLOOR_PRESSURE_RELEASE])
+def test_depth_grid_converges_to_the_continuous_waveguide(floor):
+    """An isovelocity layer 0 < z < zmax with u(0) = 0 and a rigid floor
+    (du/dz = 0 at zmax) has the continuous modes sin(kz z) with
+    kz = (k - 1/2) pi / zmax; a pressure-release floor (u(zmax) = 0) has
+    kz = k pi / zmax.  X = (n^2 - 1) + k0^-2 d_zz then has the eigenvalues
+    (n^2 - 1) - (kz / k0)^2.  The discrete X converges to them at second
+    order only when the ghost rule's plane of symmetry (rigid: node Nz;
+    pressure release: node Nz + 1) lies exactly at zmax, i.e. with the grid
+    conventions dz = zmax/Nz (rigid) and zmax/(Nz + 1) (pressure release).
+    One node too many or too few moves the floor by dz and the eigenvalues
+    by O(1/Nz), 100x more than allowed here."""
+    for nz in (200, 400):
+        assert _waveguide_defect(floor, nz) < 1.0, nz
+    # config 1: Nz = 64 nodes over a 200 m rigid-floored layer
+    p = W.config1()
+    st = O.setup(p.env, p.grid, p.f_hz)
+    assert p.env.floor == W.FLOOR_RIGID and st.dz == 3.125 and st.z[-1] == p.env.zmax
+
+
 # --------------------------------------------------------------- range-dependent depth
 def test_equal_range_rows_reduce_to_range_independent():
     base = W.random_env(21, floor=W.FLOOR_RIGID)
