@@ -22,12 +22,14 @@
 //    The operator is circulant (periodic) or Toeplitz (sector) with constant
 //    coefficients and factors exactly as c (1 - rho S)(1 - rho S^-1), S the
 //    cyclic shift, s rho^2 - (1 + 2s) rho + s = 0, |rho| < 1, c = s / rho.
-//    The kernel solves for the defect e = u - v, B e = s D_theta v, i.e.
-//    e = rho (1 - rho S^-1)^-1 (1 - rho S)^-1 D_theta v: two constant-coefficient
-//    recurrences (forward, backward) split into azimuth chunks, with the
-//    cross-chunk carries and the periodic wrap (a Sherman-Morrison rank-one
-//    correction of each cyclic bidiagonal factor) evaluated in FP64; a sector
-//    adds the rank-one correction of its first row.  Lanes are consecutive
+//    The kernel solves u = (rho/s) (1 - rho S^-1)^-1 (1 - rho S)^-1 v directly:
+//    two constant-coefficient recurrences (forward, backward) split into
+//    azimuth chunks, with the cross-chunk carries and the periodic wrap (a
+//    Sherman-Morrison rank-one correction of each cyclic bidiagonal factor)
+//    evaluated in FP64; a sector adds the rank-one correction of its first
+//    row.  (Solving for the defect u - v instead, from s D_theta v, cancels
+//    about log10(4 sigma) digits on fields rough in azimuth: there u is
+//    |v| / (4 sigma) while the defect is as large as v.)  Lanes are consecutive
 //    depths, so every load and store is coalesced along z.  The same kernel
 //    also applies the next step's azimuth factor [I + s_{j+1} D_theta] before
 //    storing, so pass A of the next step is column-local.
@@ -291,12 +293,17 @@ __device__ __forceinline__ void medium_update_next(const ProbDesc& d, int tile, 
 }
 
 // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle, s = i sigma:
-// rho = 2s / (1 + 2s + sqrt(1 + 4s))
-__device__ __forceinline__ C<double> rho_of(double sigma) {
-  C<double> s = mk<double>(0.0, sigma);
+// rho = 2s / (1 + 2s + sqrt(1 + 4s)), and rho / s = 2 / (1 + 2s + sqrt(1 + 4s))
+// (no division by s, which vanishes far from the source)
+__device__ __forceinline__ C<double> rho_den(double sigma) {
   C<double> q = csqrt(mk<double>(1.0, 4.0 * sigma));
-  C<double> den = mk<double>(1.0 + q.re, 2.0 * sigma + q.im);
-  return cdiv(mk<double>(2.0 * s.re, 2.0 * s.im), den);
+  return mk<double>(1.0 + q.re, 2.0 * sigma + q.im);
+}
+__device__ __forceinline__ C<double> rho_of(double sigma) {
+  return cdiv(mk<double>(0.0, 2.0 * sigma), rho_den(sigma));
+}
+__device__ __forceinline__ C<double> rho_over_s(double sigma) {
+  return cdiv(mk<double>(2.0, 0.0), rho_den(sigma));
 }
 
 
@@ -1406,6 +1413,7 @@ __global__ PE3D_PASS_A_ATTR __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 
 // lanes of a line read distinct banks and slot offsets are immediates.
 struct BConst {
   D rho;      // root of s rho^2 - (1+2s) rho + s = 0 inside the unit circle
+  D cs;       // rho / s = 1 / c, the scale of the factored operator
   D rinv;     // 1 / rho (sector)
   D rL;       // rho^lastlen
   D winv;     // 1 / (1 - rho^NT)      (periodic closure)
@@ -1476,13 +1484,15 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
     // the step constants are computed while the loads are in flight
     // ---- step constants (wavefront 0; read by all after the staging barrier)
     if (tid < 64) {
-      const D rho = rho_of(sigma_of(d, j));
+      const double sg = sigma_of(d, j);
+      const D rho = rho_of(sg);
       const int lastlen = NT - (NC - 1) * M;
       const D rM = cpow(rho, M);
       sPowC[tid] = cpow(rM, tid);
       if (!periodic) sPowS[tid] = cpow(rho, 2 * (long long)NT - (long long)M * tid);
       if (tid == 0) {
         K->rho = rho;
+        K->cs = rho_over_s(sg);
         K->rinv = cdiv(one<double>(), rho);
         K->rL = cpow(rho, lastlen);
         const D rN = cpow(rho, NT);
@@ -1509,30 +1519,15 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   C<S>* T = tl + c * CST + dl * DS;
   auto vat = [&](int i) { return to_d(T[i]); };
 
-  // ---- t = D_theta v, forward recurrence y_m = t_m + rho y_{m-1}: end value
-  //      with zero carry
+  // ---- forward recurrence y_m = v_m + rho y_{m-1}: end value with zero carry
   D xr[MM];
   D E = zero<double>();
-  {
-    D a;  // v_{m0-1}
-    if (c > 0) a = to_d(T[M - 1 - CST]);
-    else if (periodic) a = to_d(tl[lidx(NT - 1, dl)]);
-    else a = zero<double>();
-    D nxe;  // v_{m0+len}
-    if (c < NC - 1) nxe = to_d(T[CST]);
-    else nxe = periodic ? to_d(tl[dl * DS]) : zero<double>();
-    D b = vat(0);
-    #pragma unroll
-    for (int i = 0; i < MM; ++i) {
-      if (EQ || i < len) {
-        const D nx = (EQ ? (i + 1 < MM) : (i + 1 < len)) ? vat(i + 1 < MM ? i + 1 : i) : nxe;
-        const D tt = sub(add(a, nx), scl(2.0, b));
-        E = fma(rho, E, tt);
-        xr[i] = tt;
-        a = b;
-        b = nx;
-        __builtin_amdgcn_sched_barrier(0);  // keep each LDS read next to its use
-      }
+  #pragma unroll
+  for (int i = 0; i < MM; ++i) {
+    if (EQ || i < len) {
+      xr[i] = vat(i);
+      E = fma(rho, E, xr[i]);
+      __builtin_amdgcn_sched_barrier(0);  // keep each LDS read next to its use
     }
   }
   // ---- forward chunk carries: inclusive scan over chunks 0..NC-2 (length M)
@@ -1634,30 +1629,31 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
         xr[i] = x;
       }
   }
-  // ---- u = v + e, e = rho x, written to the tile rounded to S (the next step
+  // ---- u = (rho/s) x, written to the tile rounded to S (the next step
   //      starts from u as stored, exactly as a new march call would); sector:
   //      rank-one correction of the first row,
-  //      e_m -= Kc (rho^m - rho^{2NT-m}),  Kc = rho^3 x_0 / (1 - rho^{2NT+2})
+  //      x_m -= Kc (rho^m - rho^{2NT-m}),  Kc = rho^2 x_0 / (1 - rho^{2NT+2})
+  const D cs = K->cs;
   if (periodic) {
     #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
-        T[i] = from_d<S>(fma(rho, xr[i], vat(i)));
+        T[i] = from_d<S>(mul(cs, xr[i]));
         __builtin_amdgcn_sched_barrier(0);
       }
   } else {
     const D x0 = shfl_idx(xr[0], seg, 64);
-    const D Kc = mul(mul(mul(rho, rho), mul(rho, x0)), K->sinv);
+    const D Kc = mul(mul(rho, rho), mul(x0, K->sinv));
     D pa = mul(Kc, sPowC[c < kPassBPow ? c : 0]);
     D pb = mul(Kc, sPowS[c < kPassBPow ? c : 0]);
     const D rinv = K->rinv;
     #pragma unroll
     for (int i = 0; i < MM; ++i)
       if (EQ || i < len) {
-        const D e = sub(mul(rho, xr[i]), sub(pa, pb));
+        const D x = sub(xr[i], sub(pa, pb));
         pa = mul(pa, rho);
         pb = mul(pb, rinv);
-        T[i] = from_d<S>(add(vat(i), e));
+        T[i] = from_d<S>(mul(cs, x));
         __builtin_amdgcn_sched_barrier(0);
       }
   }
