@@ -173,6 +173,24 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid,
  * PE3D_EDEVICE (launch failure). */
 pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that forbid
+ * it): pe3d_march with the march's scratch field taken from a file-scope
+ * device array of the library instead of the handle's, and nothing allocated
+ * (no hipMalloc, hipFree or event creation; no profiling records).  Same
+ * arithmetic, kernels and results as pe3d_march, bit for bit.
+ * Limit: the field (nz * ntheta * 8 bytes for PE3D_C64, * 16 for PE3D_C128)
+ * must fit in PE3D_STATIC_SCRATCH_BYTES (32 MiB: every complex64 shape the
+ * kernels accept, complex128 up to 2 Mi points such as 2048 x 1024), else
+ * PE3D_EUNSUPPORTED with nothing enqueued.  The array (one per GPU, held until
+ * the process ends) is shared by every call on that GPU and keeps the last
+ * call's contents; nothing in it needs to start at zero.  Calls that overlap
+ * on one GPU (two streams, two threads, or an unsynchronised host) race on
+ * it: the caller serialises them.  The handle's device must be the current
+ * device (else PE3D_ESTATE).  Errors otherwise as pe3d_march. */
+#define PE3D_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+pe3d_status pe3d_march_static(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream);
+
 /* Release every device and host resource of the handle.  NULL is OK.  The
  * caller must make sure no enqueued work of the handle is still running. */
 pe3d_status pe3d_destroy(pe3d_handle h);

@@ -975,12 +975,17 @@ pe3d_status pe3d_get_info(pe3d_handle h, pe3d_info* info) {
 
 static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream) {
-  if (!h || !u_dev || nsteps < 0 || !aligned16(u_dev)) return PE3D_EINVAL;
-  if (nsteps == 0) return PE3D_OK;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+// The plain march of one problem: the handle's scratch field (pe3d_march) or
+// another of the same size or larger (pe3d_march_static); `profile` false
+// records no events.  Arguments are checked by the callers.
+pe3d_status march_impl(pe3d_handle h, int32_t nsteps, void* u_dev, hipStream_t st, void* scr, bool profile) {
   ProbDesc d = h->desc;
   d.u = u_dev;
+  d.scr = scr;
   d.nsteps = nsteps;
   const double fbytes = 2.0 * double(d.nz) * d.nth * (h->prec ? 16.0 : 8.0);
   if (d.nx2d && !d.nbr && !d.nsr) {
@@ -989,7 +994,7 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
     // as one launch per step); algorithmic bytes: the field in and out once
     if (prof_launch("pass_a_nx2d", h->prec, h->maxm_a, fbytes, st, [&] {
           return launch_pass_a_multi(h->prec, d, h->lds_a, st);
-        }) != hipSuccess)
+        }, profile) != hipSuccess)
       return PE3D_EDEVICE;
     if (launch_advance(nullptr, nullptr, 0, h->d_j, nsteps, st) != hipSuccess) return PE3D_EDEVICE;
     h->j += nsteps;
@@ -1002,16 +1007,39 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
       return PE3D_EDEVICE;
     if (prof_launch("pass_a", h->prec, h->maxm_a, fbytes, st, [&] {
           return launch_pass_a(h->prec, &d, nullptr, nullptr, 0, k, h->lds_a, st);
-        }) != hipSuccess)
+        }, profile) != hipSuccess)
       return PE3D_EDEVICE;
     if (!d.nx2d && prof_launch("pass_b", h->prec, h->maxm_b, fbytes, st, [&] {
           return launch_pass_b(h->prec, &d, nullptr, nullptr, 0, k, h->lds_b, st);
-        }) != hipSuccess)
+        }, profile) != hipSuccess)
       return PE3D_EDEVICE;
   }
   if (launch_advance(nullptr, nullptr, 0, h->d_j, nsteps, st) != hipSuccess) return PE3D_EDEVICE;
   h->j += nsteps;
   return PE3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream) {
+  if (!h || !u_dev || nsteps < 0 || !aligned16(u_dev)) return PE3D_EINVAL;
+  if (nsteps == 0) return PE3D_OK;
+  return march_impl(h, nsteps, u_dev, static_cast<hipStream_t>(stream), h->d_scr, true);
+}
+
+pe3d_status pe3d_march_static(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream) {
+  if (!h || !u_dev || nsteps < 0 || !aligned16(u_dev)) return PE3D_EINVAL;
+  if (nsteps == 0) return PE3D_OK;
+  const size_t fb = (size_t)h->desc.nz * h->desc.nth * (h->prec ? 16u : 8u);
+  if (fb > kStaticScratchBytes) return PE3D_EUNSUPPORTED;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return PE3D_EDEVICE;
+  if (dev != h->device) return PE3D_ESTATE;
+  void* scr = nullptr;
+  if (static_scratch(&scr) != hipSuccess) return PE3D_EDEVICE;
+  return march_impl(h, nsteps, u_dev, static_cast<hipStream_t>(stream), scr, false);
 }
 
 pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream) {

@@ -129,6 +129,10 @@ hipError_t launch_starter(int prec, const ProbDesc& d, double zs, void* u, hipSt
 hipError_t launch_tl(int prec, const ProbDesc& d, const void* u, float* tl, hipStream_t st);
 hipError_t launch_scale(int prec, const ProbDesc& d, const void* u, void* p, double hre, double him,
                         hipStream_t st);  // p = u * (hre + i him)
+// Bytes of the file-scope scratch field that pe3d_march_static uses (one copy
+// per device); its address on the current device (looked up once per device).
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+hipError_t static_scratch(void** ptr);
 
 
 }  // namespace pe3d

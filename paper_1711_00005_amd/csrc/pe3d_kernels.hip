@@ -43,7 +43,6 @@
 // roundings change from step to step and only accumulate as a random walk.
 #include <hip/hip_runtime.h>
 #include <mutex>
-#include <set>
 #include <type_traits>
 #include <utility>
 
@@ -1787,18 +1786,50 @@ __global__ void scale_kernel(const C<R>* u, C<R>* p, size_t n, double hre, doubl
 }
 
 // ============================================================== launchers
-// Raise a kernel's dynamic-LDS limit once per device (thread-safe).
+// Raise a kernel's dynamic-LDS limit once per device (thread-safe).  The
+// (device, kernel) pairs already done sit in a fixed table, so a launch
+// never allocates; past its capacity the attribute is simply set again.
 static hipError_t allow_lds(const void* fn, int bytes) {
   static std::mutex mu;
-  static std::set<std::pair<int, const void*>> done;
+  constexpr int kCap = 512;
+  static std::pair<int, const void*> done[kCap];
+  static int ndone = 0;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(mu);
-  if (done.count({dev, fn})) return hipSuccess;
+  for (int i = 0; i < ndone; ++i)
+    if (done[i].first == dev && done[i].second == fn) return hipSuccess;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) done.insert({dev, fn});
+  if (e == hipSuccess && ndone < kCap) done[ndone++] = {dev, fn};
   return e;
+}
+
+// Scratch field of pe3d_march_static: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends.  Host code
+// never uses the array's name as an address (on the host it is a stand-in,
+// not a device pointer): each device's address comes from
+// hipGetSymbolAddress, called once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void** ptr) {
+  static std::mutex mu;
+  constexpr int kMaxDevices = 64;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 template <typename S, int M>

@@ -42,11 +42,12 @@ PE3D_C64 = 0
 PE3D_C128 = 1
 PE3D_MODE_3D = 0
 PE3D_MODE_NX2D = 1
+PE3D_STATIC_SCRATCH_BYTES = 32 << 20
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
             "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror",
-            "pe3d_set_batch_schedule")
+            "pe3d_set_batch_schedule", "pe3d_march_static")
 
 
 class pe3d_env(ct.Structure):
@@ -90,6 +91,7 @@ _H = ct.c_void_p
 _lib.pe3d_create.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid), ct.POINTER(pe3d_freq),
                              ct.POINTER(_H)]
 _lib.pe3d_march.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p]
+_lib.pe3d_march_static.argtypes = [_H, ct.c_int32, ct.c_void_p, ct.c_void_p]
 _lib.pe3d_destroy.argtypes = [_H]
 _lib.pe3d_footprint.argtypes = [ct.POINTER(pe3d_env), ct.POINTER(pe3d_grid),
                                 ct.POINTER(pe3d_freq), ct.POINTER(ct.c_size_t)]
@@ -238,6 +240,11 @@ def pe3d_march(h, nsteps: int, u_ptr: int, stream_ptr) -> None:
     _check(_lib.pe3d_march(h, int(nsteps), ct.c_void_p(u_ptr), ct.c_void_p(stream_ptr)), "pe3d_march")
 
 
+def pe3d_march_static(h, nsteps: int, u_ptr: int, stream_ptr) -> None:
+    _check(_lib.pe3d_march_static(h, int(nsteps), ct.c_void_p(u_ptr), ct.c_void_p(stream_ptr)),
+           "pe3d_march_static")
+
+
 def pe3d_starter(h, zs: float, u_ptr: int, stream_ptr) -> None:
     _check(_lib.pe3d_starter(h, float(zs), ct.c_void_p(u_ptr), ct.c_void_p(stream_ptr)),
            "pe3d_starter")
@@ -345,6 +352,12 @@ class Pe3d:
 
     def march(self, nsteps: int, u, stream=None):
         pe3d_march(self.h, nsteps, _field_ptr(u, self.nz, self.ntheta, self.precision), _stream_ptr(stream))
+        return u
+
+    def march_static(self, nsteps: int, u, stream=None):
+        """pe3d_march with the library's file-scope scratch field (allocates nothing)."""
+        pe3d_march_static(self.h, nsteps, _field_ptr(u, self.nz, self.ntheta, self.precision),
+                          _stream_ptr(stream))
         return u
 
     def tl(self, u, stream=None):

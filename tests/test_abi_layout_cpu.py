@@ -28,6 +28,7 @@ def _c_layout(P, tmp_path):
         lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
         for field, _ in cls._fields_:
             lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines.append('  printf("macro PE3D_STATIC_SCRATCH_BYTES %zu\\n", (size_t)PE3D_STATIC_SCRATCH_BYTES);')
     lines += ["  return 0;", "}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
@@ -46,3 +47,8 @@ def test_ctypes_structs_match_the_header(P, tmp_path):
         assert c[(name, "size")] == ct.sizeof(cls), name
         for field, _ in cls._fields_:
             assert c[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_static_scratch_limit_matches_the_header(P, tmp_path):
+    c = _c_layout(P, tmp_path)
+    assert c[("macro", "PE3D_STATIC_SCRATCH_BYTES")] == P.PE3D_STATIC_SCRATCH_BYTES
