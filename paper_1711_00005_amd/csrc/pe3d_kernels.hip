@@ -420,7 +420,12 @@ __host__ __device__ constexpr int pass_a_lds_bytes(int esz, int L, int N, int M)
          8 * 16;
 }
 
-template <typename S, int M>
+// MULTI: the depth pass of an N x 2D problem over a fixed medium (no range
+// rows) for every step of a call in one launch: without azimuth coupling a
+// column depends on nothing but itself, so the workgroup's columns stay in
+// LDS from step to step, read from the caller's field once (koff = 0) and
+// written back once.  Otherwise one step, koff steps into the call.
+template <typename S, int M, bool MULTI = false>
 __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
   const int lane = threadIdx.x;
   const int L = d.lpc;
@@ -441,7 +446,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const bool first = (koff == 0);
   const bool ystage = first && !d.nx2d;  // first step of a 3D march: apply [I + s_0 D]
   const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
-  C<S>* __restrict__ dst = (C<S>*)((d.nx2d && koff == d.nsteps - 1) ? d.u : d.scr);
+  C<S>* __restrict__ dst = (C<S>*)((MULTI || (d.nx2d && koff == d.nsteps - 1)) ? d.u : d.scr);
 
   // ---- zero the guard rows of every column buffer, stage the columns.  The
   //      workgroup's columns are one contiguous span of ncols*N values;
@@ -588,7 +593,9 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   const int tc = top ? t : (bot ? t - a : 0);
   const int sc = top ? s : (bot ? sb : M);
   const int tb = bot ? 1 : 0;
-  const int row0 = top ? t * M - s : (bot ? N - 1 - (tc * M - sb) : -1);
+  // (idle lanes read and write the outermost guard row, which no chain lane
+  // reads or writes)
+  const int row0 = top ? t * M - s : (bot ? N - 1 - (tc * M - sb) : -GA);
   const int dir = top ? 1 : (bot ? -1 : 0);
 
   // table byte offsets of the lane's slots (lane-major, padded by M zero rows)
@@ -648,668 +655,199 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
   // Table values are prefetched PF slots ahead.
   constexpr int PF = 6;
 
-  // ---- phase 1: Rt = [I + beta_+ X] w / nbmh along the chain (sliding
-  //      window), local elimination with zero carry -> the lane's map
-  //      yh_out = tp yh_in + E
-  const C<S>* col = buf + cw * CS + GA;
-  D Rv[M];
-  // GREG: the lane's multipliers stay in registers from the RHS sweep to the
-  // elimination and back substitution (no further table reads); otherwise
-  // those sweeps read the table again (fewer registers: complex64 with
-  // M >= 15 keeps 3 waves per SIMD that way)
-  constexpr bool GREG = sizeof(S) == 8 || M <= 13;
-  D Gv[GREG ? M : 1];
-  D E = zero<double>();
-  auto phase1 = [&](auto tab) {
-    D gq[PF], cq[PF];
-    #pragma unroll
-    for (int j = 0; j < PF; ++j)
-      if (j < M) {
-        gq[j] = G_at(tab, j, E);
-        cq[j] = C_at(tab, j, E);
-      }
-    const C<S>* p = col + row0;
-    D wp = to_d(p[-dir]);
-    D wc = to_d(p[0]);
-    // row of the next window entry, advanced by dir per slot; the empty asm
-    // orders the read after the previous slot's value and is applied to the
-    // index, not to a pointer, so the read stays an LDS read
-    int rn = row0;
-    #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const D g = gq[j % PF];
-      const D cdv = cq[j % PF];
-      if constexpr (GREG) Gv[j] = g;
-      rn += dir;
-      asm volatile("" : "+v"(rn) : "v"(E.re));
-      const D wn = to_d(col[rn]);
-      D R;
-      if (j == M - 1) {
-        D c0 = cdv, cp = cbs, cn = cbs, cf = one<double>();
-        if (head) {
-          c0 = hrec(0);
-          cp = hrec(1);
-          cn = hrec(2);
-          cf = hrec(3);
-        }
-        R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
-        const D y = fma(cf, E, R);
-        E = head ? y : mul(g, y);
-      } else {
-        R = fma(cdv, wc, mul(cbs, add(wp, wn)));
-        E = mul(g, add(R, E));
-      }
-      if (j + PF < M) {
-        gq[j % PF] = G_at(tab, j + PF, E);
-        cq[j % PF] = C_at(tab, j + PF, E);
-      }
-      Rv[j] = R;
-      wp = wc;
-      wc = wn;
-    }
-  };
-  if (wtab)
-    phase1(std::true_type{});
-  else
-    phase1(std::false_type{});
-  const D cin = scan_excl<true>(tp, E, t, L, tot);
-
-  // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
-  //      reduced interface right-hand side, divided by nbmh).  The same sweep
-  //      accumulates the lane's local back-substitution end value with zero
-  //      carry, X = sum_j (Gh_0 ... Gh_{j-1}) yh_j (the back substitution
-  //      x_j = yh_j + Gh_j x_{j+1} unrolled from the lane's first slot), so the
-  //      back substitution needs one sweep only; a head lane adds its own
-  //      slot's term once the interface value is known.
-  D X = zero<double>();
-  D pr = one<double>();  // Gh_0 ... Gh_{j-1}
-  if constexpr (GREG) {
-    {
-      D yh = cin;
-      #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const D g = Gv[j];
-        if (j == M - 1) {
-          D cf = one<double>();
-          if (head) cf = hrec(3);
-          const D y = fma(cf, yh, Rv[j]);
-          Rv[j] = head ? y : mul(g, y);
-          if (!head) X = fma(pr, Rv[j], X);
-        } else {
-          yh = mul(g, add(Rv[j], yh));
-          Rv[j] = yh;
-          X = fma(pr, yh, X);
-          pr = mul(pr, g);
-          // keep the accumulation in slot order (not batched up over the sweep)
-          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
-        }
-      }
-    }
-  } else {
-    // The elimination sweep reads the table in every wavefront; a lane that
-    // needs no entry reads the chain's tail row or a zero row instead (the same
-    // address for many lanes, fewer cache lines per read).
-    const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
-    auto G2_at = [&](int j, const D& after) {
-      unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
-      asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(tabG, o);
-    };
-    {
-      D yh = cin;
-      D gq[PF];
+  // one step on the columns in LDS
+  auto step = [&]() __attribute__((always_inline)) {
+    // ---- phase 1: Rt = [I + beta_+ X] w / nbmh along the chain (sliding
+    //      window), local elimination with zero carry -> the lane's map
+    //      yh_out = tp yh_in + E
+    const C<S>* col = buf + cw * CS + GA;
+    D Rv[M];
+    // GREG: the lane's multipliers stay in registers from the RHS sweep to the
+    // elimination and back substitution (no further table reads); otherwise
+    // those sweeps read the table again (fewer registers: complex64 with
+    // M >= 15 keeps 3 waves per SIMD that way)
+    constexpr bool GREG = sizeof(S) == 8 || M <= 13;
+    D Gv[GREG ? M : 1];
+    D E = zero<double>();
+    auto phase1 = [&](auto tab) {
+      D gq[PF], cq[PF];
       #pragma unroll
       for (int j = 0; j < PF; ++j)
-        if (j < M) gq[j] = G2_at(j, yh);
+        if (j < M) {
+          gq[j] = G_at(tab, j, E);
+          cq[j] = C_at(tab, j, E);
+        }
+      const C<S>* p = col + row0;
+      D wp = to_d(p[-dir]);
+      D wc = to_d(p[0]);
+      // row of the next window entry, advanced by dir per slot; the empty asm
+      // orders the read after the previous slot's value and is applied to the
+      // index, not to a pointer, so the read stays an LDS read
+      int rn = row0;
       #pragma unroll
       for (int j = 0; j < M; ++j) {
         const D g = gq[j % PF];
+        const D cdv = cq[j % PF];
+        if constexpr (GREG) Gv[j] = g;
+        rn += dir;
+        asm volatile("" : "+v"(rn) : "v"(E.re));
+        const D wn = to_d(col[rn]);
+        D R;
         if (j == M - 1) {
-          D cf = one<double>();
-          if (head) cf = hrec(3);
-          const D y = fma(cf, yh, Rv[j]);
-          Rv[j] = head ? y : mul(g, y);
-          if (!head) X = fma(pr, Rv[j], X);
-        } else {
-          yh = mul(g, add(Rv[j], yh));
-          Rv[j] = yh;
-          X = fma(pr, yh, X);
-          pr = mul(pr, g);
-          // keep the accumulation in slot order (not batched up over the sweep)
-          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
-        }
-        if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
-      }
-    }
-  }
-  // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
-  //      (inverse entries times nbmh, r divided by nbmh)
-  if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
-  __syncthreads();
-  if (head) {
-    Rv[M - 1] = fma(hrec(4), Rv[M - 1], mul(hrec(5), xch[2 * cw + (bot ? 0 : 1)]));
-    X = fma(pr, Rv[M - 1], X);
-  }
-  const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
-
-  // ---- phase 3: back substitution with the exact carry, written to the column
-  //      buffer (the input was last read before the interface barrier; zero
-  //      slots and idle lanes write guard rows only)
-  if constexpr (GREG) {
-    {
-      D x = xin;
-      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
-      #pragma unroll
-      for (int jj = 0; jj < M; ++jj) {
-        const int j = M - 1 - jj;
-        if (j == M - 1 && head) x = Rv[j];
-        else x = fma(Gv[j], x, Rv[j]);
-        *p = from_d<S>(x);
-        p -= dir;
-      }
-    }
-  } else {
-    auto phase3 = [&](auto tab) {
-      D x = xin;
-      D gq[PF];
-      #pragma unroll
-      for (int jj = 0; jj < PF; ++jj)
-        if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
-      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
-      #pragma unroll
-      for (int jj = 0; jj < M; ++jj) {
-        const int j = M - 1 - jj;
-        const D g = gq[jj % PF];
-        if (j == M - 1 && head) x = Rv[j];
-        else x = fma(g, x, Rv[j]);
-        *p = from_d<S>(x);
-        p -= dir;
-        if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
-      }
-    };
-    if (wtab)
-      phase3(std::true_type{});
-    else
-      phase3(std::false_type{});
-  }
-  __syncthreads();
-  {
-    // the staging addresses are recomputed here rather than kept live
-    int lane_r = lane;
-    asm volatile("" : "+v"(lane_r));
-    C<S>* __restrict__ out = dst + (size_t)m0 * N;
-    if (pairs) {
-      using F4 = float __attribute__((ext_vector_type(4)));
-      constexpr int MP = (M + 1) / 2;
-      __attribute__((address_space(1))) F4* o4 = (__attribute__((address_space(1))) F4*)out;
-      #pragma unroll
-      for (int q = 0; q < MP; ++q) {
-        const int e = 2 * (lane_r + q * kPassAThreads);
-        if (e < span) {
-          const int c = cpw == 1 ? 0 : int((float(e) + 0.5f) * invN);
-          const int idx = c * CS + GA + (e - c * N);
-          const C<S> x0 = buf[idx], x1 = buf[idx + 1];
-          F4 w;
-          w.x = float(x0.re);
-          w.y = float(x0.im);
-          w.z = float(x1.re);
-          w.w = float(x1.im);
-          o4[e >> 1] = w;
-        }
-      }
-    } else if (cpw == 1) {
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int e = lane_r + q * kPassAThreads;
-        if (e < span) gstore(out, unsigned(e), buf[GA + e]);
-      }
-    } else if (N >= kPassAThreads) {
-      int r = lane_r, idx = GA + lane_r;
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int e = lane_r + q * kPassAThreads;
-        if (e < span) gstore(out, unsigned(e), buf[idx]);
-        r += kPassAThreads;
-        idx += kPassAThreads;
-        if (r >= N) {
-          r -= N;
-          idx += 2 * GA;
-        }
-      }
-    } else {
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int e = lane_r + q * kPassAThreads;
-        if (e < span) {
-          const int c = int((float(e) + 0.5f) * invN);
-          gstore(out, unsigned(e), buf[c * CS + GA + (e - c * N)]);
-        }
-      }
-    }
-  }
-}
-
-// The depth pass of an N x 2D problem over a fixed medium (no range rows)
-// for every step of a call in one launch: the workgroup's columns stay in
-// LDS from step to step (no azimuth coupling), read from the caller's field
-// once and written back once.  The body of pass_a_body with the steps in a
-// loop (kept apart so that the single-step kernels keep their own code).
-template <typename S, int M>
-__device__ __forceinline__ void pass_a_body_multi(const ProbDesc& d, int tile, unsigned char* smem) {
-  const int koff = 0;
-  const int lane = threadIdx.x;
-  const int L = d.lpc;
-  const int lgL = 31 - __clz(L);
-  const int cpw = kPassAThreads >> lgL;
-  const int cw = lane >> lgL;
-  const int t = lane & (L - 1);
-  const int N = d.nz, NT = d.nth;
-  const int m0 = tile * cpw;
-  const int m = m0 + cw;
-  const bool colok = m < NT;
-  const int ncols = min(cpw, NT - m0);
-  constexpr int GA = M + 1;
-  const int CS = N + 2 * GA;
-  C<S>* buf = reinterpret_cast<C<S>*>(smem);
-  D* xch = reinterpret_cast<D*>(smem + pass_a_align(cpw * CS * int(sizeof(C<S>))));
-  D* tot = xch + 2 * cpw;
-  const bool first = (koff == 0);
-  const bool ystage = first && !d.nx2d;  // first step of a 3D march: apply [I + s_0 D]
-  const C<S>* __restrict__ src = (const C<S>*)(first ? d.u : d.scr);
-  C<S>* __restrict__ dst = (C<S>*)d.u;
-
-  // ---- zero the guard rows of every column buffer, stage the columns.  The
-  //      workgroup's columns are one contiguous span of ncols*N values;
-  //      thread `lane` takes entries lane + 256 q, q < M (ncols*N < 256 M),
-  //      all loads issued before the first LDS write.  On the first step
-  //      apply [I + s_0 D_theta] from the neighbouring columns.
-  // the column's water nodes (they set the lane roles) are read first, so
-  // that their latency overlaps the staging
-  const int nw_early = colok ? ((const __attribute__((address_space(1))) int*)d.nwcol)[m] : 0;
-  // the tables of this step's water row (uniform scalar loads)
-  const __attribute__((address_space(4))) TabPtrs* const tcur =
-      (const __attribute__((address_space(4))) TabPtrs*)d.cur;
-  const void* const tabG = tcur->tabG;
-  const void* const tabC = tcur->tabC;
-  const void* const tabP = tcur->tabP;
-  const void* const trec = tcur->rec;
-  for (int i = lane; i < cpw * 2 * GA; i += kPassAThreads) {
-    const int c = i / (2 * GA);
-    const int g = i - c * 2 * GA;
-    buf[c * CS + (g < GA ? g : N + g)] = zero<S>();
-  }
-  const int span = ncols * N;
-  const float invN = 1.0f / float(N);
-  const C<S>* __restrict__ base = src + (size_t)m0 * N;
-  // complex64 with an even column length: thread `lane` takes the pairs of
-  // entries 2 (lane + 256 q), q < (M+1)/2, with one 16-byte load each (a pair
-  // never crosses a column; the span and its base are 16-byte aligned)
-  const bool pairs = sizeof(S) == 4 && (N & 1) == 0;
-  if (!ystage && pairs) {
-    using F4 = float __attribute__((ext_vector_type(4)));
-    constexpr int MP = (M + 1) / 2;
-    const __attribute__((address_space(1))) F4* b4 = (const __attribute__((address_space(1))) F4*)base;
-    F4 v2[MP];
-    __builtin_amdgcn_s_setprio(2);  // issue the staging loads at raised priority
-    #pragma unroll
-    for (int q = 0; q < MP; ++q) {
-      const int e = 2 * (lane + q * kPassAThreads);
-      if (e < span) v2[q] = b4[e >> 1];
-    }
-    __builtin_amdgcn_s_setprio(0);
-    #pragma unroll
-    for (int q = 0; q < MP; ++q) {
-      const int e = 2 * (lane + q * kPassAThreads);
-      if (e < span) {
-        const int c = cpw == 1 ? 0 : int((float(e) + 0.5f) * invN);
-        const int idx = c * CS + GA + (e - c * N);
-        buf[idx] = mk<S>(S(v2[q].x), S(v2[q].y));
-        buf[idx + 1] = mk<S>(S(v2[q].z), S(v2[q].w));
-      }
-    }
-  } else if (!ystage) {
-    typename Stage<S>::T v[M];
-    #pragma unroll
-    for (int q = 0; q < M; ++q) {
-      const int e = lane + q * kPassAThreads;
-      if (e < span) v[q] = stage_load(base, e);
-    }
-    // LDS index of span entry e (column c = e / N, row e - c N): c CS + GA + e - c N
-    if (cpw == 1) {
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int e = lane + q * kPassAThreads;
-        if (e < span) buf[GA + e] = stage_val(v[q]);
-      }
-    } else if (N >= kPassAThreads) {
-      // e advances by 256 <= N per entry: the column advances by at most one
-      int r = lane, idx = GA + lane;
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        if (lane + q * kPassAThreads < span) buf[idx] = stage_val(v[q]);
-        r += kPassAThreads;
-        idx += kPassAThreads;
-        if (r >= N) {
-          r -= N;
-          idx += 2 * GA;
-        }
-      }
-    } else {
-      #pragma unroll
-      for (int q = 0; q < M; ++q) {
-        const int e = lane + q * kPassAThreads;
-        if (e < span) {
-          const int c = int((float(e) + 0.5f) * invN);
-          buf[c * CS + GA + (e - c * N)] = stage_val(v[q]);
-        }
-      }
-    }
-  } else {
-    // first step of a march call only: groups of 4 entries (a rolled loop), so
-    // that its three loads per entry do not set the kernel's register count
-    const long long j = *d.jdev + koff;
-    const double s0 = sigma_of(d, j);  // s_0 = i * s0
-    constexpr int QG = 4;
-#pragma unroll 1
-    for (int q0 = 0; q0 < M; q0 += QG) {
-      typename Stage<S>::T vc[QG], vl[QG], vr[QG];
-      #pragma unroll
-      for (int qq = 0; qq < QG; ++qq) {
-        const int e = lane + (q0 + qq) * kPassAThreads;
-        if (q0 + qq < M && e < span) {
-          const int c = int((float(e) + 0.5f) * invN);
-          const int r = e - c * N;
-          const int mm = m0 + c;
-          int ml = mm - 1, mr = mm + 1;
-          if (d.periodic) {
-            if (ml < 0) ml = NT - 1;
-            if (mr >= NT) mr = 0;
+          D c0 = cdv, cp = cbs, cn = cbs, cf = one<double>();
+          if (head) {
+            c0 = hrec(0);
+            cp = hrec(1);
+            cn = hrec(2);
+            cf = hrec(3);
           }
-          // sector edges: load an in-range column, zero it below
-          vc[qq] = stage_load(base, e);
-          vl[qq] = stage_load(src, (size_t)max(ml, 0) * N + r);
-          vr[qq] = stage_load(src, (size_t)min(mr, NT - 1) * N + r);
-        }
-      }
-      #pragma unroll
-      for (int qq = 0; qq < QG; ++qq) {
-        const int e = lane + (q0 + qq) * kPassAThreads;
-        if (q0 + qq < M && e < span) {
-          const int c = int((float(e) + 0.5f) * invN);
-          const int mm = m0 + c;
-          const bool hl = d.periodic || mm > 0, hr = d.periodic || mm < NT - 1;
-          const D uc = to_d(stage_val(vc[qq]));
-          const D ul = hl ? to_d(stage_val(vl[qq])) : zero<double>();
-          const D ur = hr ? to_d(stage_val(vr[qq])) : zero<double>();
-          const D dd = sub(add(ul, ur), scl(2.0, uc));
-          buf[c * CS + GA + (e - c * N)] = from_d<S>(mk<double>(uc.re - s0 * dd.im, uc.im + s0 * dd.re));
-        }
-      }
-    }
-  }
-
-  // ---- lane role: the column's water nodes nw (at r_{j+1}, written by
-  //      the medium update before this launch, when the depth depends on range)
-  //      set its interface row k and record
-  const int nw = nw_early;
-  const int k = min(max(nw - 1, 0), N - 2);
-  const int a = (k + 1) / M + 1;
-  const int s = a * M - (k + 1);
-  const int nbl = (N - k - 1) / M + 1;
-  const int sb = nbl * M - (N - k - 1);
-  const bool top = colok && t < a;
-  const bool bot = colok && !top && t < a + nbl;
-  const bool head = colok && (t == a - 1 || t == a + nbl - 1);
-  const int tc = top ? t : (bot ? t - a : 0);
-  const int sc = top ? s : (bot ? sb : M);
-  const int tb = bot ? 1 : 0;
-  const int row0 = top ? t * M - s : (bot ? N - 1 - (tc * M - sb) : -1);
-  const int dir = top ? 1 : (bot ? -1 : 0);
-
-  // table byte offsets of the lane's slots (lane-major, padded by M zero rows)
-  const int LT = d.lt;
-  unsigned offb[M];
-  {
-    const int lo = tb * M * LT + (M - sc) * LT + tc;  // slot j < sc
-    const int hi = tb * M * LT + tc + 1 - sc * LT;    // slot j >= sc
-    #pragma unroll
-    for (int j = 0; j < M; ++j) offb[j] = unsigned((j < sc ? lo : hi) + j * LT) * 16u;
-  }
-  // A prefetch is issued only after the current slot's value `after` exists:
-  // its offset passes through an empty volatile asm that also reads that
-  // value, so the compiler can neither hoist the load to the phase start nor
-  // sink the slot's arithmetic below it.
-  // Table reads.  A lane needs the tables only for its chain rows below the
-  // chain's converged tail: slots j < jlo are the chain's leading zero rows
-  // (only its first lane has them), slots j >= jhi tail rows (the chain's
-  // constants); idle lanes need none.  A wavefront in which no lane needs
-  // them (wtab false) runs the sweeps with the constants instead of reads
-  // (the tables hold the same values, so both forms give the same numbers).
-  const int jlo = (top || bot) ? max(sc - tc * M, 0) : M;
-  const int jhi = (top || bot) ? min(max(d.bconv[tb] + sc - tc * M, jlo), M) : M;
-  const bool wtab = __ballot(jlo < jhi) != 0;
-  auto G_at = [&](auto tab, int j, const D& after) {
-    if constexpr (decltype(tab)::value) {
-      unsigned o = offb[j];
-      asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(tabG, o);
-    } else {
-      D v = j < jlo ? zero<double>() : mk<double>(d.gt_re[tb], d.gt_im[tb]);
-      asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));  // same order as the reads
-      return v;
-    }
-  };
-  auto C_at = [&](auto tab, int j, const D& after) {
-    if constexpr (decltype(tab)::value) {
-      unsigned o = offb[j];
-      asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(tabC, o);
-    } else {
-      D v = j < jlo ? zero<double>() : mk<double>(d.ct_re[tb], d.ct_im[tb]);
-      asm volatile("" : "+v"(v.re), "+v"(v.im) : "v"(after.re));
-      return v;
-    }
-  };
-  // the head lanes' interface coefficients: RHS diagonal, previous and next
-  // coefficient, elimination multiplier, then the two inverse entries
-  const unsigned hoff = unsigned(nw * 12 + (bot ? 6 : 0)) * 16u;  // byte offset in the records
-  auto hrec = [&](int q) { return gload_b(trec, hoff + unsigned(q) * 16u); };
-
-  const D cbs = mk<double>(d.cbs_re, d.cbs_im);
-  D tp = zero<double>();
-  if (top || bot) tp = gload_b(tabP, unsigned((tb * (M + 1) + sc) * L + tc) * 16u);
-  __syncthreads();
-
-  // Table values are prefetched PF slots ahead.
-  constexpr int PF = 6;
-
-  // every step of the call on the columns in LDS
-  for (int kk = 0; kk < d.nsteps; ++kk) {
-  // ---- phase 1: Rt = [I + beta_+ X] w / nbmh along the chain (sliding
-  //      window), local elimination with zero carry -> the lane's map
-  //      yh_out = tp yh_in + E
-  const C<S>* col = buf + cw * CS + GA;
-  D Rv[M];
-  // GREG: the lane's multipliers stay in registers from the RHS sweep to the
-  // elimination and back substitution (no further table reads); otherwise
-  // those sweeps read the table again (fewer registers: complex64 with
-  // M >= 15 keeps 3 waves per SIMD that way)
-  constexpr bool GREG = sizeof(S) == 8 || M <= 13;
-  D Gv[GREG ? M : 1];
-  D E = zero<double>();
-  auto phase1 = [&](auto tab) {
-    D gq[PF], cq[PF];
-    #pragma unroll
-    for (int j = 0; j < PF; ++j)
-      if (j < M) {
-        gq[j] = G_at(tab, j, E);
-        cq[j] = C_at(tab, j, E);
-      }
-    const C<S>* p = col + row0;
-    D wp = to_d(p[-dir]);
-    D wc = to_d(p[0]);
-    // row of the next window entry, advanced by dir per slot; the empty asm
-    // orders the read after the previous slot's value and is applied to the
-    // index, not to a pointer, so the read stays an LDS read
-    int rn = row0;
-    #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const D g = gq[j % PF];
-      const D cdv = cq[j % PF];
-      if constexpr (GREG) Gv[j] = g;
-      rn += dir;
-      asm volatile("" : "+v"(rn) : "v"(E.re));
-      const D wn = to_d(col[rn]);
-      D R;
-      if (j == M - 1) {
-        D c0 = cdv, cp = cbs, cn = cbs, cf = one<double>();
-        if (head) {
-          c0 = hrec(0);
-          cp = hrec(1);
-          cn = hrec(2);
-          cf = hrec(3);
-        }
-        R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
-        const D y = fma(cf, E, R);
-        E = head ? y : mul(g, y);
-      } else {
-        R = fma(cdv, wc, mul(cbs, add(wp, wn)));
-        E = mul(g, add(R, E));
-      }
-      if (j + PF < M) {
-        gq[j % PF] = G_at(tab, j + PF, E);
-        cq[j % PF] = C_at(tab, j + PF, E);
-      }
-      Rv[j] = R;
-      wp = wc;
-      wc = wn;
-    }
-  };
-  if (wtab)
-    phase1(std::true_type{});
-  else
-    phase1(std::false_type{});
-  const D cin = scan_excl<true>(tp, E, t, L, tot);
-
-  // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
-  //      reduced interface right-hand side, divided by nbmh).  The same sweep
-  //      accumulates the lane's local back-substitution end value with zero
-  //      carry, X = sum_j (Gh_0 ... Gh_{j-1}) yh_j (the back substitution
-  //      x_j = yh_j + Gh_j x_{j+1} unrolled from the lane's first slot), so the
-  //      back substitution needs one sweep only; a head lane adds its own
-  //      slot's term once the interface value is known.
-  D X = zero<double>();
-  D pr = one<double>();  // Gh_0 ... Gh_{j-1}
-  if constexpr (GREG) {
-    {
-      D yh = cin;
-      #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const D g = Gv[j];
-        if (j == M - 1) {
-          D cf = one<double>();
-          if (head) cf = hrec(3);
-          const D y = fma(cf, yh, Rv[j]);
-          Rv[j] = head ? y : mul(g, y);
-          if (!head) X = fma(pr, Rv[j], X);
+          R = fma(c0, wc, fma(cp, wp, mul(cn, wn)));
+          const D y = fma(cf, E, R);
+          E = head ? y : mul(g, y);
         } else {
-          yh = mul(g, add(Rv[j], yh));
-          Rv[j] = yh;
-          X = fma(pr, yh, X);
-          pr = mul(pr, g);
-          // keep the accumulation in slot order (not batched up over the sweep)
-          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+          R = fma(cdv, wc, mul(cbs, add(wp, wn)));
+          E = mul(g, add(R, E));
         }
-      }
-    }
-  } else {
-    // The elimination sweep reads the table in every wavefront; a lane that
-    // needs no entry reads the chain's tail row or a zero row instead (the same
-    // address for many lanes, fewer cache lines per read).
-    const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
-    auto G2_at = [&](int j, const D& after) {
-      unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
-      asm volatile("" : "+v"(o) : "v"(after.re));
-      return gload_b(tabG, o);
-    };
-    {
-      D yh = cin;
-      D gq[PF];
-      #pragma unroll
-      for (int j = 0; j < PF; ++j)
-        if (j < M) gq[j] = G2_at(j, yh);
-      #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const D g = gq[j % PF];
-        if (j == M - 1) {
-          D cf = one<double>();
-          if (head) cf = hrec(3);
-          const D y = fma(cf, yh, Rv[j]);
-          Rv[j] = head ? y : mul(g, y);
-          if (!head) X = fma(pr, Rv[j], X);
-        } else {
-          yh = mul(g, add(Rv[j], yh));
-          Rv[j] = yh;
-          X = fma(pr, yh, X);
-          pr = mul(pr, g);
-          // keep the accumulation in slot order (not batched up over the sweep)
-          asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+        if (j + PF < M) {
+          gq[j % PF] = G_at(tab, j + PF, E);
+          cq[j % PF] = C_at(tab, j + PF, E);
         }
-        if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
-      }
-    }
-  }
-  // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
-  //      (inverse entries times nbmh, r divided by nbmh)
-  if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
-  __syncthreads();
-  if (head) {
-    Rv[M - 1] = fma(hrec(4), Rv[M - 1], mul(hrec(5), xch[2 * cw + (bot ? 0 : 1)]));
-    X = fma(pr, Rv[M - 1], X);
-  }
-  const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
-
-  // ---- phase 3: back substitution with the exact carry, written to the column
-  //      buffer (the input was last read before the interface barrier; zero
-  //      slots and idle lanes write guard rows only)
-  if constexpr (GREG) {
-    {
-      D x = xin;
-      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
-      #pragma unroll
-      for (int jj = 0; jj < M; ++jj) {
-        const int j = M - 1 - jj;
-        if (j == M - 1 && head) x = Rv[j];
-        else x = fma(Gv[j], x, Rv[j]);
-        *p = from_d<S>(x);
-        p -= dir;
-      }
-    }
-  } else {
-    auto phase3 = [&](auto tab) {
-      D x = xin;
-      D gq[PF];
-      #pragma unroll
-      for (int jj = 0; jj < PF; ++jj)
-        if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
-      C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
-      #pragma unroll
-      for (int jj = 0; jj < M; ++jj) {
-        const int j = M - 1 - jj;
-        const D g = gq[jj % PF];
-        if (j == M - 1 && head) x = Rv[j];
-        else x = fma(g, x, Rv[j]);
-        *p = from_d<S>(x);
-        p -= dir;
-        if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
+        Rv[j] = R;
+        wp = wc;
+        wc = wn;
       }
     };
     if (wtab)
-      phase3(std::true_type{});
+      phase1(std::true_type{});
     else
-      phase3(std::false_type{});
-  }
-  __syncthreads();
+      phase1(std::false_type{});
+    const D cin = scan_excl<true>(tp, E, t, L, tot);
+
+    // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
+    //      reduced interface right-hand side, divided by nbmh).  The same sweep
+    //      accumulates the lane's local back-substitution end value with zero
+    //      carry, X = sum_j (Gh_0 ... Gh_{j-1}) yh_j (the back substitution
+    //      x_j = yh_j + Gh_j x_{j+1} unrolled from the lane's first slot), so the
+    //      back substitution needs one sweep only; a head lane adds its own
+    //      slot's term once the interface value is known.
+    D X = zero<double>();
+    D pr = one<double>();  // Gh_0 ... Gh_{j-1}
+    if constexpr (GREG) {
+      {
+        D yh = cin;
+        #pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const D g = Gv[j];
+          if (j == M - 1) {
+            D cf = one<double>();
+            if (head) cf = hrec(3);
+            const D y = fma(cf, yh, Rv[j]);
+            Rv[j] = head ? y : mul(g, y);
+            if (!head) X = fma(pr, Rv[j], X);
+          } else {
+            yh = mul(g, add(Rv[j], yh));
+            Rv[j] = yh;
+            X = fma(pr, yh, X);
+            pr = mul(pr, g);
+            // keep the accumulation in slot order (not batched up over the sweep)
+            asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+          }
+        }
+      }
+    } else {
+      // The elimination sweep reads the table in every wavefront; a lane that
+      // needs no entry reads the chain's tail row or a zero row instead (the same
+      // address for many lanes, fewer cache lines per read).
+      const unsigned toff = unsigned(tb * M * LT + ((N - 2 + M) % M) * LT + (N - 2 + M) / M) * 16u;
+      auto G2_at = [&](int j, const D& after) {
+        unsigned o = (j >= jlo && j < jhi) ? offb[j] : (j < jlo ? 0u : toff);
+        asm volatile("" : "+v"(o) : "v"(after.re));
+        return gload_b(tabG, o);
+      };
+      {
+        D yh = cin;
+        D gq[PF];
+        #pragma unroll
+        for (int j = 0; j < PF; ++j)
+          if (j < M) gq[j] = G2_at(j, yh);
+        #pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const D g = gq[j % PF];
+          if (j == M - 1) {
+            D cf = one<double>();
+            if (head) cf = hrec(3);
+            const D y = fma(cf, yh, Rv[j]);
+            Rv[j] = head ? y : mul(g, y);
+            if (!head) X = fma(pr, Rv[j], X);
+          } else {
+            yh = mul(g, add(Rv[j], yh));
+            Rv[j] = yh;
+            X = fma(pr, yh, X);
+            pr = mul(pr, g);
+            // keep the accumulation in slot order (not batched up over the sweep)
+            asm volatile("" : "+v"(X.re), "+v"(X.im), "+v"(pr.re), "+v"(pr.im) : "v"(yh.re));
+          }
+          if (j + PF < M) gq[j % PF] = G2_at(j + PF, yh);
+        }
+      }
+    }
+    // ---- 2x2 interface block: v_k = i00 r_k + i01 r_{k+1}, v_{k+1} = i10 r_k + i11 r_{k+1}
+    //      (inverse entries times nbmh, r divided by nbmh)
+    if (head) xch[2 * cw + (bot ? 1 : 0)] = Rv[M - 1];
+    __syncthreads();
+    if (head) {
+      Rv[M - 1] = fma(hrec(4), Rv[M - 1], mul(hrec(5), xch[2 * cw + (bot ? 0 : 1)]));
+      X = fma(pr, Rv[M - 1], X);
+    }
+    const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
+
+    // ---- phase 3: back substitution with the exact carry, written to the column
+    //      buffer (the input was last read before the interface barrier; zero
+    //      slots and idle lanes write guard rows only)
+    if constexpr (GREG) {
+      {
+        D x = xin;
+        C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
+        #pragma unroll
+        for (int jj = 0; jj < M; ++jj) {
+          const int j = M - 1 - jj;
+          if (j == M - 1 && head) x = Rv[j];
+          else x = fma(Gv[j], x, Rv[j]);
+          *p = from_d<S>(x);
+          p -= dir;
+        }
+      }
+    } else {
+      auto phase3 = [&](auto tab) {
+        D x = xin;
+        D gq[PF];
+        #pragma unroll
+        for (int jj = 0; jj < PF; ++jj)
+          if (jj < M) gq[jj] = G_at(tab, M - 1 - jj, x);
+        C<S>* p = buf + cw * CS + GA + row0 + dir * (M - 1);
+        #pragma unroll
+        for (int jj = 0; jj < M; ++jj) {
+          const int j = M - 1 - jj;
+          const D g = gq[jj % PF];
+          if (j == M - 1 && head) x = Rv[j];
+          else x = fma(g, x, Rv[j]);
+          *p = from_d<S>(x);
+          p -= dir;
+          if (jj + PF < M) gq[jj % PF] = G_at(tab, j - PF, x);
+        }
+      };
+      if (wtab)
+        phase3(std::true_type{});
+      else
+        phase3(std::false_type{});
+    }
+    __syncthreads();
+  };
+  // every step of the call (MULTI), else this one
+  if constexpr (MULTI) {
+    for (int kk = 0; kk < d.nsteps; ++kk) step();
+  } else {
+    step();
   }
   {
     // the staging addresses are recomputed here rather than kept live
@@ -1378,7 +916,7 @@ __global__ PE3D_PASS_A_ATTR void pass_a_single(ProbDesc d, int koff) {
 template <typename S, int M>
 __global__ PE3D_PASS_A_ATTR void pass_a_multi(ProbDesc d) {
   extern __shared__ __align__(16) unsigned char smem_a[];
-  pass_a_body_multi<S, M>(d, blockIdx.x, smem_a);
+  pass_a_body<S, M, true>(d, blockIdx.x, 0, smem_a);
 }
 
 // Batched launch over work items of problems with any M: each workgroup takes

@@ -214,6 +214,35 @@ def test_size_limits_match_oracle(torch, P, case):
     assert O.rel_l2(got, ref) < TOL[prec], name
 
 
+# Depth-pass shapes whose complex64 bodies keep multipliers in LDS between the
+# sweeps (chunks of M = 15 and 17 rows) at every lane count the rule gives for
+# them, under a wedge whose interface row moves over many chunk offsets from
+# column to column (so that every lane role, idle lanes included, occurs).
+CHUNKS = [
+    # name, nz (lanes L, rows per lane M)
+    ("L16_M15", 224), ("L16_M17", 254), ("L32_M15", 448), ("L32_M17", 512),
+    ("L64_M15", 944), ("L64_M17", 1070), ("L128_M15", 1904), ("L128_M17", 2158),
+    ("L256_M15", 3824), ("L256_M17", 4096),
+]
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+@pytest.mark.parametrize("case", CHUNKS, ids=[c[0] for c in CHUNKS])
+def test_depth_chunk_shapes_match_oracle(torch, P, case, prec):
+    name, nz = case
+    env = W.wedge_env()
+    grid = W.Grid(nz=nz, ntheta=48, theta0=0.1, width=W.TWO_PI, dr=10.0, precision=prec)
+    m = P.Pe3d(env, grid, 80.0)
+    info = m.info()
+    m.close()
+    assert (info.pass_a_lanes, info.pass_a_chunk) == tuple(int(x) for x in name[1:].split("_M")), name
+    st = O.setup(env, grid, 80.0)
+    u0 = O.starter(st, 100.0) * (1 + 0.3 * np.cos(st.theta))[:, None] + 0.05 * W.random_field(48, nz, nz)
+    got, ref = run_pair(torch, P, env, grid, 80.0, u0, 3, name)
+    assert np.isfinite(got).all(), name
+    assert O.rel_l2(got, ref) < TOL[prec], name
+
+
 # ---------------------------------------------------------------- state and batching
 @pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
 @pytest.mark.parametrize("lanes", [(0, 0), (64, 0), (256, 0), (0, 32), (0, 64), (128, 64)])
@@ -467,6 +496,8 @@ def test_config4_batch_matches_oracle_on_samples(torch, P, prec):
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]
     P.march_batch(ms, 2, us, use_graph=True)
     torch.cuda.synchronize()
+    # every field finite (a NaN anywhere would also reach the sampled norms)
+    assert all(bool(torch.isfinite(torch.view_as_real(u)).all()) for u in us)
     for i in (0, 21, 42, 63):
         p = probs[i]
         st = O.setup(p.env, p.grid, p.f_hz)
