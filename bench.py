@@ -70,8 +70,10 @@ def parse():
                     help="also time the config-2 grid over the range-dependent sloping bottom")
     ap.add_argument("--tune", action="store_true",
                     help="choose every problem's kernel lanes by timing its shape alone (tune.py) first")
-    ap.add_argument("--serve-requests", type=int, default=300)
-    ap.add_argument("--serve-range-scale", type=float, default=0.25)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served stream (the first n of the 2000-request trace)")
+    ap.add_argument("--serve-range-scale", type=float, default=1.0,
+                    help="multiply every served request's range (and steps) by this factor")
     ap.add_argument("--serve-chunk", type=int, default=20,
                     help="range steps every resident request advances per served iteration")
     ap.add_argument("--serve-backlog-chunk", type=int, default=100,
@@ -345,7 +347,8 @@ def main():
                          "Ntheta by sqrt(f) and width, dr=clamp(1500/f,2,75) m")
         out["serving"] = rep
         log(f"serve: p50 {rep['p50_latency_s']:.3f} s, p99 {rep['p99_latency_s']:.3f} s, "
-            f"{rep['throughput_pt_steps_per_s']:.3e} pt*steps/s")
+            f"{rep['throughput_pt_steps_per_s']:.3e} pt*steps/s served of "
+            f"{rep['offered_pt_steps_per_s']:.3e} offered, makespan {rep['makespan_s']:.2f} s")
     if args.precision_study:
         out["precision_study"] = precision_study(P)
     if args.nx2d_report:

@@ -192,7 +192,12 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
 pe3d_status pe3d_march_static(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream);
 
 /* Release every device and host resource of the handle.  NULL is OK.  The
- * caller must make sure no enqueued work of the handle is still running. */
+ * caller must make sure no enqueued work of the handle is still running.
+ * Does not synchronise the device: the handle's device memory goes back to
+ * the library's pool (reused by later handles and batch plans of the same
+ * size class, returned to the runtime only when an allocation fails), and
+ * the batch plans that used the handle are freed once their last work has
+ * finished. */
 pe3d_status pe3d_destroy(pe3d_handle h);
 
 /* Device bytes pe3d_create would allocate for these arguments (coefficient

@@ -70,6 +70,76 @@ hipError_t upload(void* dst, const void* src, size_t n) {
   return hipStreamSynchronize(s);
 }
 
+// ------------------------------------------------------------------ device pool
+// Device memory of handles (tables, scratch field) and batch plans comes from
+// a per-device pool: a released block is kept and handed to a later request
+// of the same size class instead of being returned with hipFree, which waits
+// for the whole device (a served stream creates and destroys handles while
+// other requests' work runs).  Size classes: multiples of 64 KiB up to
+// 1 MiB, then 8 steps per power of two (at most 12.5 % above the request).
+// Pooled blocks are returned to the runtime only when an allocation fails.
+size_t pool_class(size_t n) {
+  const size_t g0 = size_t(64) << 10;
+  if (n <= (size_t(1) << 20)) return (std::max<size_t>(n, 1) + g0 - 1) / g0 * g0;
+  size_t p = size_t(1) << 20;
+  while (p * 2 <= n) p *= 2;
+  const size_t g = p / 8;
+  return (n + g - 1) / g * g;
+}
+std::mutex g_pool_mu;
+std::map<std::pair<int, size_t>, std::vector<void*>> g_pool_free;  // (device, class) -> blocks
+std::map<void*, std::pair<int, size_t>> g_pool_live;               // live block -> (device, class)
+
+hipError_t pool_alloc(void** out, size_t n) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t c = pool_class(n);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_free.find({dev, c});
+  if (it != g_pool_free.end() && !it->second.empty()) {
+    *out = it->second.back();
+    it->second.pop_back();
+    g_pool_live[*out] = {dev, c};
+    return hipSuccess;
+  }
+  e = hipMalloc(out, c);
+  if (e != hipSuccess) {
+    // give the pooled blocks of this device back and try once more
+    (void)hipGetLastError();
+    for (auto& kv : g_pool_free)
+      if (kv.first.first == dev) {
+        for (void* b : kv.second) (void)hipFree(b);
+        kv.second.clear();
+      }
+    e = hipMalloc(out, c);
+    if (e != hipSuccess) return e;
+  }
+  g_pool_live[*out] = {dev, c};
+  return hipSuccess;
+}
+
+// The block must no longer be used by any enqueued work.
+void pool_release(void* b) {
+  if (!b) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_live.find(b);
+  if (it == g_pool_live.end()) return;
+  g_pool_free[it->second].push_back(b);
+  g_pool_live.erase(it);
+}
+
+// The device blocks of a destroyed handle, released to the pool when the
+// last plan that used the handle is freed (its last work has finished).
+struct HandleBlocks {
+  void* tables = nullptr;
+  void* scr = nullptr;
+  ~HandleBlocks() {
+    pool_release(scr);
+    pool_release(tables);
+  }
+};
+
 // ------------------------------------------------------------------ validation
 pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) {
   if (!e || !g || !f) return PE3D_EINVAL;
@@ -547,6 +617,10 @@ struct pe3d_handle_s {
   size_t bytes = 0;
   int device = 0;
   double r0 = 0, dr = 0;
+  // the stream of the last work enqueued for the handle (destroy releases
+  // the device memory only once that work has finished)
+  bool used = false;
+  hipStream_t last = nullptr;
 };
 
 namespace {
@@ -589,8 +663,10 @@ struct BatchPlan {
     for (auto e : join) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     if (done) (void)hipEventDestroy(done);
-    if (d_mem) (void)hipFree(d_mem);
+    pool_release(d_mem);
   }
+  // device blocks of destroyed handles this plan used: released with it
+  std::vector<std::shared_ptr<HandleBlocks>> keep;
 };
 
 // Batch schedule (pe3d_set_batch_schedule): independent chains replayed on
@@ -619,12 +695,28 @@ void touch(const std::vector<uintptr_t>& key) {
 // `done` event), so that eviction never waits for the device.
 std::vector<std::unique_ptr<BatchPlan>> g_graveyard;
 
+// Device blocks of destroyed handles waiting for the handle's last work
+// (an event recorded on its last stream at destroy).
+struct Deferred {
+  hipEvent_t ev = nullptr;
+  std::shared_ptr<HandleBlocks> blocks;
+};
+std::vector<Deferred> g_deferred;
+
 // Caller holds g_mu.
 void reap() {
   for (auto it = g_graveyard.begin(); it != g_graveyard.end();) {
     const hipEvent_t e = (*it)->done;
     if (!e || hipEventQuery(e) != hipErrorNotReady) it = g_graveyard.erase(it);
     else ++it;
+  }
+  for (auto it = g_deferred.begin(); it != g_deferred.end();) {
+    if (!it->ev || hipEventQuery(it->ev) != hipErrorNotReady) {
+      if (it->ev) (void)hipEventDestroy(it->ev);
+      it = g_deferred.erase(it);
+    } else {
+      ++it;
+    }
   }
 }
 
@@ -698,27 +790,42 @@ hipError_t prof_launch(const char* pass, int prec, int maxm, double bytes, hipSt
   return e;
 }
 
-// A plan's graphs, streams and device tables may still be in use by
-// enqueued work, so the device is drained before a plan is freed.
-void drop_plans_of(pe3d_handle h) {
+// The plans that use a destroyed handle leave the cache for the graveyard,
+// and the handle's device blocks go back to the pool once both the plans'
+// last work (their `done` events) and the handle's last work (an event
+// recorded now on the stream it last used) have finished: destroying a
+// handle never waits for the device, where other requests' work may run.
+void drop_plans_of(pe3d_handle h, std::shared_ptr<HandleBlocks> blocks) {
   std::lock_guard<std::mutex> lk(g_mu);
-  bool any = false;
-  for (auto& kv : g_plans) {
-    auto& hs = kv.second->handles;
-    any = any || std::find(hs.begin(), hs.end(), h) != hs.end();
+  if (h->used) {
+    Deferred df;
+    df.blocks = blocks;
+    if (hipEventCreateWithFlags(&df.ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(df.ev, h->last) != hipSuccess) {
+      // cannot order the release after the handle's work: wait for the device
+      (void)hipGetLastError();
+      if (df.ev) (void)hipEventDestroy(df.ev);
+      df.ev = nullptr;
+      (void)hipDeviceSynchronize();
+    }
+    g_deferred.push_back(std::move(df));
   }
-  if (!any) return;
-  (void)hipDeviceSynchronize();
-  g_graveyard.clear();
   for (auto it = g_plans.begin(); it != g_plans.end();) {
     auto& hs = it->second->handles;
     if (std::find(hs.begin(), hs.end(), h) != hs.end()) {
       g_lru.remove(it->first);
+      g_graveyard.push_back(std::move(it->second));
       it = g_plans.erase(it);
     } else {
       ++it;
     }
   }
+  // every plan in the graveyard that used the handle keeps its blocks
+  for (auto& pl : g_graveyard) {
+    auto& hs = pl->handles;
+    if (std::find(hs.begin(), hs.end(), h) != hs.end()) pl->keep.push_back(blocks);
+  }
+  reap();
 }
 
 }  // namespace
@@ -832,12 +939,12 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     delete h;
     return PE3D_EDEVICE;
   }
-  if (hipMalloc(&h->d_tables, tb) != hipSuccess) {
+  if (pool_alloc(&h->d_tables, tb) != hipSuccess) {
     delete h;
     return PE3D_ENOMEM;
   }
-  if (hipMalloc(&h->d_scr, field_bytes(b)) != hipSuccess) {
-    (void)hipFree(h->d_tables);
+  if (pool_alloc(&h->d_scr, field_bytes(b)) != hipSuccess) {
+    pool_release(h->d_tables);
     delete h;
     return PE3D_ENOMEM;
   }
@@ -852,8 +959,8 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
     std::memcpy(img.data() + y.o_cur, &t0, sizeof t0);
   }
   if (upload(h->d_tables, img.data(), tb) != hipSuccess) {
-    (void)hipFree(h->d_tables);
-    (void)hipFree(h->d_scr);
+    pool_release(h->d_tables);
+    pool_release(h->d_scr);
     delete h;
     return PE3D_EDEVICE;
   }
@@ -929,9 +1036,10 @@ pe3d_status pe3d_create(const pe3d_env* env, const pe3d_grid* grid, const pe3d_f
 
 pe3d_status pe3d_destroy(pe3d_handle h) {
   if (!h) return PE3D_OK;
-  drop_plans_of(h);
-  (void)hipFree(h->d_scr);
-  (void)hipFree(h->d_tables);
+  auto blocks = std::make_shared<HandleBlocks>();
+  blocks->tables = h->d_tables;
+  blocks->scr = h->d_scr;
+  drop_plans_of(h, std::move(blocks));
   delete h;
   return PE3D_OK;
 }
@@ -1026,6 +1134,8 @@ extern "C" {
 pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream) {
   if (!h || !u_dev || nsteps < 0 || !aligned16(u_dev)) return PE3D_EINVAL;
   if (nsteps == 0) return PE3D_OK;
+  h->used = true;
+  h->last = static_cast<hipStream_t>(stream);
   return march_impl(h, nsteps, u_dev, static_cast<hipStream_t>(stream), h->d_scr, true);
 }
 
@@ -1039,11 +1149,15 @@ pe3d_status pe3d_march_static(pe3d_handle h, int32_t nsteps, void* u_dev, void* 
   if (dev != h->device) return PE3D_ESTATE;
   void* scr = nullptr;
   if (static_scratch(&scr) != hipSuccess) return PE3D_EDEVICE;
+  h->used = true;
+  h->last = static_cast<hipStream_t>(stream);
   return march_impl(h, nsteps, u_dev, static_cast<hipStream_t>(stream), scr, false);
 }
 
 pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream) {
   if (!h || !u_dev || !is_fin(zs) || zs < 0.0 || !aligned16(u_dev)) return PE3D_EINVAL;
+  h->used = true;
+  h->last = static_cast<hipStream_t>(stream);
   if (launch_starter(h->prec, h->desc, zs, u_dev, static_cast<hipStream_t>(stream)) != hipSuccess)
     return PE3D_EDEVICE;
   return PE3D_OK;
@@ -1051,6 +1165,8 @@ pe3d_status pe3d_starter(pe3d_handle h, double zs, void* u_dev, void* stream) {
 
 pe3d_status pe3d_tl(pe3d_handle h, const void* u_dev, float* tl_dev, void* stream) {
   if (!h || !u_dev || !tl_dev || !aligned16(u_dev)) return PE3D_EINVAL;
+  h->used = true;
+  h->last = static_cast<hipStream_t>(stream);
   if (launch_tl(h->prec, h->desc, u_dev, tl_dev, static_cast<hipStream_t>(stream)) != hipSuccess)
     return PE3D_EDEVICE;
   return PE3D_OK;
@@ -1060,6 +1176,8 @@ pe3d_status pe3d_pressure(pe3d_handle h, const void* u_dev, void* p_dev, void* s
   if (!h || !u_dev || !p_dev || !aligned16(u_dev) || !aligned16(p_dev)) return PE3D_EINVAL;
   const double r = h->r0 + double(h->j) * h->dr;
   if (!(r > 0.0)) return PE3D_ESTATE;
+  h->used = true;
+  h->last = static_cast<hipStream_t>(stream);
   // H0^(1)(x) = J0(x) + i Y0(x), x = k0 r_j (C++17 special functions, FP64)
   const double x = h->desc.k0 * r;
   const double hre = std::cyl_bessel_j(0.0, x), him = std::cyl_neumann(0.0, x);
@@ -1229,7 +1347,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::memcpy(img.data() + off_desc, descs.data(), np * sizeof(ProbDesc));
   std::memcpy(img.data() + off_j, jdevs.data(), np * sizeof(long long*));
   std::memcpy(img.data() + off_add, adds.data(), np * sizeof(int));
-  if (hipMalloc(&P.d_mem, total) != hipSuccess) return PE3D_ENOMEM;
+  if (pool_alloc(&P.d_mem, total) != hipSuccess) return PE3D_ENOMEM;
   unsigned char* base = static_cast<unsigned char*>(P.d_mem);
   P.d_descs = reinterpret_cast<ProbDesc*>(base + off_desc);
   P.d_jdevs = reinterpret_cast<long long**>(base + off_j);
@@ -1481,6 +1599,10 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     if (s != PE3D_OK) return s;
   }
   if (hipEventRecord(plan->done, st) != hipSuccess) return PE3D_EDEVICE;
-  for (int i = 0; i < n; ++i) hs[i]->j += nsteps[i];
+  for (int i = 0; i < n; ++i) {
+    hs[i]->j += nsteps[i];
+    hs[i]->used = true;
+    hs[i]->last = st;
+  }
   return PE3D_OK;
 }

@@ -16,8 +16,13 @@ Scheduling, per iteration:
      batched march (one launch per pass per step over all of
      them, pe3d_march_batch); while the device runs it, newly arrived
      requests are admitted and set up (they join the next iteration);
-  4. requests that reached their range are checked (non-finite field ->
-     failed), summarised, and their device memory is released.
+  4. the loop runs one iteration ahead: iteration k+1 is enqueued behind
+     iteration k before the host waits for k (its event only, not the
+     device), so the device does not idle while the host turns over; the
+     requests whose last iteration was k are then checked (non-finite field
+     -> failed) on a stream of their own, summarised, and released (their
+     device memory goes back to the library's pool without waiting for the
+     device).
 
 The backend does the device work; `Pe3dBackend` drives libpe3d, tests use
 host-only backends.  Latency of a request = completion time - arrival time.
@@ -60,12 +65,14 @@ class Backend:
     def create(self, problem):
         raise NotImplementedError
 
-    def march(self, states: Sequence, nsteps: Sequence[int]) -> None:
-        """Advance the states; may return before the device has finished."""
+    def march(self, states: Sequence, nsteps: Sequence[int]):
+        """Advance the states; may return before the device has finished.
+        Returns a token for wait() (host-only backends: None)."""
         raise NotImplementedError
 
-    def wait(self) -> None:
-        """Block until the last march has finished (host-only backends: no-op)."""
+    def wait(self, token) -> None:
+        """Block until the march that returned `token` has finished
+        (host-only backends: no-op)."""
 
     def finish(self, state, rid: int) -> dict:
         """Summary of a finished request; must report {'finite': bool, ...}."""
@@ -80,12 +87,15 @@ class Pe3dBackend(Backend):
     all residents advanced by one pe3d_march_batch call per iteration."""
 
     def __init__(self, keep_fields: Sequence[int] = (), use_graph: bool = False):
-        import torch  # noqa: F401  (device memory and streams only)
+        import torch  # (device memory and streams only)
         from . import pe3d as P
         self.P = P
         self.keep = set(keep_fields)
         self.use_graph = use_graph
         self.kept: Dict[int, np.ndarray] = {}
+        # finished fields are checked on a stream of their own (default
+        # priority), so that the check does not wait behind the next iteration
+        self.side = torch.cuda.Stream()
 
     def footprint(self, problem) -> int:
         g = problem.grid
@@ -97,25 +107,30 @@ class Pe3dBackend(Backend):
         u = m.starter(problem.zs)
         return (m, u)
 
-    def march(self, states, nsteps) -> None:
+    def march(self, states, nsteps):
         import torch
         ms = [s[0] for s in states]
         us = [s[1] for s in states]
         self.P.march_batch(ms, list(nsteps), us, use_graph=self.use_graph)
+        ev = torch.cuda.Event()
+        ev.record()
+        return ev
 
-    def wait(self) -> None:
-        import torch
-        torch.cuda.synchronize()
+    def wait(self, token) -> None:
+        if token is not None:
+            token.synchronize()
 
     def finish(self, state, rid: int = -1) -> dict:
+        """After wait() on the request's last march: its field is final."""
         import torch
         m, u = state
-        # one transfer for both checks
-        chk = torch.stack((torch.isfinite(torch.view_as_real(u)).all().double(),
-                           torch.linalg.vector_norm(u).double())).cpu()
+        with torch.cuda.stream(self.side):
+            # one transfer for both checks (waits for this stream only)
+            chk = torch.stack((torch.isfinite(torch.view_as_real(u)).all().double(),
+                               torch.linalg.vector_norm(u).double())).cpu()
+            if rid in self.keep:
+                self.kept[rid] = u.detach().cpu().numpy()
         finite, nrm = bool(chk[0].item()), float(chk[1].item())
-        if rid in self.keep:
-            self.kept[rid] = u.detach().cpu().numpy()
         return {"finite": finite, "norm": nrm, "step": m.step, "range_m": m.range_m}
 
     def destroy(self, state) -> None:
@@ -180,29 +195,41 @@ class Scheduler:
             self.max_used = max(self.max_used, used)
             self.max_resident = max(self.max_resident, len(resident))
 
+        # the iteration on the device: (token, its entries); an entry's steps
+        # left already exclude every enqueued iteration
+        inflight = None
         while pending or waiting or resident:
             admit()
-            if not resident:
-                if pending:
+            nxt = [x for x in resident if x[2] > 0]
+            enqueued = None
+            if nxt:
+                # enqueued behind the iteration in flight, before waiting for it
+                K = self.Kb if waiting else self.K
+                self.backlog_iterations += K != self.K
+                steps = [min(K, x[2]) for x in nxt]
+                token = self.backend.march([x[1] for x in nxt], steps)
+                self.iterations += 1
+                for x, s in zip(nxt, steps):
+                    x[2] -= s
+                enqueued = (token, nxt)
+                # while the device works: admit and set up new arrivals
+                admit()
+            if inflight is None:
+                if enqueued is None and pending:
                     wait = pending[0].arrival_s - (self.clock() - t0)
                     if wait > 0:
                         self.sleep(wait)
+                inflight = enqueued
                 continue
-            marching = list(resident)
-            K = self.Kb if waiting else self.K
-            self.backlog_iterations += K != self.K
-            steps = [min(K, x[2]) for x in marching]
-            self.backend.march([x[1] for x in marching], steps)
-            # while the device works: admit and set up new arrivals (next iteration)
-            admit()
-            self.backend.wait()
-            self.iterations += 1
-            for x, s in zip(marching, steps):
-                x[2] -= s
+            self.backend.wait(inflight[0])
             now = self.clock() - t0
+            # requests whose last iteration was the one just finished (not
+            # those that also run in the iteration enqueued behind it)
+            later = {id(x) for x in enqueued[1]} if enqueued else set()
+            done_ids = {id(x) for x in inflight[1] if x[2] == 0 and id(x) not in later}
             keep = []
             for x in resident:
-                if x[2] > 0:
+                if id(x) not in done_ids:
                     keep.append(x)
                     continue
                 rec = recs[x[0]]
@@ -215,6 +242,7 @@ class Scheduler:
                 rec.done = now
                 rec.status = "done" if summ.get("finite", True) else "failed"
             resident = keep
+            inflight = enqueued
             if self.log and self.iterations % 50 == 0:
                 self.log(f"iter {self.iterations} t={now:.2f}s resident={len(resident)} "
                          f"waiting={len(waiting)} pending={len(pending)}")

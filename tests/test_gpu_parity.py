@@ -756,6 +756,40 @@ def test_plan_cache_eviction_and_handle_destruction(torch, P):
         m.close()
 
 
+def test_pooled_blocks_of_a_destroyed_handle_serve_a_new_one(torch, P):
+    """Destroying a handle returns its device memory to the library's pool
+    without waiting for the device; a new handle of the same size reuses it
+    while another problem's batched march is still queued, and every field
+    still equals the plain march."""
+    env = W.wedge_env()
+    g = W.Grid(nz=300, ntheta=40, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    a, b = P.Pe3d(env, g, 50.0), P.Pe3d(env, g, 50.0)
+    ua, ub = a.starter(80.0), b.starter(80.0)
+    say("pooled blocks")
+    P.march_batch([a, b], [3, 5], [ua, ub], use_graph=False)
+    torch.cuda.synchronize()
+    a.close()                        # its plan goes to the graveyard with its blocks
+    P.march_batch([b], [40], [ub], use_graph=False)   # queued, not waited for
+    for _ in range(3):               # new handles of a's size while b's work runs
+        c = P.Pe3d(env, g, 50.0)
+        uc = c.starter(80.0)
+        P.march_batch([c], [4], [uc], use_graph=False)
+        ref = P.Pe3d(env, g, 50.0)
+        ur = ref.starter(80.0)
+        ref.march(4, ur)
+        torch.cuda.synchronize()
+        assert torch.equal(uc, ur)
+        c.close()
+        ref.close()
+    rb = P.Pe3d(env, g, 50.0)
+    urb = rb.starter(80.0)
+    rb.march(45, urb)
+    torch.cuda.synchronize()
+    assert torch.equal(ub, urb)
+    b.close()
+    rb.close()
+
+
 def test_prepared_graph_runs_nothing_then_replays(torch, P):
     """Capture-only (use_graph == 2) leaves fields and step counters alone;
     the next identical call replays it and equals direct launches bitwise."""

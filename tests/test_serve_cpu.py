@@ -48,6 +48,48 @@ class TimedBackend(Backend):
         self.live -= 1
 
 
+class AsyncBackend(Backend):
+    """Marches take effect only once waited for, in enqueue order (device
+    work behind an event); finishing a request before its last march has
+    been waited for is an error."""
+
+    def __init__(self, clock=None, rate=1e6):
+        self.clock, self.rate = clock, rate
+        self.queue = []      # (token, [(state, n), ...])
+        self.tok = 0
+        self.live = 0
+
+    def footprint(self, p):
+        return p.points * 16
+
+    def create(self, p):
+        self.live += 1
+        return {"p": p, "done": 0, "queued": 0}
+
+    def march(self, states, nsteps):
+        self.tok += 1
+        self.queue.append((self.tok, list(zip(states, nsteps))))
+        for s, n in zip(states, nsteps):
+            s["queued"] += n
+        return self.tok
+
+    def wait(self, token):
+        while self.queue and self.queue[0][0] <= token:
+            _, work = self.queue.pop(0)
+            for s, n in work:
+                s["done"] += n
+                if self.clock is not None:
+                    self.clock.t += s["p"].points * n / self.rate
+
+    def finish(self, s, rid):
+        assert s["done"] == s["queued"], f"request {rid} finished with a march still in flight"
+        return {"finite": True, "steps": s["done"]}
+
+    def destroy(self, s):
+        assert s["done"] == s["queued"]
+        self.live -= 1
+
+
 def small_trace(n=12, seed=1):
     env = W.wedge_env(zmax=600.0)
     rng = np.random.default_rng(seed)
@@ -179,3 +221,17 @@ def test_served_results_equal_the_plain_march():
         p = r.problem
         st = O.setup(p.env, p.grid, p.f_hz)
         assert np.array_equal(be.out[r.rid], O.march(st, O.starter(st, p.zs), 0, p.nsteps))
+
+
+def test_pipelined_loop_finishes_a_request_only_after_its_last_march():
+    """The loop enqueues iteration k+1 before waiting for k: a request whose
+    last iteration is k+1 must not be finished when k completes."""
+    for seed in (1, 3, 5):
+        clk = VirtualClock()
+        be = AsyncBackend(clk, rate=3e4)
+        tr = small_trace(25, seed=seed)
+        sch = Scheduler(be, budget_bytes=4 * max(r.problem.points for r in tr) * 16, chunk_steps=3,
+                        clock=clk, sleep=clk.sleep, backlog_chunk_steps=6)
+        recs = sch.run(tr)
+        assert all(r.status == "done" and r.summary["steps"] == r.steps for r in recs)
+        assert be.live == 0 and not be.queue
