@@ -64,6 +64,17 @@ typedef enum { PE3D_C64 = 0, PE3D_C128 = 1 } pe3d_precision;
  * is [1 + (1/4 - d/4) X] u^{j+1} = [1 + (1/4 + d/4) X] u^j per azimuth and
  * the azimuth pass is not run. */
 typedef enum { PE3D_MODE_3D = 0, PE3D_MODE_NX2D = 1 } pe3d_mode;
+/* Solver of the azimuth systems of Eq. (6)/(8) (the per-depth periodic or
+ * sector tridiagonal systems [1 - (d/4) Y] u^{j+1} = v).
+ * PE3D_AZIMUTH_CHUNKED: each lane runs the constant-coefficient recurrences
+ * of the factored operator over a chunk of azimuths (a Thomas sweep), the
+ * chunks joined by a wavefront scan of their affine maps (hybrid
+ * Thomas / cyclic reduction; one lane per depth line, azimuth_lanes = 1, is
+ * the plain per-lane Thomas solve for ntheta <= 16).
+ * PE3D_AZIMUTH_PCR: parallel cyclic reduction of the whole line in LDS, one
+ * uniform multiplier per level, as many levels as the coupling needs at that
+ * range step (many near the source, few far from it). */
+typedef enum { PE3D_AZIMUTH_CHUNKED = 0, PE3D_AZIMUTH_PCR = 1 } pe3d_azimuth_solver;
 
 /* Ocean environment (the sound-speed profiles, bathymetry and bottom that
  * the set-up of Fig. 2 reads).  Water: sound speed c(z) piecewise linear through
@@ -120,10 +131,11 @@ typedef struct {
  * azimuths.  The march starts at range r0 with range step dr (the range loop of Fig. 2):
  * r_j = r0 + j*dr.  mode selects the azimuthal coupling (pe3d_mode; a
  * zero-initialised grid is the full 3D march).  depth_lanes and
- * azimuth_lanes override the kernels' shape for this problem (tuning; the
- * results agree with the default shape to rounding); a value the sizes do
- * not allow gives PE3D_EUNSUPPORTED, one that is not a power of two in range
- * PE3D_EINVAL. */
+ * azimuth_lanes override the kernels' shape for this problem, and
+ * azimuth_solver the algorithm of the azimuth pass (tuning; the results
+ * agree with the defaults to rounding); a value the sizes do not allow gives
+ * PE3D_EUNSUPPORTED, one that is not a power of two in range, an unknown
+ * solver or azimuth lanes with PE3D_AZIMUTH_PCR PE3D_EINVAL. */
 typedef struct {
   int32_t nz, ntheta;
   double theta0, width;
@@ -135,7 +147,9 @@ typedef struct {
                                  two 4..256 giving <= 17 rows per lane */
   int32_t azimuth_lanes;      /* 0: the library's choice; else the lanes per
                                  depth line of the azimuth pass, a power of
-                                 two 1..64 giving <= 16 azimuths per lane */
+                                 two 1..64 giving <= 16 azimuths per lane
+                                 (PE3D_AZIMUTH_CHUNKED only) */
+  int32_t azimuth_solver;     /* pe3d_azimuth_solver (0: chunked) */
 } pe3d_grid;
 
 typedef struct { double f_hz; } pe3d_freq;

@@ -180,6 +180,8 @@ pe3d_status validate(const pe3d_env* e, const pe3d_grid* g, const pe3d_freq* f) 
   if (g->mode != PE3D_MODE_3D && g->mode != PE3D_MODE_NX2D) return PE3D_EINVAL;
   auto pow2_in = [](int v, int lo, int hi) { return v == 0 || (v >= lo && v <= hi && (v & (v - 1)) == 0); };
   if (!pow2_in(g->depth_lanes, 4, 256) || !pow2_in(g->azimuth_lanes, 1, 64)) return PE3D_EINVAL;
+  if (g->azimuth_solver != PE3D_AZIMUTH_CHUNKED && g->azimuth_solver != PE3D_AZIMUTH_PCR) return PE3D_EINVAL;
+  if (g->azimuth_solver == PE3D_AZIMUTH_PCR && g->azimuth_lanes != 0) return PE3D_EINVAL;
   if (g->precision == PE3D_C64 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   if (g->precision == PE3D_C128 && (g->nz > 4096 || g->ntheta > 1024)) return PE3D_EUNSUPPORTED;
   return PE3D_OK;
@@ -268,6 +270,7 @@ struct Built {
   int nsr = 0;                          // water-profile rows (0: one profile)
   double sr0 = 0, sdr = 0;
   int la_req = 0, lb_req = 0;           // requested lanes (0: the rule)
+  int bsolver = 0;                      // pe3d_azimuth_solver
   int lpc = 0, ma = 0, lt = 0, ntile_a = 0;
   int bconv[2] = {0, 0};   // first row of each chain's converged tail
   cd gtail[2], ctail[2];   // the tail's Gh and RHS diagonal / nbmh
@@ -298,6 +301,16 @@ pe3d_status choose_shapes(Built& b) {
   const int cpw = 256 / L;
   b.ntile_a = (NT + cpw - 1) / cpw;
 
+  if (b.bsolver == PE3D_AZIMUTH_PCR) {
+    // pass B by cyclic reduction: tiles of pcr_td(NT) depths, whole lines
+    b.wb = 0;
+    b.nc = 0;
+    b.mb = 0;
+    b.td = pcr_td(NT);
+    b.maxm_b = kPcrClass;
+    b.ntile_b = (N + b.td - 1) / b.td;
+    return PE3D_OK;
+  }
   // pass B: the fewest lanes W per depth line (power of two, 1..64) with chunks
   // of M = ceil(nth / W) <= 16 azimuths; lines of exactly W*M azimuths with
   // M >= 9 use the kernel specialised for M (class M), others the general
@@ -332,6 +345,7 @@ pe3d_status build(const pe3d_env& e, const pe3d_grid& g, const pe3d_freq& f, Bui
   b.prec = g.precision;
   b.la_req = g.depth_lanes;
   b.lb_req = g.azimuth_lanes;
+  b.bsolver = g.azimuth_solver;
   b.rigid = e.floor == PE3D_FLOOR_RIGID;
   b.periodic = is_periodic(g.width);
   b.k0 = 2.0 * kPi * f.f_hz / e.c0;
@@ -857,6 +871,7 @@ pe3d_status pe3d_footprint(const pe3d_env* env, const pe3d_grid* grid, const pe3
   b.nsr = env->n_ssp_r >= 2 ? env->n_ssp_r : 0;
   b.la_req = grid->depth_lanes;
   b.lb_req = grid->azimuth_lanes;
+  b.bsolver = grid->azimuth_solver;
   st = choose_shapes(b);
   if (st != PE3D_OK) return st;
   *bytes = table_bytes(b) + field_bytes(b);

@@ -75,7 +75,8 @@ struct ProbDesc {
   int td;               // depths per workgroup = kPassBThreads / W
   int mb;               // M, azimuth nodes per chunk (<= 16)
   int ntile_b;          // ceil(nz / td)
-  int bcls;             // kernel class: M (9..16) if nth == W*M, else 0 (general)
+  int bcls;             // kernel class: M (9..16) if nth == W*M, 0 (general) else,
+                        //   kPcrClass for cyclic reduction (td from pcr_td; wb, nc, mb unused)
   double k0, dr, r0, dth;
   double dz;            // starter / TL only
   int nx2d;             // N x 2D mode (Y = 0): pass A writes the caller's field on
@@ -89,6 +90,18 @@ struct WorkItem {
 };
 
 constexpr int kPassBThreads = 512;
+
+// Azimuth pass by parallel cyclic reduction (pass_b_pcr_body): class of the
+// batched kernels' dispatch (ProbDesc::bcls), nodes (azimuth x depth) of one
+// workgroup's tile held in LDS as FP64 complex, and its depths per tile: the
+// largest power of two td <= 512 with td * nth <= kPcrNodes.
+constexpr int kPcrClass = 1;
+constexpr int kPcrNodes = 2048;
+__host__ __device__ inline int pcr_td(int nth) {
+  int td = 1;
+  while (td < 512 && 2 * td * nth <= kPcrNodes) td *= 2;
+  return td;
+}
 
 // Depth tiles of the azimuth pass: tile t covers depths [t td, (t+1) td).
 // When a tile's row segment (td values) is half a 128-byte cache line, tiles

@@ -1231,6 +1231,149 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   }
 }
 
+// ============================================================== pass B by cyclic reduction
+// Parallel cyclic reduction of [I - s D_theta] u = v, the alternative to the
+// chunked recurrences above.  The equation at azimuth m is
+//   b u_m + a (u_{m-d} + u_{m+d}) = v_m,   b = 1 + 2s, a = -s, d = 1;
+// adding k = -a/b times the equations at m - d and m + d removes u_{m-d} and
+// u_{m+d} and leaves the same form at distance 2d:
+//   v_m <- v_m + k (v_{m-d} + v_{m+d}),  a <- k a,  b <- b + 2 k a  (old a).
+// The coefficients are the same at every azimuth and depth (the operator is
+// circulant and does not depend on z), so each level is one complex
+// multiplier for the whole tile.  |a/b| < 1/2 (diagonal dominance) and
+// q = a/b maps to q^2/(1 - 2 q^2): the levels stop once |a/b| <= 2^-60, where
+// the remaining coupling is below FP64 resolution (about 12 levels at sigma
+// = 600, 3-5 far from the source), and u_m = v_m / b.  Periodic lines wrap
+// with period Ntheta; a sector (zero ghosts at m = -1 and m = Ntheta) is the
+// restriction of the periodic line of period 2 Ntheta + 2 whose data are odd
+// about the ghosts (v_{Ntheta+k} = -v_{Ntheta-k}, v_{-1} = 0), so a node
+// outside 0..Ntheta-1 reads the mirrored node with its sign flipped.
+// A workgroup's tile of td depths x Ntheta azimuths (td * Ntheta <=
+// kPcrNodes) sits in LDS as FP64 complex, node m * td + dl, so consecutive
+// threads load consecutive depths.  As in the chunked kernel the field is
+// stored rounded to S and the next step's azimuth factor is applied to the
+// rounded values before the store.
+__host__ __device__ constexpr int pass_b_pcr_lds_bytes() { return kPcrNodes * 16; }
+
+template <typename S>
+__device__ __forceinline__ void pass_b_pcr_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
+  constexpr int NTHR = kPassBThreads;
+  constexpr int NPT = kPcrNodes / NTHR;  // nodes per thread
+  const int tid = threadIdx.x;
+  const int NT = d.nth, N = d.nz, TD = d.td;
+  const int lgTD = 31 - __clz(TD);
+  const int z0 = tile * TD;
+  const int nn = TD * NT;
+  D* V = reinterpret_cast<D*>(smem);
+  const long long j = *d.jdev + koff;
+  const bool last = (koff == d.nsteps - 1);
+  const bool periodic = d.periodic != 0;
+  const C<S>* __restrict__ src = (const C<S>*)d.scr;
+  C<S>* __restrict__ dst = (C<S>*)(last ? d.u : d.scr);
+
+  // ---- stage the tile (all loads issued first), FP64 in LDS; depths past
+  //      the end of the column are zero and never stored
+  {
+    C<S> v[NPT];
+    __builtin_amdgcn_s_setprio(2);
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      const int m = n >> lgTD, z = z0 + (n & (TD - 1));
+      v[q] = (n < nn && z < N) ? gload(src, unsigned(m * N + z)) : zero<S>();
+    }
+    __builtin_amdgcn_s_setprio(0);
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      if (n < nn) V[n] = to_d(v[q]);
+    }
+  }
+  const double sg = sigma_of(d, j);  // s = i sg
+  D b = mk<double>(1.0, 2.0 * sg);
+  D a = mk<double>(0.0, -sg);
+  const int P = periodic ? NT : 2 * NT + 2;  // period of the (extended) line
+  // node value at azimuth index i in [0, P) of the extended line, depth dl
+  auto at = [&](int i, int dl) {
+    if (periodic || i < NT) return V[(i << lgTD) + dl];
+    if (i == NT || i == P - 1) return zero<double>();
+    const D w = V[((2 * NT - i) << lgTD) + dl];
+    return mk<double>(-w.re, -w.im);
+  };
+  __syncthreads();
+
+  // ---- levels (uniform loop: the same a, b in every thread)
+  int dist = 1 % P;  // level distance modulo the period
+  for (int lvl = 0; lvl < 64; ++lvl) {
+    const double qa = a.re * a.re + a.im * a.im, qb = b.re * b.re + b.im * b.im;
+    if (!(qa > 0x1p-120 * qb)) break;
+    const D k = cdiv(mk<double>(-a.re, -a.im), b);
+    D nv[NPT];
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      if (n < nn) {
+        const int m = n >> lgTD, dl = n & (TD - 1);
+        int lo = m - dist, hi = m + dist;
+        if (lo < 0) lo += P;
+        if (hi >= P) hi -= P;
+        nv[q] = fma(k, add(at(lo, dl), at(hi, dl)), V[n]);
+      }
+    }
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      if (n < nn) V[n] = nv[q];
+    }
+    __syncthreads();
+    b = fma(scl(2.0, k), a, b);
+    a = mul(k, a);
+    dist = (2 * dist) % P;
+  }
+
+  // ---- u = v / b rounded to S; the next step's factor w = u + s_{j+1} D_theta u
+  //      from the rounded u (zero ghosts for a sector)
+  const D ib = cdiv(one<double>(), b);
+  C<S> u[NPT];
+  #pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int n = tid + q * NTHR;
+    if (n < nn) u[q] = from_d<S>(mul(V[n], ib));
+  }
+  if (!last) {
+    __syncthreads();
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      if (n < nn) V[n] = to_d(u[q]);
+    }
+    __syncthreads();
+    const double s1 = sigma_of(d, j + 1);
+    #pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+      const int n = tid + q * NTHR;
+      if (n < nn) {
+        const int m = n >> lgTD, dl = n & (TD - 1);
+        D ul = zero<double>(), ur = zero<double>();
+        if (m > 0) ul = V[n - TD];
+        else if (periodic) ul = V[((NT - 1) << lgTD) + dl];
+        if (m < NT - 1) ur = V[n + TD];
+        else if (periodic) ur = V[dl];
+        const D c = V[n];
+        const D dd = sub(add(ul, ur), scl(2.0, c));
+        u[q] = from_d<S>(mk<double>(c.re - s1 * dd.im, c.im + s1 * dd.re));
+      }
+    }
+  }
+  #pragma unroll
+  for (int q = 0; q < NPT; ++q) {
+    const int n = tid + q * NTHR;
+    const int m = n >> lgTD, z = z0 + (n & (TD - 1));
+    if (n < nn && z < N) gstore(dst, unsigned(m * N + z), u[q]);
+  }
+}
+
 // two workgroups per CU: one stages or stores its tile while the other computes
 #define PE3D_PASS_B_OCC __attribute__((amdgpu_waves_per_eu(4, 4)))
 
@@ -1260,8 +1403,18 @@ __global__ __launch_bounds__(kPassBThreads) PE3D_PASS_B_OCC void pass_b_batch(co
     case 14: pass_b_body<S, 14, true>(d, it.tile, koff, smem_b); break;
     case 15: pass_b_body<S, 15, true>(d, it.tile, koff, smem_b); break;
     case 16: pass_b_body<S, 16, true>(d, it.tile, koff, smem_b); break;
+    case kPcrClass: pass_b_pcr_body<S>(d, it.tile, koff, smem_b); break;
     default: pass_b_body<S, 16, false>(d, it.tile, koff, smem_b); break;
   }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kPassBThreads) void pass_b_pcr_single(ProbDesc d, int koff) {
+  extern __shared__ __align__(16) unsigned char smem_b[];
+  const int b = blockIdx.x;
+  const int tile = pass_b_pairs(d.td, int(sizeof(C<S>))) ? pass_b_paired_tile(b, d.ntile_b) : b;
+  pass_b_pcr_body<S>(d, tile, koff, smem_b);
+  medium_update_next(d, tile, koff);
 }
 
 // ============================================================== small kernels
@@ -1415,6 +1568,18 @@ static hipError_t run_b(const ProbDesc& d, int koff, int lds, hipStream_t st) {
 }
 
 template <typename S>
+static hipError_t run_b_pcr(const ProbDesc& d, int koff, int lds, hipStream_t st) {
+  constexpr int lds_max = pass_b_pcr_lds_bytes();
+  if (lds > lds_max) return hipErrorInvalidValue;
+  {
+    const hipError_t e = allow_lds(reinterpret_cast<const void*>(&pass_b_pcr_single<S>), lds_max);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((pass_b_pcr_single<S>), dim3(d.ntile_b), dim3(kPassBThreads), lds, st, d, koff);
+  return hipGetLastError();
+}
+
+template <typename S>
 static hipError_t run_b_batch(const ProbDesc* d_descs, const WorkItem* items, int nitems, int koff, int lds,
                               hipStream_t st) {
   constexpr int lds_max = pass_b_lds_bytes(int(sizeof(C<S>)), 64, 16);
@@ -1457,12 +1622,15 @@ hipError_t launch_pass_a(int prec, const ProbDesc* single, const ProbDesc* d_des
                    : run_a_batch<double>(d_descs, items, nitems, koff, lds, st);
 }
 
-int pass_b_lds(int prec, int W, int M) { return pass_b_lds_bytes(prec ? 16 : 8, W, M); }
+int pass_b_lds(int prec, int W, int M) {
+  return W == 0 ? pass_b_pcr_lds_bytes() : pass_b_lds_bytes(prec ? 16 : 8, W, M);
+}
 
 // class: M in 9..16 for lines of exactly W*M azimuths, 0 for the general kernel
 template <typename S>
 static hipError_t run_b_cls(const ProbDesc& d, int koff, int lds, hipStream_t st) {
   switch (d.bcls) {
+    case kPcrClass: return run_b_pcr<S>(d, koff, lds, st);
     case 0: return run_b<S, 16, false>(d, koff, lds, st);
     case 9: return run_b<S, 9, true>(d, koff, lds, st);
     case 10: return run_b<S, 10, true>(d, koff, lds, st);

@@ -43,6 +43,8 @@ PE3D_C128 = 1
 PE3D_MODE_3D = 0
 PE3D_MODE_NX2D = 1
 PE3D_STATIC_SCRATCH_BYTES = 32 << 20
+PE3D_AZIMUTH_CHUNKED = 0
+PE3D_AZIMUTH_PCR = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
@@ -66,7 +68,8 @@ class pe3d_grid(ct.Structure):
     _fields_ = [("nz", ct.c_int32), ("ntheta", ct.c_int32), ("theta0", ct.c_double),
                 ("width", ct.c_double), ("dr", ct.c_double), ("r0", ct.c_double),
                 ("precision", ct.c_int32), ("mode", ct.c_int32),
-                ("depth_lanes", ct.c_int32), ("azimuth_lanes", ct.c_int32)]
+                ("depth_lanes", ct.c_int32), ("azimuth_lanes", ct.c_int32),
+                ("azimuth_solver", ct.c_int32)]
 
 
 class pe3d_freq(ct.Structure):
@@ -162,7 +165,8 @@ def make_grid(grid):
                      precision=int(getattr(grid, "precision", PE3D_C64)),
                      mode=int(getattr(grid, "mode", PE3D_MODE_3D)),
                      depth_lanes=int(getattr(grid, "depth_lanes", 0)),
-                     azimuth_lanes=int(getattr(grid, "azimuth_lanes", 0)))
+                     azimuth_lanes=int(getattr(grid, "azimuth_lanes", 0)),
+                     azimuth_solver=int(getattr(grid, "azimuth_solver", 0)))
 
 
 def _stream_ptr(stream) -> Optional[int]:

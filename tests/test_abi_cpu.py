@@ -139,6 +139,18 @@ def test_kernel_lanes_overrides_are_validated(P):
     assert b0 > 0 and b1 > 0
 
 
+def test_azimuth_solver_is_validated(P):
+    env = W.wedge_env()
+    g = dict(nz=300, ntheta=70, theta0=0.0, width=W.TWO_PI, dr=10.0)
+    for solver, lb in ((W.AZ_CHUNKED, 0), (W.AZ_PCR, 0), (W.AZ_CHUNKED, 8)):
+        assert _status(P, env, W.Grid(azimuth_solver=solver, azimuth_lanes=lb, **g)) not in (
+            P.PE3D_EINVAL, P.PE3D_EUNSUPPORTED), (solver, lb)
+    # unknown solver; lanes are a parameter of the chunked solver only
+    for solver, lb in ((2, 0), (-1, 0), (W.AZ_PCR, 8)):
+        assert _status(P, env, W.Grid(azimuth_solver=solver, azimuth_lanes=lb, **g)) == P.PE3D_EINVAL, (solver, lb)
+    assert (P.PE3D_AZIMUTH_CHUNKED, P.PE3D_AZIMUTH_PCR) == (W.AZ_CHUNKED, W.AZ_PCR)
+
+
 def test_create_reports_unsupported_sizes(P):
     env = W.wedge_env()
     assert _status(P, env, W.Grid(nz=4097, ntheta=8, theta0=0, width=W.TWO_PI, dr=10.0)) == P.PE3D_EUNSUPPORTED

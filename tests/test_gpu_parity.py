@@ -192,6 +192,82 @@ def test_config5_worst_sector_request(torch, P, prec):
     assert O.rel_l2(got, ref) < TOL[prec]
 
 
+# ---------------------------------------------------------------- azimuth solver: cyclic reduction
+@pytest.mark.parametrize("rough", [False, True])
+@pytest.mark.parametrize("prec", [W.PREC_C128, W.PREC_C64])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_pcr_azimuth_solver_matches_oracle(torch, P, case, prec, rough):
+    """The azimuth pass by parallel cyclic reduction (periodic lines and
+    sectors through their odd extension), smooth and white-noise fields, at
+    the strict bars."""
+    name, env, gk, f, steps = case
+    grid = W.Grid(precision=prec, azimuth_solver=W.AZ_PCR, **gk)
+    st = O.setup(env, grid, f)
+    if rough:
+        u0 = W.random_field(grid.ntheta, grid.nz, seed=_seed(name))
+    else:
+        u0 = O.starter(st, 0.3 * env.zmax) * (1 + 0.4 * np.cos(st.theta) + 0.2 * np.sin(3 * st.theta))[:, None]
+    got, ref = run_pair(torch, P, env, grid, f, u0, steps, name + "_pcr")
+    assert O.rel_l2(got, ref) < TOL[prec], name
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_pcr_config5_worst_sector_request(torch, P, prec):
+    """Cyclic reduction on the served stream's sector with sigma_0 = 613."""
+    p = worst_sector_request()
+    grid = dataclasses.replace(p.grid, precision=prec, azimuth_solver=W.AZ_PCR)
+    st = O.setup(p.env, grid, p.f_hz)
+    say("config5 worst sector, pcr", p.name, f"nz={grid.nz} nth={grid.ntheta} prec={prec}")
+    m = P.Pe3d(p.env, grid, p.f_hz)
+    u = m.starter(p.zs)
+    u0 = to_host(torch, u)
+    m.march(20, u)
+    got = to_host(torch, u)
+    m.close()
+    assert O.rel_l2(got, O.march(st, u0, 0, 20)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [W.PREC_C64, W.PREC_C128])
+def test_pcr_size_limits_and_batch(torch, P, prec):
+    """Cyclic reduction at the largest Ntheta (2 depths per tile) and a
+    ragged depth count, alone against the oracle, then batched together with
+    chunked problems: every field equals its plain march bit for bit."""
+    env = W.wedge_env()
+    specs = [
+        dict(nz=20, ntheta=1024, theta0=0.0, width=W.TWO_PI, dr=10.0, azimuth_solver=W.AZ_PCR),
+        dict(nz=333, ntheta=300, theta0=2.0, width=W.TWO_PI, dr=8.0, azimuth_solver=W.AZ_PCR),
+        dict(nz=64, ntheta=9, theta0=1.0, width=math.radians(30.0), dr=12.0, azimuth_solver=W.AZ_PCR),
+        dict(nz=200, ntheta=24, theta0=0.0, width=W.TWO_PI, dr=10.0),
+    ]
+    fs = [50.0, 60.0, 25.0, 40.0]
+    steps = [3, 4, 6, 5]
+    probs = [(W.Grid(precision=prec, **g), f) for g, f in zip(specs, fs)]
+    fields0, plain = [], []
+    for (grid, f), n in zip(probs, steps):
+        st = O.setup(env, grid, f)
+        u0 = (O.starter(st, 0.3 * env.zmax) * (1 + 0.3 * np.cos(2 * st.theta))[:, None]
+              + 0.05 * W.random_field(grid.ntheta, grid.nz, grid.nz))
+        fields0.append(u0)
+        say("pcr alone", grid.nz, grid.ntheta, prec)
+        got, ref = run_pair(torch, P, env, grid, f, u0, n, "pcr_alone")
+        assert O.rel_l2(got, ref) < TOL[prec]
+        m = P.Pe3d(env, grid, f)
+        u = to_dev(torch, u0, prec)
+        m.march(n, u)
+        torch.cuda.synchronize()
+        plain.append(u)
+        m.close()
+    for use_graph in (False, True):
+        ms = [P.Pe3d(env, grid, f) for grid, f in probs]
+        us = [to_dev(torch, u0, prec) for u0 in fields0]
+        P.march_batch(ms, steps, us, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (a, b) in enumerate(zip(plain, us)):
+            assert torch.equal(a, b), f"problem {i} graph={use_graph}"
+        for m in ms:
+            m.close()
+
+
 # ---------------------------------------------------------------- size limits
 LIMITS = [
     ("max_nz_c64", W.PREC_C64, dict(nz=4096, ntheta=4, theta0=0.0, width=W.TWO_PI, dr=10.0), 100.0),

@@ -29,6 +29,8 @@ PREC_C128 = 1
 MODE_3D = 0
 MODE_NX2D = 1
 TWO_PI = 2.0 * math.pi
+AZ_CHUNKED = 0   # azimuth solver of the GPU path: chunked recurrences + wavefront scan
+AZ_PCR = 1       # parallel cyclic reduction in LDS
 
 
 @dataclass(frozen=True)
@@ -74,8 +76,9 @@ class Grid:
     azimuth); a smaller width is a sector centred on theta0 with zero field on
     the two edge azimuths.  The march starts at range r0.  mode MODE_NX2D
     drops the azimuth operator (Y = 0): N independent 2D marches.
-    depth_lanes / azimuth_lanes: kernel shape of the GPU path (0: its own
-    choice; a tuning knob that changes nothing but rounding)."""
+    depth_lanes / azimuth_lanes / azimuth_solver: kernel shape and azimuth
+    solver of the GPU path (0: its own choice, the chunked solver; tuning
+    knobs that change nothing but rounding)."""
     nz: int
     ntheta: int
     theta0: float
@@ -86,6 +89,7 @@ class Grid:
     mode: int = MODE_3D
     depth_lanes: int = 0
     azimuth_lanes: int = 0
+    azimuth_solver: int = 0
 
 
 @dataclass(frozen=True)
