@@ -70,6 +70,9 @@ def parse():
                     help="also time the config-2 grid over the range-dependent sloping bottom")
     ap.add_argument("--tune", action="store_true",
                     help="choose every problem's kernel lanes by timing its shape alone (tune.py) first")
+    ap.add_argument("--no-tune-azimuth", action="store_true",
+                    help="skip the in-batch choice of the azimuth solver (chunked or cyclic reduction) "
+                         "per Ntheta class")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the served stream (the first n of the 2000-request trace)")
     ap.add_argument("--serve-range-scale", type=float, default=1.0,
@@ -208,6 +211,18 @@ def main():
                 p.grid, depth_lanes=g.depth_lanes, azimuth_lanes=g.azimuth_lanes))
         tuned = dict(shapes=len(cache), seconds=round(time.perf_counter() - t0, 2))
         log(f"tuned {len(cache)} shapes in {tuned['seconds']} s")
+    variants = None
+    if not args.no_tune_azimuth:
+        # azimuth solver per Ntheta class, measured inside batched launches
+        # near the source and half-way through the march
+        from paper_1711_00005_amd import tune as T
+        t0 = time.perf_counter()
+        probs, variants = T.tune_batch_azimuth(probs, far=max(1, probs[0].nsteps // 2) if len(probs) == 1
+                                               else 500)
+        chosen = [c["chosen"] for c in variants["classes"].values()]
+        variants.update(seconds=round(time.perf_counter() - t0, 2),
+                        summary=f"{chosen.count('chunked')} classes chunked, {chosen.count('pcr')} cyclic reduction")
+        log(f"azimuth solver: {variants['summary']} ({variants['seconds']} s)")
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]
     torch.cuda.synchronize()
@@ -284,7 +299,8 @@ def main():
            "storage": "complex128" if args.precision == "c128" else "complex64", "data": "synthetic",
            "config": {"workload": workload, "problems": len(probs), "grid_points": npts,
                       "graph": use_graph, "chunk_steps": args.chunk, "chains": args.chains,
-                      "group_mib": args.group_mib, "tuned_lanes": tuned},
+                      "group_mib": args.group_mib, "tuned_lanes": tuned,
+                      "azimuth_solver_variants": variants},
            "roofline": roofline}
 
     # ---- plain per-frequency march on the same batch

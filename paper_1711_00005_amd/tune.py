@@ -1,12 +1,16 @@
-"""Per-shape choice of the kernels' lanes by measurement.
+"""Per-shape choice of the kernels' lanes and azimuth solver by measurement.
 
 The library picks the lanes per depth column (depth pass) and per depth line
 (azimuth pass) by a fixed rule (the fewest lanes whose chunks stay within
-the kernels' limits).  `tune` times the alternatives for one problem shape on
-the GPU, each pass separately (the depth pass does not depend on the azimuth
-lanes and vice versa), with the library's own per-launch event timing, and
-returns the fastest of each.  The lanes change only the split of the same
-recurrences over lanes, so a tuned march agrees with the default one to
+the kernels' limits), and solves the azimuth systems by chunked recurrences
+joined by a wavefront scan unless the grid asks for cyclic reduction.
+`tune` times the alternatives for one problem shape alone on the GPU, each
+pass separately (the depth pass does not depend on the azimuth lanes and
+vice versa), with the library's own per-launch event timing, and returns the
+fastest of each.  `tune_batch_azimuth` chooses the azimuth solver per class
+of problems (same Ntheta and azimuth boundary) inside batched launches, where
+a problem shares the GPU with the others.  Lanes and solver change only how
+the same systems are solved, so a tuned march agrees with the default one to
 rounding.
 """
 from __future__ import annotations
@@ -80,3 +84,66 @@ def tune(env, grid, f_hz: float, steps: int = 6, reps: int = 2) -> Tuple[object,
     best = dataclasses.replace(grid, depth_lanes=min(ta, key=ta.get),
                                azimuth_lanes=min(tb, key=tb.get) if tb else 0)
     return best, {"depth_lanes_ms": ta, "azimuth_lanes_ms": tb}
+
+
+def _batch_pass_b_ms(problems, steps: int, start: int, reps: int) -> float:
+    """Best whole-batch azimuth-pass launch time (ms) of the problems marched
+    together from step `start` (one chain, one group: one launch per pass)."""
+    import torch
+    ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in problems]
+    try:
+        us = [m.starter(p.zs) for m, p in zip(ms, problems)]
+        if start:
+            for m in ms:
+                m.set_step(start)
+        P.set_batch_schedule(1, 0)
+        P.march_batch(ms, 1, us, use_graph=False)  # first step of a call and first use
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            P.pe3d_profile_read()
+            P.pe3d_profile_enable(True)
+            try:
+                P.march_batch(ms, steps, us, use_graph=False)
+                torch.cuda.synchronize()
+                stats = P.pe3d_profile_read()
+            finally:
+                P.pe3d_profile_enable(False)
+            best = min(best, _pass_ms(stats, "pass_b"))
+        return best
+    finally:
+        P.set_batch_schedule(2, 112 << 20)
+        for m in ms:
+            m.close()
+
+
+def tune_batch_azimuth(problems, steps: int = 6, far: int = 0, reps: int = 2):
+    """Azimuth solver per class of problems (same Ntheta and boundary) by
+    measurement inside a batch: the class's problems marched together with
+    each solver near the source (from step 1, where the azimuth coupling is
+    strong and cyclic reduction needs the most levels) and from step `far`
+    (default: half the problems' steps), the solver with the smaller sum
+    chosen.  Returns the problems with the chosen solver in their grids and a
+    report {class: {solver: [near_ms, far_ms]}, ...}."""
+    import dataclasses as dc
+    far = far or max(1, min(p.nsteps for p in problems) // 2)
+    classes = {}
+    for i, p in enumerate(problems):
+        periodic = p.grid.width >= 2 * 3.141592653589793 * (1 - 1e-12)
+        classes.setdefault((p.grid.ntheta, periodic), []).append(i)
+    out = list(problems)
+    report = {}
+    for (nt, periodic), idx in sorted(classes.items()):
+        times = {}
+        for solver in (P.PE3D_AZIMUTH_CHUNKED, P.PE3D_AZIMUTH_PCR):
+            ps = [dc.replace(problems[i], grid=dc.replace(problems[i].grid, azimuth_solver=solver,
+                                                         azimuth_lanes=0)) for i in idx]
+            times[solver] = [_batch_pass_b_ms(ps, steps, 0, reps), _batch_pass_b_ms(ps, steps, far, reps)]
+        best = min(times, key=lambda k: sum(times[k]))
+        for i in idx:
+            out[i] = dc.replace(problems[i], grid=dc.replace(problems[i].grid, azimuth_solver=best))
+        key = f"ntheta {nt} {'periodic' if periodic else 'sector'} ({len(idx)} problems)"
+        report[key] = {"chunked_ms": [round(t, 4) for t in times[P.PE3D_AZIMUTH_CHUNKED]],
+                       "pcr_ms": [round(t, 4) for t in times[P.PE3D_AZIMUTH_PCR]],
+                       "chosen": "pcr" if best == P.PE3D_AZIMUTH_PCR else "chunked"}
+    return out, {"near_steps_from": 1, "far_steps_from": far, "classes": report}

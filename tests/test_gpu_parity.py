@@ -360,6 +360,30 @@ def test_tune_returns_a_shape_that_matches_oracle(torch, P):
     m.close()
 
 
+def test_tune_batch_azimuth_chooses_per_class_by_measurement(torch, P):
+    """The in-batch choice of the azimuth solver: one entry per (Ntheta,
+    boundary) class with both solvers timed near the source and further out,
+    the problems returned with the faster solver, and a march with the
+    chosen solvers matches the oracle."""
+    from paper_1711_00005_amd import tune as T
+    env = W.wedge_env()
+    probs = [W.Problem(env, W.Grid(nz=200, ntheta=nt, theta0=0.0, width=w, dr=10.0), 40.0, 100.0, 30, f"p{i}")
+             for i, (nt, w) in enumerate([(24, W.TWO_PI), (24, W.TWO_PI), (64, W.TWO_PI), (32, 1.0)])]
+    say("tune batch azimuth")
+    out, rep = T.tune_batch_azimuth(probs, steps=3, far=20, reps=1)
+    assert len(rep["classes"]) == 3
+    for c in rep["classes"].values():
+        assert all(t > 0 for t in c["chunked_ms"] + c["pcr_ms"]) and c["chosen"] in ("chunked", "pcr")
+        best = min(("chunked", "pcr"), key=lambda k: sum(c[k + "_ms"]))
+        assert c["chosen"] == best
+    assert out[0].grid.azimuth_solver == out[1].grid.azimuth_solver
+    p = out[3]
+    st = O.setup(p.env, p.grid, p.f_hz)
+    u0 = O.starter(st, p.zs)
+    got, ref = run_pair(torch, P, p.env, p.grid, p.f_hz, u0, 5, "tuned sector")
+    assert O.rel_l2(got, ref) < TOL[p.grid.precision]
+
+
 def test_tune_nx2d_times_the_depth_pass_only(torch, P):
     """The tuner of an N x 2D shape searches the depth lanes only (there is
     no azimuth pass) and its choice matches the oracle."""
