@@ -488,6 +488,22 @@ def range_report(P, nsteps=1000):
         msps = e0.elapsed_time(e1) / nsteps
         res[name] = dict(ms_per_step=round(msps, 5),
                          pt_steps_per_s=p.points / (msps * 1e-3))
+        if name == "wedge_range_independent":
+            # the same lone problem through the batched march: calls of 100
+            # steps, each replayed from a captured graph
+            m.set_step(0)
+            P.prepare_batch([m], 100, [u])
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(nsteps // 100):
+                P.march_batch([m], 100, [u], use_graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            g = e0.elapsed_time(e1) / (100 * (nsteps // 100))
+            res["wedge_range_independent_graph"] = dict(ms_per_step=round(g, 5),
+                                                        pt_steps_per_s=p.points / (g * 1e-3),
+                                                        how="pe3d_march_batch of the one problem, "
+                                                            "calls of 100 steps replayed from a graph")
         m.close()
     res.update(workload="config2 grid: periodic wedge vs slope_env (d0 400 m, 3 deg plane slope "
                         "clipped to 30-2500 m, rows every 250 m) vs front_env (the wedge under a Munk "
