@@ -205,14 +205,22 @@ pe3d_status pe3d_march(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream)
 #define PE3D_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
 pe3d_status pe3d_march_static(pe3d_handle h, int32_t nsteps, void* u_dev, void* stream);
 
-/* Release every device and host resource of the handle.  NULL is OK.  The
- * caller must make sure no enqueued work of the handle is still running.
+/* Release every device and host resource of the handle.  NULL is OK.
  * Does not synchronise the device: the handle's device memory goes back to
  * the library's pool (reused by later handles and batch plans of the same
- * size class, returned to the runtime only when an allocation fails), and
+ * size class) once an event recorded now on the stream of the handle's last
+ * enqueued work has passed, so that stream must still exist at this call;
  * the batch plans that used the handle are freed once their last work has
- * finished. */
+ * finished.  Work of the handle enqueued on other streams than its last one
+ * must have finished. */
 pe3d_status pe3d_destroy(pe3d_handle h);
+
+/* Return the library's pooled device memory that no handle, plan or pending
+ * work holds to the runtime (hipFree, which waits for the device), on every
+ * device.  Pooled blocks are otherwise kept for reuse until the process ends,
+ * or until an allocation fails.  *bytes (may be NULL) receives the bytes
+ * returned.  Errors: PE3D_EDEVICE. */
+pe3d_status pe3d_release_pooled_memory(size_t* bytes);
 
 /* Device bytes pe3d_create would allocate for these arguments (coefficient
  * tables, one block per water-profile row, + scratch field), excluding the

@@ -119,6 +119,20 @@ hipError_t pool_alloc(void** out, size_t n) {
   return hipSuccess;
 }
 
+// Free every pooled (idle) block; returns the bytes freed.
+size_t pool_trim() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  size_t n = 0;
+  for (auto& kv : g_pool_free) {
+    for (void* b : kv.second) {
+      (void)hipFree(b);
+      n += kv.first.second;
+    }
+    kv.second.clear();
+  }
+  return n;
+}
+
 // The block must no longer be used by any enqueued work.
 void pool_release(void* b) {
   if (!b) return;
@@ -1536,6 +1550,17 @@ extern "C" pe3d_status pe3d_profile_read(pe3d_kernel_stat* stats, int32_t cap, i
   *n = int(order.size());
   for (int i = 0; i < int(order.size()) && i < cap; ++i) stats[i] = agg[order[i]];
   return st;
+}
+
+extern "C" pe3d_status pe3d_release_pooled_memory(size_t* bytes) {
+  {
+    // blocks whose plans or handles have finished join the pool first
+    std::lock_guard<std::mutex> lk(g_mu);
+    reap();
+  }
+  const size_t n = pool_trim();
+  if (bytes) *bytes = n;
+  return hipGetLastError() == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
 }
 
 extern "C" pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes) {

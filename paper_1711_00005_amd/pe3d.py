@@ -49,7 +49,7 @@ PE3D_AZIMUTH_PCR = 1
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
             "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror",
-            "pe3d_set_batch_schedule", "pe3d_march_static")
+            "pe3d_set_batch_schedule", "pe3d_march_static", "pe3d_release_pooled_memory")
 
 
 class pe3d_env(ct.Structure):
@@ -112,6 +112,7 @@ _lib.pe3d_profile_enable.argtypes = [ct.c_int32]
 _lib.pe3d_profile_read.argtypes = [ct.POINTER(pe3d_kernel_stat), ct.c_int32, ct.POINTER(ct.c_int32)]
 _lib.pe3d_strerror.argtypes = [ct.c_int]
 _lib.pe3d_set_batch_schedule.argtypes = [ct.c_int32, ct.c_int64]
+_lib.pe3d_release_pooled_memory.argtypes = [ct.POINTER(ct.c_size_t)]
 for _n in EXPORTED:
     getattr(_lib, _n).restype = ct.c_int
 _lib.pe3d_strerror.restype = ct.c_char_p
@@ -294,6 +295,13 @@ def pe3d_march_batch(handles: Sequence[int], nsteps: Sequence[int], u_ptrs: Sequ
 
 def pe3d_set_batch_schedule(chains: int, group_bytes: int) -> None:
     _check(_lib.pe3d_set_batch_schedule(int(chains), int(group_bytes)), "pe3d_set_batch_schedule")
+
+
+def pe3d_release_pooled_memory() -> int:
+    """Return the library's idle pooled device memory to the runtime; bytes freed."""
+    n = ct.c_size_t(0)
+    _check(_lib.pe3d_release_pooled_memory(ct.byref(n)), "pe3d_release_pooled_memory")
+    return int(n.value)
 
 
 def pe3d_profile_enable(on: bool) -> None:

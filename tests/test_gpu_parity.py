@@ -888,6 +888,17 @@ def test_pooled_blocks_of_a_destroyed_handle_serve_a_new_one(torch, P):
     assert torch.equal(ub, urb)
     b.close()
     rb.close()
+    # the idle pool goes back to the runtime, and marching works after it
+    torch.cuda.synchronize()
+    assert P.pe3d_release_pooled_memory() > 0
+    assert P.pe3d_release_pooled_memory() == 0
+    c = P.Pe3d(env, g, 50.0)
+    uc = c.starter(80.0)
+    c.march(3, uc)
+    got = to_host(torch, uc)
+    st = O.setup(env, g, 50.0)
+    assert O.rel_l2(got, O.march(st, O.starter(st, 80.0), 0, 3)) < TOL[g.precision]
+    c.close()
 
 
 def test_prepared_graph_runs_nothing_then_replays(torch, P):
