@@ -281,6 +281,51 @@ pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n,
  * in MI355X's 256 MB last-level cache.  Errors: PE3D_EINVAL. */
 pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes);
 
+/* Kernel of later pe3d_march_batch plans (library-wide; plans already built
+ * keep theirs):
+ *   PE3D_BATCH_LAUNCHES (default): one launch per pass per step per group,
+ *     as described at pe3d_march_batch;
+ *   PE3D_BATCH_PERSISTENT: one persistent kernel per call runs every step of
+ *     every problem (the frequency loop of Fig. 2 on one device).  Its
+ *     workgroups (as many as are resident at once, 256 lanes each) take
+ *     tasks from a device list in order: one depth-pass tile or one group of
+ *     azimuth-pass tiles of one problem at one step.  The list holds the same
+ *     chains and groups as the launches, their phases (one pass of one step
+ *     of one group) interleaved chain by chain.  A task starts once its
+ *     problem's counter shows that the other pass of its step (depth pass)
+ *     or of the previous step (azimuth pass) has finished; every such wait
+ *     is bounded by wait_limit_s (>= 0, finite; default 1 s): when a wait
+ *     runs out the call's workgroups leave early, the call's fields and step
+ *     counters are then undefined, and pe3d_batch_wait_timeouts reports it.
+ *     A call whose problems include range rows (depth or water) uses the
+ *     launches.  Results are meant to be bitwise identical to the launches.
+ *     SWITCHED OFF: the first run of this kernel on the device made no
+ *     progress for minutes and no cause has been found in the code, so
+ *     asking for it returns PE3D_EUNSUPPORTED and the launches stay in use.
+ * Errors: PE3D_EINVAL (unknown kind, wait_limit_s negative, not finite or
+ * above 3600), PE3D_EUNSUPPORTED (PE3D_BATCH_PERSISTENT, switched off). */
+#define PE3D_BATCH_LAUNCHES 0
+#define PE3D_BATCH_PERSISTENT 1
+pe3d_status pe3d_set_batch_kernel(int32_t kind, double wait_limit_s);
+
+/* Waits of persistent batched marches on the current device that ran out
+ * since the last call (the count is then reset).  Synchronous: call it
+ * after the marches' streams have been synchronised.  Errors: PE3D_EINVAL
+ * (null), PE3D_EDEVICE. */
+pe3d_status pe3d_batch_wait_timeouts(int64_t* count);
+
+/* Host only, for tests of the persistent kernel's task list: the list the
+ * library builds for n problems with na[i] depth-pass tiles, nb[i]
+ * azimuth-pass tiles (0: no azimuth pass) taken nsub[i] at a time, nsteps[i]
+ * steps, in group group[i] of chain chain[i] (groups numbered from 0 within
+ * each chain, problems listed in their group's order).  Writes up to `cap`
+ * tasks as 6 int32 each (problem, first tile, step, kind 0 depth / 1
+ * azimuth, tiles of the task, finished tasks of the problem it waits for)
+ * and sets *ntasks to the list's length.  Errors: PE3D_EINVAL. */
+pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* nb, const int32_t* nsub,
+                                  const int32_t* nsteps, const int32_t* chain, const int32_t* group,
+                                  int32_t* tasks, int64_t cap, int64_t* ntasks);
+
 /* Transmission loss of a field at the handle's current step (Sec. 4.1,
  * Fig. 5): tl[m*nz + l] = -20 log10 |u| + 10 log10 r_j, in FP32, written to a
  * device array of ntheta*nz floats.  Asynchronous on `stream`. */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <limits>
 #include <list>
 #include <cmath>
 #include <complex>
@@ -695,6 +696,15 @@ struct BatchPlan {
   }
   // device blocks of destroyed handles this plan used: released with it
   std::vector<std::shared_ptr<HandleBlocks>> keep;
+  // persistent kernel (pe3d_set_batch_kernel): its task list, the launch's
+  // control words and per-problem counters (2 + n ints, zeroed by the launch)
+  bool persist = false;
+  PTask* d_tasks = nullptr;
+  int ntasks = 0;
+  int* d_ctl = nullptr;
+  int lds_p = 0;
+  double bytes_p = 0.0;       // algorithmic bytes of the whole call
+  long long wait_ticks = 0;
 };
 
 // Batch schedule (pe3d_set_batch_schedule): independent chains replayed on
@@ -702,6 +712,10 @@ struct BatchPlan {
 constexpr int kMaxChains = 4;
 std::atomic<int> g_chains{2};
 std::atomic<long long> g_group_bytes{112ll << 20};
+
+// Batch kernel (pe3d_set_batch_kernel) and the persistent kernel's wait limit.
+std::atomic<int> g_batch_kernel{PE3D_BATCH_LAUNCHES};
+std::atomic<double> g_wait_limit_s{1.0};
 
 constexpr int kBatchClass = -1;  // profiling name "batch"
 
@@ -1266,8 +1280,79 @@ std::vector<std::vector<std::vector<int>>> batch_partition(const pe3d_handle* hs
   return out;
 }
 
+// The persistent kernel's task list.  Problem p has na depth-pass tiles and
+// nb azimuth-pass tiles (0: none), taken nsub at a time; its tasks of one
+// step are the depth pass's na then the azimuth pass's ceil(nb / nsub), and
+// a task waits for every task of the problem's earlier passes.  Per chain,
+// the phases (one pass of one step of one group, over the group's problems
+// still stepping) follow each group through its steps, groups in order; the
+// chains' phases are interleaved, phase i of every chain before phase i + 1
+// of any, so that the wait of a phase for the previous phase of its group
+// is covered by the other chains' work.  Every task's waits are on tasks
+// earlier in the list.
+struct PersistProb {
+  int na, nb, nsub, nsteps;
+};
+void persist_tasks(const std::vector<std::vector<std::vector<int>>>& chains, const std::vector<PersistProb>& pp,
+                   std::vector<PTask>& out) {
+  struct Phase {
+    int g, k, kind;
+  };
+  std::vector<std::vector<Phase>> ph(chains.size());
+  size_t most = 0;
+  for (size_t c = 0; c < chains.size(); ++c) {
+    for (int g = 0; g < int(chains[c].size()); ++g) {
+      int ms = 0;
+      bool azimuth = false;
+      for (int p : chains[c][g]) {
+        ms = std::max(ms, pp[p].nsteps);
+        azimuth = azimuth || pp[p].nb > 0;
+      }
+      for (int k = 0; k < ms; ++k) {
+        ph[c].push_back({g, k, 0});
+        if (azimuth) ph[c].push_back({g, k, 1});
+      }
+    }
+    most = std::max(most, ph[c].size());
+  }
+  out.clear();
+  for (size_t i = 0; i < most; ++i)
+    for (size_t c = 0; c < chains.size(); ++c) {
+      if (i >= ph[c].size()) continue;
+      const Phase f = ph[c][i];
+      for (int p : chains[c][f.g]) {
+        const PersistProb& q = pp[p];
+        if (q.nsteps <= f.k) continue;
+        const int nbt = q.nb > 0 ? (q.nb + q.nsub - 1) / q.nsub : 0;
+        const int per_step = q.na + nbt;
+        if (f.kind == 0) {
+          for (int t = 0; t < q.na; ++t) out.push_back({p, t, f.k, f.k * per_step, 0, 1});
+        } else {
+          for (int t = 0; t < nbt; ++t)
+            out.push_back({p, t * q.nsub, f.k, f.k * per_step + q.na, 1, short(q.nsub)});
+        }
+      }
+    }
+}
+
+// Azimuth-pass tiles of the persistent kernel (256 lanes) and how many one
+// task takes: consecutive tiles until a depth line's segment fills a
+// 128-byte cache line, so that one workgroup reads whole lines.
+void persist_b_shape(const pe3d_handle h, int& nb, int& nsub) {
+  const ProbDesc& d = h->desc;
+  const int esz = h->prec ? 16 : 8;
+  if (d.nx2d) {
+    nb = 0;
+    nsub = 1;
+    return;
+  }
+  const int td = d.bcls == kPcrClass ? d.td : kPersistThreads / d.wb;
+  nb = d.bcls == kPcrClass ? d.ntile_b : (d.nz + td - 1) / td;
+  nsub = std::max(1, std::min(8, 128 / (td * esz)));
+}
+
 pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
-                       int nchains, long long group_bytes, BatchPlan& P) {
+                       int nchains, long long group_bytes, bool persist, long long wait_ticks, BatchPlan& P) {
   auto part = batch_partition(hs, n, nsteps, nchains, group_bytes);
   // problem slots in the descriptor table, in partition order
   std::vector<int> order;
@@ -1303,8 +1388,10 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
           int(std::lower_bound(steps.begin(), steps.end(), k, [](int a, int v) { return a > v; }) - steps.begin());
     return c;
   };
+  std::vector<std::vector<std::vector<int>>> pchains;  // slots, in the groups' order
   for (auto& cpart : part) {
     std::vector<BatchPlan::Group> chain;
+    pchains.emplace_back();
     for (auto g : cpart) {
       // within a group: problems sorted by steps (descending) so that the
       // problems still stepping at step k are a prefix of every item list,
@@ -1315,6 +1402,9 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
         if (nsteps[a] != nsteps[b]) return nsteps[a] > nsteps[b];
         return hs[a]->desc.nz > hs[b]->desc.nz;
       });
+      pchains.back().emplace_back();
+      for (int i : g) pchains.back().back().push_back(slot[i]);
+      if (persist) continue;
       BatchPlan::Group G;
       G.maxsteps = nsteps[g[0]];
       std::vector<WorkItem> ia, ib, iu;
@@ -1362,6 +1452,28 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     }
     P.chains.push_back(std::move(chain));
   }
+  std::vector<PTask> tasks;
+  if (persist) {
+    std::vector<PersistProb> pp(np);
+    for (int p = 0; p < np; ++p) {
+      pe3d_handle h = hs[order[p]];
+      pp[p].na = h->desc.ntile_a;
+      persist_b_shape(h, pp[p].nb, pp[p].nsub);
+      pp[p].nsteps = nsteps[order[p]];
+      const double esz = h->prec ? 16.0 : 8.0;
+      const double pts = double(h->desc.nz) * h->desc.nth;
+      P.bytes_p += pp[p].nsteps * (pp[p].nb > 0 ? 4.0 : 2.0) * esz * pts;
+      P.lds_p = std::max(P.lds_p, h->lds_a);
+      if (pp[p].nb > 0)
+        P.lds_p = std::max(P.lds_p, pass_b_lds(h->prec, h->desc.bcls == kPcrClass ? 0 : h->desc.wb,
+                                               h->desc.mb, kPersistThreads));
+    }
+    persist_tasks(pchains, pp, tasks);
+    if (tasks.size() > size_t(std::numeric_limits<int>::max())) return PE3D_EUNSUPPORTED;
+    P.persist = true;
+    P.ntasks = int(tasks.size());
+    P.wait_ticks = wait_ticks;
+  }
   size_t nitems = 0;
   for (auto& c : P.chains)
     for (auto& g : c)
@@ -1371,8 +1483,11 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   size_t off_j = (off_desc + np * sizeof(ProbDesc) + 255) & ~size_t(255);
   size_t off_add = (off_j + np * sizeof(long long*) + 255) & ~size_t(255);
   size_t off_it = (off_add + np * sizeof(int) + 255) & ~size_t(255);
-  size_t total = off_it + nitems * sizeof(WorkItem) + 256;
+  size_t off_tk = (off_it + nitems * sizeof(WorkItem) + 255) & ~size_t(255);
+  size_t off_ctl = (off_tk + tasks.size() * sizeof(PTask) + 255) & ~size_t(255);
+  size_t total = off_ctl + (persist ? (2 + np) * sizeof(int) : 0) + 256;
   std::vector<unsigned char> img(total, 0);
+  if (persist) std::memcpy(img.data() + off_tk, tasks.data(), tasks.size() * sizeof(PTask));
   std::memcpy(img.data() + off_desc, descs.data(), np * sizeof(ProbDesc));
   std::memcpy(img.data() + off_j, jdevs.data(), np * sizeof(long long*));
   std::memcpy(img.data() + off_add, adds.data(), np * sizeof(int));
@@ -1381,6 +1496,10 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   P.d_descs = reinterpret_cast<ProbDesc*>(base + off_desc);
   P.d_jdevs = reinterpret_cast<long long**>(base + off_j);
   P.d_adds = reinterpret_cast<int*>(base + off_add);
+  if (persist) {
+    P.d_tasks = reinterpret_cast<PTask*>(base + off_tk);
+    P.d_ctl = reinterpret_cast<int*>(base + off_ctl);
+  }
   size_t cur = off_it;
   for (auto& c : P.chains)
     for (auto& g : c)
@@ -1481,21 +1600,36 @@ pe3d_status fork_join(const BatchPlan& P, hipStream_t st, F run) {
   return enqueue_advance(P, st);
 }
 
+// The persistent kernel (its counters zeroed first) on the caller's stream.
+pe3d_status enqueue_persist(const BatchPlan& P, hipStream_t st, bool profile) {
+  return prof_launch("persist", P.prec, kBatchClass, P.bytes_p, st, [&] {
+           return launch_persist(P.prec, P.d_descs, P.d_tasks, P.ntasks, P.d_ctl, P.n, P.wait_ticks, P.lds_p, st);
+         }, profile) == hipSuccess
+             ? PE3D_OK
+             : PE3D_EDEVICE;
+}
+
 // Direct launches, on the same streams as a graph replay.
 pe3d_status enqueue_plan(BatchPlan& P, hipStream_t st) {
+  if (P.persist) {
+    pe3d_status s = enqueue_persist(P, st, true);
+    return s == PE3D_OK ? enqueue_advance(P, st) : s;
+  }
   pe3d_status s = ensure_side(P);
   if (s != PE3D_OK) return s;
   return fork_join(P, st, [&](size_t c, hipStream_t cs) { return enqueue_chain(P, P.chains[c], cs, true); });
 }
 
-// One graph per chain, captured on a private stream.
+// One graph per chain (persistent kernel: one graph), captured on a private
+// stream.
 pe3d_status capture_plan(BatchPlan& P) {
-  for (const auto& c : P.chains) {
+  const size_t ng = P.persist ? 1 : P.chains.size();
+  for (size_t ci = 0; ci < ng; ++ci) {
     hipStream_t cap;
     if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return PE3D_EDEVICE;
     pe3d_status s = PE3D_OK;
     if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PE3D_EDEVICE;
-    if (s == PE3D_OK) s = enqueue_chain(P, c, cap, false);
+    if (s == PE3D_OK) s = P.persist ? enqueue_persist(P, cap, false) : enqueue_chain(P, P.chains[ci], cap, false);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cap, &g) != hipSuccess && s == PE3D_OK) s = PE3D_EDEVICE;
     (void)hipStreamDestroy(cap);
@@ -1505,10 +1639,14 @@ pe3d_status capture_plan(BatchPlan& P) {
     if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) return PE3D_EDEVICE;
     P.execs.push_back(x);
   }
-  return ensure_side(P);
+  return P.persist ? PE3D_OK : ensure_side(P);
 }
 
 pe3d_status replay_plan(const BatchPlan& P, hipStream_t st) {
+  if (P.persist) {
+    if (hipGraphLaunch(P.execs[0], st) != hipSuccess) return PE3D_EDEVICE;
+    return enqueue_advance(P, st);
+  }
   return fork_join(P, st, [&](size_t c, hipStream_t cs) {
     return hipGraphLaunch(P.execs[c], cs) == hipSuccess ? PE3D_OK : PE3D_EDEVICE;
   });
@@ -1570,6 +1708,61 @@ extern "C" pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_byt
   return PE3D_OK;
 }
 
+// The persistent kernel is switched off: its first run on the device made
+// no progress for minutes, with no cause found in the code; requests for it
+// are refused until one is.
+constexpr bool kPersistEnabled = false;
+
+extern "C" pe3d_status pe3d_set_batch_kernel(int32_t kind, double wait_limit_s) {
+  if (kind != PE3D_BATCH_LAUNCHES && kind != PE3D_BATCH_PERSISTENT) return PE3D_EINVAL;
+  if (!(wait_limit_s >= 0.0 && wait_limit_s <= 3600.0)) return PE3D_EINVAL;  // NaN fails too
+  if (kind == PE3D_BATCH_PERSISTENT && !kPersistEnabled) return PE3D_EUNSUPPORTED;
+  g_batch_kernel.store(kind);
+  g_wait_limit_s.store(wait_limit_s);
+  return PE3D_OK;
+}
+
+extern "C" pe3d_status pe3d_batch_wait_timeouts(int64_t* count) {
+  if (!count) return PE3D_EINVAL;
+  unsigned long long v = 0;
+  if (persist_take_timeouts(&v) != hipSuccess) return PE3D_EDEVICE;
+  *count = int64_t(v);
+  return PE3D_OK;
+}
+
+extern "C" pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* nb, const int32_t* nsub,
+                                             const int32_t* nsteps, const int32_t* chain, const int32_t* group,
+                                             int32_t* tasks, int64_t cap, int64_t* ntasks) {
+  if (n < 1 || !na || !nb || !nsub || !nsteps || !chain || !group || !ntasks || cap < 0 || (cap > 0 && !tasks))
+    return PE3D_EINVAL;
+  std::vector<std::vector<std::vector<int>>> chains;
+  std::vector<PersistProb> pp(n);
+  for (int i = 0; i < n; ++i) {
+    if (na[i] < 1 || nb[i] < 0 || nsub[i] < 1 || nsub[i] > 8 || nsteps[i] < 0 || chain[i] < 0 ||
+        chain[i] > 1024 || group[i] < 0 || group[i] > 1 << 20)
+      return PE3D_EINVAL;
+    pp[i] = {na[i], nb[i], nsub[i], nsteps[i]};
+    if (int(chains.size()) <= chain[i]) chains.resize(chain[i] + 1);
+    auto& c = chains[chain[i]];
+    if (int(c.size()) <= group[i]) c.resize(group[i] + 1);
+    c[group[i]].push_back(i);
+  }
+  std::vector<PTask> out;
+  persist_tasks(chains, pp, out);
+  *ntasks = int64_t(out.size());
+  for (int64_t t = 0; t < std::min<int64_t>(cap, int64_t(out.size())); ++t) {
+    const PTask& k = out[t];
+    int32_t* o = tasks + 6 * t;
+    o[0] = k.prob;
+    o[1] = k.tile;
+    o[2] = k.k;
+    o[3] = k.kind;
+    o[4] = k.nsub;
+    o[5] = k.need;
+  }
+  return PE3D_OK;
+}
+
 constexpr int32_t kPrepareOnly = 2;  // pe3d_march_batch: build and capture, do not launch
 
 extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const int32_t* nsteps,
@@ -1588,10 +1781,22 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
 
   const int nchains = g_chains.load();
   const long long group_bytes = g_group_bytes.load();
+  // the persistent kernel, unless a problem has range rows (its medium
+  // changes from step to step)
+  bool persist = g_batch_kernel.load() == PE3D_BATCH_PERSISTENT;
+  for (int i = 0; i < n && persist; ++i)
+    if (nsteps[i] > 0 && (hs[i]->desc.nbr || hs[i]->desc.nsr)) persist = false;
+  const double wait_s = g_wait_limit_s.load();
   std::vector<uintptr_t> key;
-  key.reserve(3 * n + 2);
+  key.reserve(3 * n + 4);
   key.push_back(uintptr_t(nchains));
   key.push_back(uintptr_t(group_bytes));
+  key.push_back(uintptr_t(persist));
+  {
+    uint64_t wb = 0;
+    std::memcpy(&wb, &wait_s, sizeof wb);
+    key.push_back(uintptr_t(persist ? wb : 0));
+  }
   for (int i = 0; i < n; ++i) {
     key.push_back(reinterpret_cast<uintptr_t>(hs[i]));
     key.push_back(reinterpret_cast<uintptr_t>(u_devs[i]));
@@ -1611,7 +1816,15 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
     if (!fresh) return PE3D_ENOMEM;
     fresh->key = key;
     fresh->handles.assign(hs, hs + n);
-    pe3d_status s = build_plan(hs, n, nsteps, u_devs, nchains, group_bytes, *fresh);
+    long long ticks = 0;
+    if (persist) {
+      int dev = 0, khz = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;  // the constant-rate clock of CDNA devices: 100 MHz
+      ticks = (long long)std::llround(wait_s * 1000.0 * khz);
+    }
+    pe3d_status s = build_plan(hs, n, nsteps, u_devs, nchains, group_bytes, persist, ticks, *fresh);
     if (s != PE3D_OK) return s;
     if (hipEventCreateWithFlags(&fresh->done, hipEventDisableTiming) != hipSuccess) return PE3D_EDEVICE;
     plan = fresh.get();

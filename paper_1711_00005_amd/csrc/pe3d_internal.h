@@ -91,6 +91,21 @@ struct WorkItem {
 
 constexpr int kPassBThreads = 512;
 
+// Persistent batched march (march_persist): workgroup lanes, and one task of
+// its list (see pe3d_kernels.hip).  kind 0: depth-pass tile `tile` of problem
+// `prob` at step k of the call; kind 1: azimuth-pass tiles tile .. tile+nsub-1
+// (tiles of kPersistThreads lanes).  need: finished tasks of the problem
+// before this one may start.
+constexpr int kPersistThreads = 256;
+struct PTask {
+  int prob;
+  int tile;
+  int k;
+  int need;
+  short kind;
+  short nsub;
+};
+
 // Azimuth pass by parallel cyclic reduction (pass_b_pcr_body): class of the
 // batched kernels' dispatch (ProbDesc::bcls), nodes (azimuth x depth) of one
 // workgroup's tile held in LDS as FP64 complex, and its depths per tile: the
@@ -130,7 +145,15 @@ int pass_a_lds(int prec, int L, int nz, int M);  // dynamic LDS bytes of one pas
 hipError_t launch_pass_a_multi(int prec, const ProbDesc& d, int lds, hipStream_t st);
 hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,
                          int nitems, int koff, int lds, hipStream_t st);
-int pass_b_lds(int prec, int W, int M);  // dynamic LDS bytes of one pass B workgroup
+// dynamic LDS bytes of one pass B workgroup of nthr lanes (W = 0: cyclic reduction)
+int pass_b_lds(int prec, int W, int M, int nthr = kPassBThreads);
+// The persistent batched march: ctl_done (2 + nprob ints) zeroed, then
+// march_persist over the task list with as many workgroups as fit on the
+// device (at most ntasks).  lds: the largest dynamic LDS of the tasks' passes.
+hipError_t launch_persist(int prec, const ProbDesc* d_descs, const PTask* tasks, int ntasks, int* ctl_done,
+                          int nprob, long long wait_ticks, int lds, hipStream_t st);
+// Waits of the persistent march that ran out since the last call (and reset).
+hipError_t persist_take_timeouts(unsigned long long* n);
 // the medium of the step at r_{j+1} for problems with range rows: the water
 // nodes of every column (depth rows) and the water-profile row (water rows)
 // (single: one problem; else nitems items of 256 columns each)

@@ -42,6 +42,8 @@
 // amount on every step and the error would grow linearly with range; data
 // roundings change from step to step and only accumulate as a random walk.
 #include <hip/hip_runtime.h>
+#include <algorithm>
+#include <map>
 #include <mutex>
 #include <type_traits>
 #include <utility>
@@ -127,6 +129,17 @@ template <>
 struct Vec2<double> {
   typedef double type __attribute__((ext_vector_type(2)));
 };
+// threadIdx.x; FRESH: read afresh at each use.  Inside the persistent
+// kernel's task loop the compiler would otherwise hoist the lane arithmetic
+// of every pass body out of the loop and keep all of it live across the
+// whole loop (spilling registers).
+template <bool FRESH>
+__device__ __forceinline__ int lane_id() {
+  int x = threadIdx.x;
+  if (FRESH) asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <typename S>
 __device__ __forceinline__ C<S> gload(const C<S>* base, unsigned off) {
   using V = typename Vec2<S>::type;
@@ -352,11 +365,11 @@ constexpr int kPassAThreads = 256;
 // first lane of the next row and lane 32 by shuffles), then a DPP shift by
 // one lane.  Columns wider than a wavefront combine the wavefront totals
 // through LDS.  tot: LDS scratch, 2 complex per wavefront.
-template <bool UP>
+template <bool UP, bool FRESH>
 __device__ __forceinline__ D scan_excl(D A, D B, int t, int L, D* tot) {
   const int w = L < 64 ? L : 64;
   const int tw = t & (w - 1);
-  const int h = threadIdx.x & 63;
+  const int h = lane_id<FRESH>() & 63;
   const int pr = h & 15;
   // the lane's map composed after the neighbour's (ap, bq)
   auto comb = [&](const D& ap, const D& bq, bool take) {
@@ -391,7 +404,7 @@ __device__ __forceinline__ D scan_excl(D A, D B, int t, int L, D* tot) {
   }
   D x = zero<double>();
   if (L > 64) {
-    const int wave = threadIdx.x >> 6;
+    const int wave = lane_id<FRESH>() >> 6;
     if (UP ? (tw == 63) : (tw == 0)) {
       tot[2 * wave + 0] = A;
       tot[2 * wave + 1] = B;
@@ -425,9 +438,10 @@ __host__ __device__ constexpr int pass_a_lds_bytes(int esz, int L, int N, int M)
 // column depends on nothing but itself, so the workgroup's columns stay in
 // LDS from step to step, read from the caller's field once (koff = 0) and
 // written back once.  Otherwise one step, koff steps into the call.
-template <typename S, int M, bool MULTI = false>
+// FRESH: see lane_id (the persistent kernel)
+template <typename S, int M, bool MULTI = false, bool FRESH = false>
 __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
-  const int lane = threadIdx.x;
+  const int lane = lane_id<FRESH>();
   const int L = d.lpc;
   const int lgL = 31 - __clz(L);
   const int cpw = kPassAThreads >> lgL;
@@ -721,7 +735,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       phase1(std::true_type{});
     else
       phase1(std::false_type{});
-    const D cin = scan_excl<true>(tp, E, t, L, tot);
+    const D cin = scan_excl<true, FRESH>(tp, E, t, L, tot);
 
     // ---- phase 2: elimination with the exact carry; Rv <- yh (head slot: the
     //      reduced interface right-hand side, divided by nbmh).  The same sweep
@@ -799,7 +813,7 @@ __device__ __forceinline__ void pass_a_body(const ProbDesc& d, int tile, int kof
       Rv[M - 1] = fma(hrec(4), Rv[M - 1], mul(hrec(5), xch[2 * cw + (bot ? 0 : 1)]));
       X = fma(pr, Rv[M - 1], X);
     }
-    const D xin = scan_excl<false>(head ? zero<double>() : tp, X, t, L, tot);
+    const D xin = scan_excl<false, FRESH>(head ? zero<double>() : tp, X, t, L, tot);
 
     // ---- phase 3: back substitution with the exact carry, written to the column
     //      buffer (the input was last read before the interface barrier; zero
@@ -962,23 +976,25 @@ struct BConst {
 constexpr int kPassBPow = 64;  // sPowC / sPowS entries: chunks <= 64
 
 __host__ __device__ constexpr int pass_b_ds(int M) { return M | 1; }
-__host__ __device__ constexpr int pass_b_tile_elems(int W, int M) {
-  return W * ((kPassBThreads / W) * pass_b_ds(M) + 1);
+__host__ __device__ constexpr int pass_b_tile_elems(int W, int M, int nthr = kPassBThreads) {
+  return W * ((nthr / W) * pass_b_ds(M) + 1);
 }
-__host__ __device__ constexpr int pass_b_lds_bytes(int esz, int W, int M) {
-  return ((pass_b_tile_elems(W, M) * esz + 15) & ~15) + int(sizeof(BConst)) + 2 * kPassBPow * 16;
+__host__ __device__ constexpr int pass_b_lds_bytes(int esz, int W, int M, int nthr = kPassBThreads) {
+  return ((pass_b_tile_elems(W, M, nthr) * esz + 15) & ~15) + int(sizeof(BConst)) + 2 * kPassBPow * 16;
 }
 
 // EQ: every chunk holds exactly M nodes (NT = W*M, M = MM); otherwise M =
 // d.mb <= MM at run time and the last chunk holds NT - (NC-1) M nodes.
-template <typename S, int MM, bool EQ>
+// NTHR: lanes of the workgroup (512; 256 in the persistent batched kernel,
+// whose tiles then hold half the depths).
+template <typename S, int MM, bool EQ, int NTHR = kPassBThreads>
 __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
-  constexpr int NTHR = kPassBThreads;
-  const int tid = threadIdx.x;
+  static_assert(NTHR == 256 || NTHR == 512, "pass B workgroups hold 256 or 512 lanes");
+  const int tid = lane_id<NTHR != kPassBThreads>();
   const int W = d.wb;
   const int lgW = 31 - __clz(W);
   const int TD = NTHR >> lgW;
-  const int lgTD = 9 - lgW;
+  const int lgTD = (NTHR == 512 ? 9 : 8) - lgW;
   const int M = EQ ? MM : d.mb;
   const int DS = EQ ? pass_b_ds(MM) : pass_b_ds(M);
   const int N = d.nz, NT = d.nth;
@@ -1001,7 +1017,7 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
   };
 
   // ---- stage the tile: thread tid loads chunk tid / TD of depth z0 + tid % TD
-  //      (W chunks x TD depths = 512 threads); all loads issued before the
+  //      (W chunks x TD depths = NTHR threads); all loads issued before the
   //      first LDS write
   const int sdl = tid & (TD - 1);
   const int sc0 = tid >> lgTD;
@@ -1255,11 +1271,10 @@ __device__ __forceinline__ void pass_b_body(const ProbDesc& d, int tile, int kof
 // rounded values before the store.
 __host__ __device__ constexpr int pass_b_pcr_lds_bytes() { return kPcrNodes * 16; }
 
-template <typename S>
+template <typename S, int NTHR = kPassBThreads>
 __device__ __forceinline__ void pass_b_pcr_body(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
-  constexpr int NTHR = kPassBThreads;
   constexpr int NPT = kPcrNodes / NTHR;  // nodes per thread
-  const int tid = threadIdx.x;
+  const int tid = lane_id<NTHR != kPassBThreads>();
   const int NT = d.nth, N = d.nz, TD = d.td;
   const int lgTD = 31 - __clz(TD);
   const int z0 = tile * TD;
@@ -1415,6 +1430,125 @@ __global__ __launch_bounds__(kPassBThreads) void pass_b_pcr_single(ProbDesc d, i
   const int tile = pass_b_pairs(d.td, int(sizeof(C<S>))) ? pass_b_paired_tile(b, d.ntile_b) : b;
   pass_b_pcr_body<S>(d, tile, koff, smem_b);
   medium_update_next(d, tile, koff);
+}
+
+// ============================================================== persistent batched march
+// One launch runs every step of a batched march (the paper's loop over
+// frequencies, each marched through its range steps, carried onto one
+// device): the workgroups, as many as fit on the device at once, take tasks
+// from a list in list order, one atomic increment per task.  A task is one
+// depth-pass tile (a span of columns) or one azimuth-pass tile group (nsub
+// consecutive tiles of 256 lanes) of one problem at one step.  A problem's
+// tasks enter the list step by step, the depth pass before the azimuth pass,
+// and each task carries the number of the problem's tasks that must have
+// finished before it may start: every task of the step's depth pass (for the
+// azimuth pass), or of the previous step (for the depth pass).  A workgroup
+// only ever waits for tasks that precede its own in the list, which were
+// taken by workgroups already running, so every wait ends without any
+// assumption on how many workgroups are resident.  Each wait is also bounded
+// in time: when it runs out, the workgroup counts the timeout
+// (g_wait_timeouts), raises the launch's abort flag and leaves; workgroups
+// that are waiting see the flag and leave too, so the kernel always ends
+// (the fields of that call are then undefined).  Ordering: a task's stores
+// are released at device scope before its problem's counter is incremented,
+// and a waiting workgroup acquires the counter at device scope before any of
+// its lanes reads the field (the L2 caches of the XCDs are not coherent with
+// each other without these fences).
+__device__ unsigned long long g_wait_timeouts;
+
+template <typename S>
+__device__ __forceinline__ void persist_pass_a(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
+  switch (d.ma) {
+    case 3: pass_a_body<S, 3, false, true>(d, tile, koff, smem); break;
+    case 5: pass_a_body<S, 5, false, true>(d, tile, koff, smem); break;
+    case 7: pass_a_body<S, 7, false, true>(d, tile, koff, smem); break;
+    case 9: pass_a_body<S, 9, false, true>(d, tile, koff, smem); break;
+    case 11: pass_a_body<S, 11, false, true>(d, tile, koff, smem); break;
+    case 13: pass_a_body<S, 13, false, true>(d, tile, koff, smem); break;
+    case 15: pass_a_body<S, 15, false, true>(d, tile, koff, smem); break;
+    default: pass_a_body<S, 17, false, true>(d, tile, koff, smem); break;
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void persist_pass_b(const ProbDesc& d, int tile, int koff, unsigned char* smem) {
+  switch (d.bcls) {
+    case 9: pass_b_body<S, 9, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 10: pass_b_body<S, 10, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 11: pass_b_body<S, 11, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 12: pass_b_body<S, 12, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 13: pass_b_body<S, 13, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 14: pass_b_body<S, 14, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 15: pass_b_body<S, 15, true, kPersistThreads>(d, tile, koff, smem); break;
+    case 16: pass_b_body<S, 16, true, kPersistThreads>(d, tile, koff, smem); break;
+    case kPcrClass: pass_b_pcr_body<S, kPersistThreads>(d, tile, koff, smem); break;
+    default: pass_b_body<S, 16, false, kPersistThreads>(d, tile, koff, smem); break;
+  }
+}
+
+// ctl[0]: next task of the list, ctl[1]: abort flag; done[p]: finished tasks
+// of problem p (all zero at launch).  wait_ticks: longest wait, in ticks of
+// the device's constant-rate clock.
+template <typename S>
+__global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 2 : 3)))
+void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__ tasks, int ntasks, int* ctl,
+                   int* done, long long wait_ticks) {
+  extern __shared__ __align__(16) unsigned char smem_p[];
+  __shared__ int s_task;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      int t = __hip_atomic_fetch_add(&ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t < ntasks) {
+        const int prob = tasks[t].prob, need = tasks[t].need;
+        int* const cnt = done + prob;
+        if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          const long long t0 = (long long)wall_clock64();
+          while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              t = ntasks;
+              break;
+            }
+            if ((long long)wall_clock64() - t0 > wait_ticks) {
+              __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              atomicAdd(&g_wait_timeouts, 1ull);
+              t = ntasks;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      s_task = t;
+    }
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_task);  // uniform: the task's data in scalar registers
+    if (t >= ntasks) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every lane reads after the wait
+    const PTask tk = tasks[t];
+    const ProbDesc d = descs[tk.prob];
+    if (tk.kind == 0) {
+      persist_pass_a<S>(d, tk.tile, tk.k, smem_p);
+    } else {
+      // nsub consecutive tiles (the last group may reach past the last tile)
+      const int ntile = d.bcls == kPcrClass ? d.ntile_b : (d.nz + (kPersistThreads / d.wb) - 1) / (kPersistThreads / d.wb);
+      for (int q = 0; q < tk.nsub && tk.tile + q < ntile; ++q) {
+        if (q) __syncthreads();  // the tile in LDS is free again
+        persist_pass_b<S>(d, tk.tile + q, tk.k, smem_p);
+      }
+    }
+    // every lane's stores complete and visible at device scope, then one
+    // lane publishes the task (LDS and s_task are free for the next task)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(done + tk.prob, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void fill_ints(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ============================================================== small kernels
@@ -1622,8 +1756,8 @@ hipError_t launch_pass_a(int prec, const ProbDesc* single, const ProbDesc* d_des
                    : run_a_batch<double>(d_descs, items, nitems, koff, lds, st);
 }
 
-int pass_b_lds(int prec, int W, int M) {
-  return W == 0 ? pass_b_pcr_lds_bytes() : pass_b_lds_bytes(prec ? 16 : 8, W, M);
+int pass_b_lds(int prec, int W, int M, int nthr) {
+  return W == 0 ? pass_b_pcr_lds_bytes() : pass_b_lds_bytes(prec ? 16 : 8, W, M, nthr);
 }
 
 // class: M in 9..16 for lines of exactly W*M azimuths, 0 for the general kernel
@@ -1649,6 +1783,60 @@ hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_des
   if (single) return prec == 0 ? run_b_cls<float>(*single, koff, lds, st) : run_b_cls<double>(*single, koff, lds, st);
   return prec == 0 ? run_b_batch<float>(d_descs, items, nitems, koff, lds, st)
                    : run_b_batch<double>(d_descs, items, nitems, koff, lds, st);
+}
+
+template <typename S>
+static hipError_t run_persist(const ProbDesc* d_descs, const PTask* tasks, int ntasks, int* ctl_done, int nprob,
+                              long long wait_ticks, int lds, hipStream_t st) {
+  constexpr int esz = int(sizeof(C<S>));
+  constexpr int la = pass_a_lds_bytes(esz, 4, 3 * 17 - 1, 17);
+  constexpr int lb = pass_b_lds_bytes(esz, 64, 16, kPersistThreads);
+  constexpr int lc = pass_b_pcr_lds_bytes();
+  constexpr int lds_max = la > lb ? (la > lc ? la : lc) : (lb > lc ? lb : lc);
+  if (lds > lds_max || ntasks < 1 || nprob < 1) return hipErrorInvalidValue;
+  const void* fn = reinterpret_cast<const void*>(&march_persist<S>);
+  hipError_t e = allow_lds(fn, lds_max);
+  if (e != hipSuccess) return e;
+  // resident workgroups of this LDS size, looked up once per (device, lds)
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, int> cap;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  int grid = 0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cap.find({dev, lds});
+    if (it != cap.end()) {
+      grid = it->second;
+    } else {
+      int per_cu = 0, ncu = 0;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistThreads, lds)) != hipSuccess) return e;
+      if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+      grid = std::max(1, per_cu) * std::max(1, ncu);
+      cap[{dev, lds}] = grid;
+    }
+  }
+  grid = std::min(grid, ntasks);
+  const int nfill = 2 + nprob;
+  hipLaunchKernelGGL(fill_ints, dim3((nfill + 255) / 256), dim3(256), 0, st, ctl_done, nfill, 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((march_persist<S>), dim3(grid), dim3(kPersistThreads), lds, st, d_descs, tasks, ntasks,
+                     ctl_done, ctl_done + 2, wait_ticks);
+  return hipGetLastError();
+}
+
+hipError_t launch_persist(int prec, const ProbDesc* d_descs, const PTask* tasks, int ntasks, int* ctl_done,
+                          int nprob, long long wait_ticks, int lds, hipStream_t st) {
+  return prec == 0 ? run_persist<float>(d_descs, tasks, ntasks, ctl_done, nprob, wait_ticks, lds, st)
+                   : run_persist<double>(d_descs, tasks, ntasks, ctl_done, nprob, wait_ticks, lds, st);
+}
+
+hipError_t persist_take_timeouts(unsigned long long* n) {
+  unsigned long long v = 0, z = 0;
+  hipError_t e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_wait_timeouts), sizeof v, 0, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && v) e = hipMemcpyToSymbol(HIP_SYMBOL(g_wait_timeouts), &z, sizeof z, 0, hipMemcpyHostToDevice);
+  *n = v;
+  return e;
 }
 
 hipError_t launch_medium_update(const ProbDesc* single, const ProbDesc* d_descs, const WorkItem* items,

@@ -45,11 +45,14 @@ PE3D_MODE_NX2D = 1
 PE3D_STATIC_SCRATCH_BYTES = 32 << 20
 PE3D_AZIMUTH_CHUNKED = 0
 PE3D_AZIMUTH_PCR = 1
+PE3D_BATCH_LAUNCHES = 0
+PE3D_BATCH_PERSISTENT = 1
 
 EXPORTED = ("pe3d_create", "pe3d_march", "pe3d_destroy", "pe3d_footprint", "pe3d_get_step",
             "pe3d_set_step", "pe3d_starter", "pe3d_march_batch", "pe3d_tl", "pe3d_pressure", "pe3d_get_info",
             "pe3d_host_tables", "pe3d_profile_enable", "pe3d_profile_read", "pe3d_strerror",
-            "pe3d_set_batch_schedule", "pe3d_march_static", "pe3d_release_pooled_memory")
+            "pe3d_set_batch_schedule", "pe3d_march_static", "pe3d_release_pooled_memory",
+            "pe3d_set_batch_kernel", "pe3d_batch_wait_timeouts", "pe3d_persist_schedule")
 
 
 class pe3d_env(ct.Structure):
@@ -113,6 +116,11 @@ _lib.pe3d_profile_read.argtypes = [ct.POINTER(pe3d_kernel_stat), ct.c_int32, ct.
 _lib.pe3d_strerror.argtypes = [ct.c_int]
 _lib.pe3d_set_batch_schedule.argtypes = [ct.c_int32, ct.c_int64]
 _lib.pe3d_release_pooled_memory.argtypes = [ct.POINTER(ct.c_size_t)]
+_lib.pe3d_set_batch_kernel.argtypes = [ct.c_int32, ct.c_double]
+_lib.pe3d_batch_wait_timeouts.argtypes = [ct.POINTER(ct.c_int64)]
+_I32P = ct.POINTER(ct.c_int32)
+_lib.pe3d_persist_schedule.argtypes = [ct.c_int32, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P,
+                                       ct.c_int64, ct.POINTER(ct.c_int64)]
 for _n in EXPORTED:
     getattr(_lib, _n).restype = ct.c_int
 _lib.pe3d_strerror.restype = ct.c_char_p
@@ -297,6 +305,30 @@ def pe3d_set_batch_schedule(chains: int, group_bytes: int) -> None:
     _check(_lib.pe3d_set_batch_schedule(int(chains), int(group_bytes)), "pe3d_set_batch_schedule")
 
 
+def pe3d_set_batch_kernel(kind: int, wait_limit_s: float = 1.0) -> None:
+    _check(_lib.pe3d_set_batch_kernel(int(kind), float(wait_limit_s)), "pe3d_set_batch_kernel")
+
+
+def pe3d_batch_wait_timeouts() -> int:
+    """Waits of persistent batched marches that ran out since the last call
+    (synchronous; call after synchronising the marches' streams)."""
+    n = ct.c_int64(0)
+    _check(_lib.pe3d_batch_wait_timeouts(ct.byref(n)), "pe3d_batch_wait_timeouts")
+    return int(n.value)
+
+
+def pe3d_persist_schedule(na, nb, nsub, nsteps, chain, group):
+    """The persistent kernel's task list for problems of these shapes (host
+    only): a list of (problem, first tile, step, kind, tiles, need)."""
+    n = len(na)
+    arrs = [(ct.c_int32 * n)(*[int(x) for x in a]) for a in (na, nb, nsub, nsteps, chain, group)]
+    cnt = ct.c_int64(0)
+    _check(_lib.pe3d_persist_schedule(n, *arrs, None, 0, ct.byref(cnt)), "pe3d_persist_schedule")
+    out = (ct.c_int32 * (6 * max(cnt.value, 1)))()
+    _check(_lib.pe3d_persist_schedule(n, *arrs, out, cnt.value, ct.byref(cnt)), "pe3d_persist_schedule")
+    return [tuple(out[6 * t:6 * t + 6]) for t in range(cnt.value)]
+
+
 def pe3d_release_pooled_memory() -> int:
     """Return the library's idle pooled device memory to the runtime; bytes freed."""
     n = ct.c_size_t(0)
@@ -415,6 +447,14 @@ def set_batch_schedule(chains: int = 2, group_bytes: int = 112 << 20) -> None:
     marched through all of its steps before the next (0: one group per
     chain).  The defaults are the library's."""
     pe3d_set_batch_schedule(chains, group_bytes)
+
+
+def set_batch_kernel(kind: int = PE3D_BATCH_LAUNCHES, wait_limit_s: float = 1.0) -> None:
+    """Kernel of later batched plans: PE3D_BATCH_LAUNCHES (one launch per
+    pass per step per group, the library's default) or PE3D_BATCH_PERSISTENT
+    (one persistent kernel per call; each of its waits bounded by
+    wait_limit_s)."""
+    pe3d_set_batch_kernel(kind, wait_limit_s)
 
 
 def prepare_batch(marches: Sequence[Pe3d], nsteps, fields, stream=None) -> None:
