@@ -10,8 +10,10 @@ every problem: pass A + pass B over the whole batch.
 
 Printed (one JSON line): throughput in grid-point * range-steps / s; the
 dominant kernel's achieved HBM bandwidth from HIP events (algorithmic bytes =
-the field read once and written once per pass); the plain per-frequency march
-(one problem at a time, per-step launches) on the same batch and the ratio;
+the field read once and written once per pass); the same calls with the
+other batch kernel (one persistent kernel per call, or the launches); the
+plain per-frequency march (one problem at a time, per-step launches) on the
+same batch and the ratio;
 a parity sample against the complex128 oracle; the oracle's own CPU
 throughput on a bounded sample.
 """
@@ -51,6 +53,11 @@ def parse():
                     help="batch schedule: independent chains replayed on concurrent streams")
     ap.add_argument("--group-mib", type=int, default=112,
                     help="batch schedule: field MiB of one group, marched through a whole call in turn (0: one group)")
+    ap.add_argument("--batch-kernel", choices=["launches", "persistent"], default="launches",
+                    help="batched march: one launch per pass per step per group, or one persistent "
+                         "kernel per call")
+    ap.add_argument("--no-persist-report", action="store_true",
+                    help="do not also time the other batch kernel on the same batch (same calls)")
     ap.add_argument("--workload", choices=["config4", "config2"], default="config4")
     ap.add_argument("--nfreq", type=int, default=64)
     ap.add_argument("--precision", choices=["c64", "c128"], default="c64",
@@ -83,6 +90,8 @@ def parse():
                     help="range steps per served iteration while requests wait for admission")
     ap.add_argument("--serve-graph", action="store_true",
                     help="replay every served iteration as a captured HIP graph")
+    ap.add_argument("--serve-batch-kernel", choices=["launches", "persistent"], default=None,
+                    help="batch kernel of the served stream (default: --batch-kernel)")
     ap.add_argument("--serve-budget-gib", type=float, default=1.0,
                     help="HBM admission budget of the served stream (fields + tables of resident requests)")
     return ap.parse_args()
@@ -228,6 +237,8 @@ def main():
     torch.cuda.synchronize()
     use_graph = not args.no_graph
     P.set_batch_schedule(args.chains, args.group_mib << 20)
+    kinds = {"launches": P.PE3D_BATCH_LAUNCHES, "persistent": P.PE3D_BATCH_PERSISTENT}
+    P.set_batch_kernel(kinds[args.batch_kernel])
 
     # ---- warmup; the graphs of the call sizes of the timed region are
     #      captured (not run) beforehand, so no capture falls inside it
@@ -299,9 +310,33 @@ def main():
            "storage": "complex128" if args.precision == "c128" else "complex64", "data": "synthetic",
            "config": {"workload": workload, "problems": len(probs), "grid_points": npts,
                       "graph": use_graph, "chunk_steps": args.chunk, "chains": args.chains,
-                      "group_mib": args.group_mib, "tuned_lanes": tuned,
+                      "group_mib": args.group_mib, "batch_kernel": args.batch_kernel, "tuned_lanes": tuned,
                       "azimuth_solver_variants": variants},
            "roofline": roofline}
+
+    # ---- the other batch kernel on the same batch, same calls
+    if not args.no_persist_report:
+        other = "persistent" if args.batch_kernel == "launches" else "launches"
+        log(f"batch kernel {other}")
+        P.set_batch_kernel(kinds[other])
+        if use_graph:
+            for k in {min(args.chunk, args.steps), args.steps % args.chunk}:
+                if k:
+                    P.prepare_batch(ms, k, us)
+        march_steps(P, ms, us, args.chunk, args.chunk, use_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        march_steps(P, ms, us, args.steps, args.chunk, use_graph)
+        ev1.record()
+        torch.cuda.synchronize()
+        el = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+        ov = npts * args.steps / el
+        out["batch_kernels"] = {args.batch_kernel: dict(value=value, ms_per_step=1e3 * elapsed / args.steps),
+                                other: dict(value=ov, ms_per_step=1e3 * el / args.steps),
+                                "wait_timeouts": P.pe3d_batch_wait_timeouts()}
+        log(f"{other}: {ov:.4e} pt*steps/s, {1e3 * el / args.steps:.3f} ms/step")
+        P.set_batch_kernel(kinds[args.batch_kernel])
 
     # ---- plain per-frequency march on the same batch
     if not args.no_plain and len(probs) > 1:
@@ -349,14 +384,17 @@ def main():
                                                       r.problem.name)) for r in tr]
         log(f"serve: {len(tr)} requests")
         budget = int(args.serve_budget_gib * (1 << 30))
+        skind = args.serve_batch_kernel or args.batch_kernel
+        P.set_batch_kernel(kinds[skind])
         sch = Scheduler(Pe3dBackend(use_graph=args.serve_graph), budget, args.serve_chunk,
                         backlog_chunk_steps=args.serve_backlog_chunk)
         t0 = time.perf_counter()
         recs = sch.run(tr)
         rep = report(recs, time.perf_counter() - t0)
+        rep["wait_timeouts"] = P.pe3d_batch_wait_timeouts()
         rep.update(rate_hz=200.0, budget_bytes=budget, chunk_steps=args.serve_chunk,
                    backlog_chunk_steps=sch.Kb, backlog_iterations=sch.backlog_iterations,
-                   graph=args.serve_graph, max_resident=sch.max_resident,
+                   graph=args.serve_graph, batch_kernel=skind, max_resident=sch.max_resident,
                    range_scale=args.serve_range_scale,
                    trace="config5 seed 0: f~U(20,400) Hz, zs~U(10,500) m, width in {30,90,360} deg, "
                          "range~U(2,20) km scaled by range_scale, Nz=clamp(ceil64(6.4 f),128,4096), "

@@ -298,12 +298,9 @@ pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes);
  *     runs out the call's workgroups leave early, the call's fields and step
  *     counters are then undefined, and pe3d_batch_wait_timeouts reports it.
  *     A call whose problems include range rows (depth or water) uses the
- *     launches.  Results are meant to be bitwise identical to the launches.
- *     SWITCHED OFF: the first run of this kernel on the device made no
- *     progress for minutes and no cause has been found in the code, so
- *     asking for it returns PE3D_EUNSUPPORTED and the launches stay in use.
+ *     launches.  Results are bitwise identical to the launches.
  * Errors: PE3D_EINVAL (unknown kind, wait_limit_s negative, not finite or
- * above 3600), PE3D_EUNSUPPORTED (PE3D_BATCH_PERSISTENT, switched off). */
+ * above 3600). */
 #define PE3D_BATCH_LAUNCHES 0
 #define PE3D_BATCH_PERSISTENT 1
 pe3d_status pe3d_set_batch_kernel(int32_t kind, double wait_limit_s);
@@ -315,16 +312,17 @@ pe3d_status pe3d_set_batch_kernel(int32_t kind, double wait_limit_s);
 pe3d_status pe3d_batch_wait_timeouts(int64_t* count);
 
 /* Host only, for tests of the persistent kernel's task list: the list the
- * library builds for n problems with na[i] depth-pass tiles, nb[i]
- * azimuth-pass tiles (0: no azimuth pass) taken nsub[i] at a time, nsteps[i]
- * steps, in group group[i] of chain chain[i] (groups numbered from 0 within
- * each chain, problems listed in their group's order).  Writes up to `cap`
- * tasks as 6 int32 each (problem, first tile, step, kind 0 depth / 1
- * azimuth, tiles of the task, finished tasks of the problem it waits for)
- * and sets *ntasks to the list's length.  Errors: PE3D_EINVAL. */
-pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* nb, const int32_t* nsub,
-                                  const int32_t* nsteps, const int32_t* chain, const int32_t* group,
-                                  int32_t* tasks, int64_t cap, int64_t* ntasks);
+ * library builds for n problems with na[i] depth-pass tiles taken asub[i] at
+ * a time and nb[i] azimuth-pass tiles (0: no azimuth pass) taken bsub[i] at
+ * a time (1..16), nsteps[i] steps, in group group[i] of chain chain[i]
+ * (groups numbered from 0 within each chain, problems listed in their
+ * group's order).  Writes up to `cap` tasks as 6 int32 each (problem, first
+ * tile, step, kind 0 depth / 1 azimuth, tiles of the task, finished tasks of
+ * the problem it waits for) and sets *ntasks to the list's length.
+ * Errors: PE3D_EINVAL. */
+pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* asub, const int32_t* nb,
+                                  const int32_t* bsub, const int32_t* nsteps, const int32_t* chain,
+                                  const int32_t* group, int32_t* tasks, int64_t cap, int64_t* ntasks);
 
 /* Transmission loss of a field at the handle's current step (Sec. 4.1,
  * Fig. 5): tl[m*nz + l] = -20 log10 |u| + 10 log10 r_j, in FP32, written to a

@@ -697,7 +697,8 @@ struct BatchPlan {
   // device blocks of destroyed handles this plan used: released with it
   std::vector<std::shared_ptr<HandleBlocks>> keep;
   // persistent kernel (pe3d_set_batch_kernel): its task list, the launch's
-  // control words and per-problem counters (2 + n ints, zeroed by the launch)
+  // control words and per-problem counters (persist_ctl_ints(n) ints, zeroed
+  // by the launch)
   bool persist = false;
   PTask* d_tasks = nullptr;
   int ntasks = 0;
@@ -1280,18 +1281,18 @@ std::vector<std::vector<std::vector<int>>> batch_partition(const pe3d_handle* hs
   return out;
 }
 
-// The persistent kernel's task list.  Problem p has na depth-pass tiles and
-// nb azimuth-pass tiles (0: none), taken nsub at a time; its tasks of one
-// step are the depth pass's na then the azimuth pass's ceil(nb / nsub), and
-// a task waits for every task of the problem's earlier passes.  Per chain,
-// the phases (one pass of one step of one group, over the group's problems
-// still stepping) follow each group through its steps, groups in order; the
-// chains' phases are interleaved, phase i of every chain before phase i + 1
-// of any, so that the wait of a phase for the previous phase of its group
-// is covered by the other chains' work.  Every task's waits are on tasks
-// earlier in the list.
+// The persistent kernel's task list.  Problem p has na depth-pass tiles
+// taken asub at a time and nb azimuth-pass tiles (0: none) taken bsub at a
+// time; its tasks of one step are the depth pass's ceil(na / asub) then the
+// azimuth pass's ceil(nb / bsub), and a task waits for every task of the
+// problem's earlier passes.  Per chain, the phases (one pass of one step of
+// one group, over the group's problems still stepping) follow each group
+// through its steps, groups in order; the chains' phases are interleaved,
+// phase i of every chain before phase i + 1 of any, so that the wait of a
+// phase for the previous phase of its group is covered by the other chains'
+// work.  Every task's waits are on tasks earlier in the list.
 struct PersistProb {
-  int na, nb, nsub, nsteps;
+  int na, asub, nb, bsub, nsteps;
 };
 void persist_tasks(const std::vector<std::vector<std::vector<int>>>& chains, const std::vector<PersistProb>& pp,
                    std::vector<PTask>& out) {
@@ -1323,32 +1324,45 @@ void persist_tasks(const std::vector<std::vector<std::vector<int>>>& chains, con
       for (int p : chains[c][f.g]) {
         const PersistProb& q = pp[p];
         if (q.nsteps <= f.k) continue;
-        const int nbt = q.nb > 0 ? (q.nb + q.nsub - 1) / q.nsub : 0;
-        const int per_step = q.na + nbt;
+        const int nat = (q.na + q.asub - 1) / q.asub;
+        const int nbt = q.nb > 0 ? (q.nb + q.bsub - 1) / q.bsub : 0;
+        const int per_step = nat + nbt;
         if (f.kind == 0) {
-          for (int t = 0; t < q.na; ++t) out.push_back({p, t, f.k, f.k * per_step, 0, 1});
+          for (int t = 0; t < nat; ++t) out.push_back({p, t * q.asub, f.k, f.k * per_step, 0, short(q.asub)});
         } else {
           for (int t = 0; t < nbt; ++t)
-            out.push_back({p, t * q.nsub, f.k, f.k * per_step + q.na, 1, short(q.nsub)});
+            out.push_back({p, t * q.bsub, f.k, f.k * per_step + nat, 1, short(q.bsub)});
         }
       }
     }
 }
 
-// Azimuth-pass tiles of the persistent kernel (256 lanes) and how many one
-// task takes: consecutive tiles until a depth line's segment fills a
-// 128-byte cache line, so that one workgroup reads whole lines.
-void persist_b_shape(const pe3d_handle h, int& nb, int& nsub) {
+// Tiles of the persistent kernel's tasks.  The depth pass's tiles are the
+// launches' (256 / L columns each); the azimuth pass's hold 256 lanes.  A
+// task takes consecutive tiles until it covers kPersistTaskPoints grid
+// points (at most kPersistMaxSub tiles), and an azimuth task at least enough
+// tiles to fill a 128-byte line of each depth line it touches: each task ends
+// with one device-scope release (a write-back of the XCD's L2), the kernel's
+// main overhead, so tasks must not be small.
+constexpr int kPersistTaskPoints = 16384;
+constexpr int kPersistMaxSub = 16;
+void persist_shape(const pe3d_handle h, PersistProb& q) {
   const ProbDesc& d = h->desc;
   const int esz = h->prec ? 16 : 8;
+  auto sub_for = [](int pts_per_tile, int at_least) {
+    int s = std::max(at_least, (kPersistTaskPoints + pts_per_tile - 1) / std::max(1, pts_per_tile));
+    return std::max(1, std::min(kPersistMaxSub, s));
+  };
+  q.na = d.ntile_a;
+  q.asub = sub_for((256 / d.lpc) * d.nz, 1);
   if (d.nx2d) {
-    nb = 0;
-    nsub = 1;
+    q.nb = 0;
+    q.bsub = 1;
     return;
   }
   const int td = d.bcls == kPcrClass ? d.td : kPersistThreads / d.wb;
-  nb = d.bcls == kPcrClass ? d.ntile_b : (d.nz + td - 1) / td;
-  nsub = std::max(1, std::min(8, 128 / (td * esz)));
+  q.nb = d.bcls == kPcrClass ? d.ntile_b : (d.nz + td - 1) / td;
+  q.bsub = sub_for(td * d.nth, 128 / (td * esz));
 }
 
 pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
@@ -1457,8 +1471,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
     std::vector<PersistProb> pp(np);
     for (int p = 0; p < np; ++p) {
       pe3d_handle h = hs[order[p]];
-      pp[p].na = h->desc.ntile_a;
-      persist_b_shape(h, pp[p].nb, pp[p].nsub);
+      persist_shape(h, pp[p]);
       pp[p].nsteps = nsteps[order[p]];
       const double esz = h->prec ? 16.0 : 8.0;
       const double pts = double(h->desc.nz) * h->desc.nth;
@@ -1485,7 +1498,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   size_t off_it = (off_add + np * sizeof(int) + 255) & ~size_t(255);
   size_t off_tk = (off_it + nitems * sizeof(WorkItem) + 255) & ~size_t(255);
   size_t off_ctl = (off_tk + tasks.size() * sizeof(PTask) + 255) & ~size_t(255);
-  size_t total = off_ctl + (persist ? (2 + np) * sizeof(int) : 0) + 256;
+  size_t total = off_ctl + (persist ? persist_ctl_ints(np) * sizeof(int) : 0) + 256;
   std::vector<unsigned char> img(total, 0);
   if (persist) std::memcpy(img.data() + off_tk, tasks.data(), tasks.size() * sizeof(PTask));
   std::memcpy(img.data() + off_desc, descs.data(), np * sizeof(ProbDesc));
@@ -1708,15 +1721,9 @@ extern "C" pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_byt
   return PE3D_OK;
 }
 
-// The persistent kernel is switched off: its first run on the device made
-// no progress for minutes, with no cause found in the code; requests for it
-// are refused until one is.
-constexpr bool kPersistEnabled = false;
-
 extern "C" pe3d_status pe3d_set_batch_kernel(int32_t kind, double wait_limit_s) {
   if (kind != PE3D_BATCH_LAUNCHES && kind != PE3D_BATCH_PERSISTENT) return PE3D_EINVAL;
   if (!(wait_limit_s >= 0.0 && wait_limit_s <= 3600.0)) return PE3D_EINVAL;  // NaN fails too
-  if (kind == PE3D_BATCH_PERSISTENT && !kPersistEnabled) return PE3D_EUNSUPPORTED;
   g_batch_kernel.store(kind);
   g_wait_limit_s.store(wait_limit_s);
   return PE3D_OK;
@@ -1730,18 +1737,20 @@ extern "C" pe3d_status pe3d_batch_wait_timeouts(int64_t* count) {
   return PE3D_OK;
 }
 
-extern "C" pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* nb, const int32_t* nsub,
-                                             const int32_t* nsteps, const int32_t* chain, const int32_t* group,
-                                             int32_t* tasks, int64_t cap, int64_t* ntasks) {
-  if (n < 1 || !na || !nb || !nsub || !nsteps || !chain || !group || !ntasks || cap < 0 || (cap > 0 && !tasks))
+extern "C" pe3d_status pe3d_persist_schedule(int32_t n, const int32_t* na, const int32_t* asub, const int32_t* nb,
+                                             const int32_t* bsub, const int32_t* nsteps, const int32_t* chain,
+                                             const int32_t* group, int32_t* tasks, int64_t cap, int64_t* ntasks) {
+  if (n < 1 || !na || !asub || !nb || !bsub || !nsteps || !chain || !group || !ntasks || cap < 0 ||
+      (cap > 0 && !tasks))
     return PE3D_EINVAL;
   std::vector<std::vector<std::vector<int>>> chains;
   std::vector<PersistProb> pp(n);
   for (int i = 0; i < n; ++i) {
-    if (na[i] < 1 || nb[i] < 0 || nsub[i] < 1 || nsub[i] > 8 || nsteps[i] < 0 || chain[i] < 0 ||
-        chain[i] > 1024 || group[i] < 0 || group[i] > 1 << 20)
+    if (na[i] < 1 || asub[i] < 1 || asub[i] > kPersistMaxSub || nb[i] < 0 || bsub[i] < 1 ||
+        bsub[i] > kPersistMaxSub || nsteps[i] < 0 || chain[i] < 0 || chain[i] > 1024 || group[i] < 0 ||
+        group[i] > 1 << 20)
       return PE3D_EINVAL;
-    pp[i] = {na[i], nb[i], nsub[i], nsteps[i]};
+    pp[i] = {na[i], asub[i], nb[i], bsub[i], nsteps[i]};
     if (int(chains.size()) <= chain[i]) chains.resize(chain[i] + 1);
     auto& c = chains[chain[i]];
     if (int(c.size()) <= group[i]) c.resize(group[i] + 1);

@@ -92,10 +92,10 @@ struct WorkItem {
 constexpr int kPassBThreads = 512;
 
 // Persistent batched march (march_persist): workgroup lanes, and one task of
-// its list (see pe3d_kernels.hip).  kind 0: depth-pass tile `tile` of problem
-// `prob` at step k of the call; kind 1: azimuth-pass tiles tile .. tile+nsub-1
-// (tiles of kPersistThreads lanes).  need: finished tasks of the problem
-// before this one may start.
+// its list (see pe3d_kernels.hip).  kind 0: depth-pass tiles tile ..
+// tile+nsub-1 of problem `prob` at step k of the call; kind 1: azimuth-pass
+// tiles tile .. tile+nsub-1 (tiles of kPersistThreads lanes).  need:
+// finished tasks of the problem before this one may start.
 constexpr int kPersistThreads = 256;
 struct PTask {
   int prob;
@@ -147,7 +147,11 @@ hipError_t launch_pass_b(int prec, const ProbDesc* single, const ProbDesc* d_des
                          int nitems, int koff, int lds, hipStream_t st);
 // dynamic LDS bytes of one pass B workgroup of nthr lanes (W = 0: cyclic reduction)
 int pass_b_lds(int prec, int W, int M, int nthr = kPassBThreads);
-// The persistent batched march: ctl_done (2 + nprob ints) zeroed, then
+// Control words and per-problem counters of the persistent march: one
+// 128-byte line each (the waiting workgroups poll them).
+constexpr int kPersistCounterStride = 32;
+inline int persist_ctl_ints(int nprob) { return (2 + nprob) * kPersistCounterStride; }
+// The persistent batched march: ctl_done (persist_ctl_ints ints) zeroed, then
 // march_persist over the task list with as many workgroups as fit on the
 // device (at most ntasks).  lds: the largest dynamic LDS of the tasks' passes.
 hipError_t launch_persist(int prec, const ProbDesc* d_descs, const PTask* tasks, int ntasks, int* ctl_done,

@@ -1436,9 +1436,9 @@ __global__ __launch_bounds__(kPassBThreads) void pass_b_pcr_single(ProbDesc d, i
 // One launch runs every step of a batched march (the paper's loop over
 // frequencies, each marched through its range steps, carried onto one
 // device): the workgroups, as many as fit on the device at once, take tasks
-// from a list in list order, one atomic increment per task.  A task is one
-// depth-pass tile (a span of columns) or one azimuth-pass tile group (nsub
-// consecutive tiles of 256 lanes) of one problem at one step.  A problem's
+// from a list in list order, one atomic increment per task.  A task is nsub
+// consecutive depth-pass tiles (spans of columns) or azimuth-pass tiles (of
+// 256 lanes) of one problem at one step.  A problem's
 // tasks enter the list step by step, the depth pass before the azimuth pass,
 // and each task carries the number of the problem's tasks that must have
 // finished before it may start: every task of the step's depth pass (for the
@@ -1486,63 +1486,85 @@ __device__ __forceinline__ void persist_pass_b(const ProbDesc& d, int tile, int 
   }
 }
 
-// ctl[0]: next task of the list, ctl[1]: abort flag; done[p]: finished tasks
-// of problem p (all zero at launch).  wait_ticks: longest wait, in ticks of
-// the device's constant-rate clock.
+// ctl[0]: next task of the list, ctl[S]: abort flag; done[S p]: finished
+// tasks of problem p (S = kPersistCounterStride: each word on a cache line of
+// its own; all zero at launch).  wait_ticks: longest wait, in ticks of the
+// device's constant-rate clock.
+// Every branch around the barriers is uniform per wavefront (a scalar
+// condition): the first wavefront takes and waits for the task with all of
+// its lanes (lane 0 adds 1, the others add 0; the values it waits on are
+// made scalar), and the other wavefronts wait at the barrier.  With a branch
+// on a per-lane condition (thread 0 alone) the compiler may turn the loop
+// into one in which the wavefront's other lanes go round the barrier and
+// re-read the task index before lane 0 has taken the next task.
 template <typename S>
 __global__ __launch_bounds__(kPersistThreads) __attribute__((amdgpu_waves_per_eu(sizeof(S) == 8 ? 2 : 3)))
 void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__ tasks, int ntasks, int* ctl,
                    int* done, long long wait_ticks) {
   extern __shared__ __align__(16) unsigned char smem_p[];
   __shared__ int s_task;
-  const int tid = threadIdx.x;
+  const bool first_wave = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // uniform per wavefront
+  const int one = (threadIdx.x & 63) == 0 ? 1 : 0;                           // lane 0 of the wavefront
   for (;;) {
-    if (tid == 0) {
-      int t = __hip_atomic_fetch_add(&ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (first_wave) {
+      int t = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_fetch_add(&ctl[0], one, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (t < ntasks) {
         const int prob = tasks[t].prob, need = tasks[t].need;
-        int* const cnt = done + prob;
-        if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        int* const cnt = done + prob * kPersistCounterStride;
+        auto count = [&] {
+          return __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        };
+        if (count() < need) {
           const long long t0 = (long long)wall_clock64();
-          while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          while (count() < need) {
+            if (__builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&ctl[kPersistCounterStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0) {
               t = ntasks;
               break;
             }
             if ((long long)wall_clock64() - t0 > wait_ticks) {
-              __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              atomicAdd(&g_wait_timeouts, 1ull);
+              __hip_atomic_store(&ctl[kPersistCounterStride], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              atomicAdd(&g_wait_timeouts, (unsigned long long)one);
               t = ntasks;
               break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(4);
           }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      s_task = t;
+      s_task = t;  // every lane writes the same value
     }
+    // (the first wavefront's acquire covers the CU: its caches are shared by
+    // the workgroup's wavefronts, which read only after this barrier)
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_task);  // uniform: the task's data in scalar registers
     if (t >= ntasks) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every lane reads after the wait
     const PTask tk = tasks[t];
     const ProbDesc d = descs[tk.prob];
+    // nsub consecutive tiles (the last task of a pass may reach past the
+    // last tile)
     if (tk.kind == 0) {
-      persist_pass_a<S>(d, tk.tile, tk.k, smem_p);
+      for (int q = 0; q < tk.nsub && tk.tile + q < d.ntile_a; ++q) {
+        if (q) __syncthreads();  // the columns in LDS are free again
+        persist_pass_a<S>(d, tk.tile + q, tk.k, smem_p);
+      }
     } else {
-      // nsub consecutive tiles (the last group may reach past the last tile)
       const int ntile = d.bcls == kPcrClass ? d.ntile_b : (d.nz + (kPersistThreads / d.wb) - 1) / (kPersistThreads / d.wb);
       for (int q = 0; q < tk.nsub && tk.tile + q < ntile; ++q) {
         if (q) __syncthreads();  // the tile in LDS is free again
         persist_pass_b<S>(d, tk.tile + q, tk.k, smem_p);
       }
     }
-    // every lane's stores complete and visible at device scope, then one
-    // lane publishes the task (LDS and s_task are free for the next task)
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wavefront waits for its stores to complete, then the first
+    // wavefront publishes the task with one device-scope release (one write
+    // back of the XCD's L2 per task: such fences are the kernel's main
+    // overhead); LDS and s_task are then free for the next task
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(done + tk.prob, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (first_wave)
+      __hip_atomic_fetch_add(done + tk.prob * kPersistCounterStride, one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1817,11 +1839,11 @@ static hipError_t run_persist(const ProbDesc* d_descs, const PTask* tasks, int n
     }
   }
   grid = std::min(grid, ntasks);
-  const int nfill = 2 + nprob;
+  const int nfill = persist_ctl_ints(nprob);
   hipLaunchKernelGGL(fill_ints, dim3((nfill + 255) / 256), dim3(256), 0, st, ctl_done, nfill, 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL((march_persist<S>), dim3(grid), dim3(kPersistThreads), lds, st, d_descs, tasks, ntasks,
-                     ctl_done, ctl_done + 2, wait_ticks);
+                     ctl_done, ctl_done + 2 * kPersistCounterStride, wait_ticks);
   return hipGetLastError();
 }
 

@@ -119,7 +119,7 @@ _lib.pe3d_release_pooled_memory.argtypes = [ct.POINTER(ct.c_size_t)]
 _lib.pe3d_set_batch_kernel.argtypes = [ct.c_int32, ct.c_double]
 _lib.pe3d_batch_wait_timeouts.argtypes = [ct.POINTER(ct.c_int64)]
 _I32P = ct.POINTER(ct.c_int32)
-_lib.pe3d_persist_schedule.argtypes = [ct.c_int32, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P,
+_lib.pe3d_persist_schedule.argtypes = [ct.c_int32, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P, _I32P,
                                        ct.c_int64, ct.POINTER(ct.c_int64)]
 for _n in EXPORTED:
     getattr(_lib, _n).restype = ct.c_int
@@ -317,11 +317,11 @@ def pe3d_batch_wait_timeouts() -> int:
     return int(n.value)
 
 
-def pe3d_persist_schedule(na, nb, nsub, nsteps, chain, group):
+def pe3d_persist_schedule(na, asub, nb, bsub, nsteps, chain, group):
     """The persistent kernel's task list for problems of these shapes (host
     only): a list of (problem, first tile, step, kind, tiles, need)."""
     n = len(na)
-    arrs = [(ct.c_int32 * n)(*[int(x) for x in a]) for a in (na, nb, nsub, nsteps, chain, group)]
+    arrs = [(ct.c_int32 * n)(*[int(x) for x in a]) for a in (na, asub, nb, bsub, nsteps, chain, group)]
     cnt = ct.c_int64(0)
     _check(_lib.pe3d_persist_schedule(n, *arrs, None, 0, ct.byref(cnt)), "pe3d_persist_schedule")
     out = (ct.c_int32 * (6 * max(cnt.value, 1)))()

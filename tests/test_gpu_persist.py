@@ -14,13 +14,7 @@ import pytest
 import oracle as O
 import workloads as W
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="the persistent batched kernel is switched off: its first GPU run "
-                            "(test_persistent_equals_launches, complex64, direct, one chain) made no "
-                            "progress for three minutes and was killed; no cause found by reading the "
-                            "kernel, the task-list protocol or the plan, so the case stays off the GPU"),
-]
+pytestmark = pytest.mark.gpu
 
 
 def say(*a):

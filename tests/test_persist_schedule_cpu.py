@@ -61,7 +61,8 @@ def simulate(tasks, nprob, workers, durations):
 def shapes(seed):
     rng = random.Random(seed)
     n = rng.randint(1, 9)
-    na = [rng.randint(1, 7) for _ in range(n)]
+    na = [rng.randint(1, 9) for _ in range(n)]
+    asub = [rng.randint(1, 4) for _ in range(n)]
     nb = [rng.choice([0, rng.randint(1, 9)]) for _ in range(n)]
     nsub = [rng.randint(1, 4) for _ in range(n)]
     steps = [rng.randint(0, 5) for _ in range(n)]
@@ -77,20 +78,20 @@ def shapes(seed):
         for i in range(n):
             if chain[i] == c:
                 group[i] = ren[group[i]]
-    return na, nb, nsub, steps, chain, group
+    return na, asub, nb, nsub, steps, chain, group
 
 
 @pytest.mark.parametrize("seed", range(40))
 def test_task_list_covers_every_tile_once_and_waits_for_earlier_passes(P, seed):
-    na, nb, nsub, steps, chain, group = shapes(seed)
-    tasks = P.pe3d_persist_schedule(na, nb, nsub, steps, chain, group)
+    na, asub, nb, nsub, steps, chain, group = shapes(seed)
+    tasks = P.pe3d_persist_schedule(na, asub, nb, nsub, steps, chain, group)
     n = len(na)
     seen = {}
     for pos, (p, tile, k, kind, sub, need) in enumerate(tasks):
         assert 0 <= p < n and 0 <= k < steps[p]
         if kind == 0:
-            assert sub == 1 and 0 <= tile < na[p]
-            key = [(p, k, 0, tile)]
+            assert sub == asub[p] and tile % asub[p] == 0 and 0 <= tile < na[p]
+            key = [(p, k, 0, t) for t in range(tile, min(tile + sub, na[p]))]
         else:
             assert kind == 1 and nb[p] > 0 and sub == nsub[p]
             assert tile % nsub[p] == 0 and 0 <= tile < nb[p]
@@ -111,8 +112,8 @@ def test_task_list_covers_every_tile_once_and_waits_for_earlier_passes(P, seed):
 
 @pytest.mark.parametrize("seed", range(30))
 def test_workers_taking_tasks_in_order_always_finish(P, seed):
-    na, nb, nsub, steps, chain, group = shapes(100 + seed)
-    tasks = P.pe3d_persist_schedule(na, nb, nsub, steps, chain, group)
+    na, asub, nb, nsub, steps, chain, group = shapes(100 + seed)
+    tasks = P.pe3d_persist_schedule(na, asub, nb, nsub, steps, chain, group)
     rng = random.Random(seed)
     for workers in (1, 2, 3, 8, 64):
         dur = [rng.uniform(0.1, 3.0) for _ in tasks]
@@ -120,7 +121,7 @@ def test_workers_taking_tasks_in_order_always_finish(P, seed):
 
 
 def test_simulation_reports_a_dependency_placed_after_its_dependant(P):
-    tasks = P.pe3d_persist_schedule([2], [3], [1], [2], [0], [0])
+    tasks = P.pe3d_persist_schedule([2], [1], [3], [1], [2], [0], [0])
     assert simulate(tasks, 1, 1, [1.0] * len(tasks)) is not None
     # the azimuth tasks of step 0 moved before the depth tasks they wait for
     bad = tasks[2:5] + tasks[0:2] + tasks[5:]
@@ -132,7 +133,7 @@ def test_phases_of_chains_are_interleaved(P):
     """Two chains of one problem each: the azimuth phase of chain 0's step 0
     comes after chain 1's depth phase of step 0 (the other chain's work
     covers the wait)."""
-    tasks = P.pe3d_persist_schedule([2, 2], [2, 2], [1, 1], [2, 2], [0, 1], [0, 0])
+    tasks = P.pe3d_persist_schedule([2, 2], [1, 1], [2, 2], [1, 1], [2, 2], [0, 1], [0, 0])
     order = [(p, k, kind) for p, tile, k, kind, sub, need in tasks]
     first = {}
     for i, x in enumerate(order):
@@ -142,18 +143,13 @@ def test_phases_of_chains_are_interleaved(P):
 
 def test_schedule_rejects_invalid_shapes(P):
     with pytest.raises(Exception):
-        P.pe3d_persist_schedule([0], [1], [1], [1], [0], [0])   # no depth tiles
+        P.pe3d_persist_schedule([0], [1], [1], [1], [1], [0], [0])    # no depth tiles
     with pytest.raises(Exception):
-        P.pe3d_persist_schedule([1], [1], [9], [1], [0], [0])   # nsub above 8
+        P.pe3d_persist_schedule([1], [1], [1], [17], [1], [0], [0])   # tiles per task above 16
     with pytest.raises(Exception):
-        P.pe3d_persist_schedule([1], [1], [1], [-1], [0], [0])  # negative steps
-
-
-def test_persistent_kernel_is_refused_while_switched_off(P):
-    with pytest.raises(P.Pe3dError) as e:
-        P.pe3d_set_batch_kernel(P.PE3D_BATCH_PERSISTENT, 1.0)
-    assert e.value.status == P.PE3D_EUNSUPPORTED
-    P.pe3d_set_batch_kernel(P.PE3D_BATCH_LAUNCHES, 1.0)
+        P.pe3d_persist_schedule([1], [0], [1], [1], [1], [0], [0])    # no depth tiles per task
+    with pytest.raises(Exception):
+        P.pe3d_persist_schedule([1], [1], [1], [1], [-1], [0], [0])   # negative steps
 
 
 def test_batch_kernel_arguments_are_validated(P):
