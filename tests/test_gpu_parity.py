@@ -374,8 +374,11 @@ def test_tune_batch_azimuth_chooses_per_class_by_measurement(torch, P):
     assert len(rep["classes"]) == 3
     for c in rep["classes"].values():
         assert all(t > 0 for t in c["chunked_ms"] + c["pcr_ms"]) and c["chosen"] in ("chunked", "pcr")
-        best = min(("chunked", "pcr"), key=lambda k: sum(c[k + "_ms"]))
-        assert c["chosen"] == best
+        # the report rounds each time to 1e-4 ms and the tuner compares the
+        # unrounded sums: the chosen solver's rounded sum exceeds the other's
+        # by at most the rounding of the four times
+        other = "pcr" if c["chosen"] == "chunked" else "chunked"
+        assert sum(c[c["chosen"] + "_ms"]) <= sum(c[other + "_ms"]) + 2e-4, c
     assert out[0].grid.azimuth_solver == out[1].grid.azimuth_solver
     p = out[3]
     st = O.setup(p.env, p.grid, p.f_hz)
