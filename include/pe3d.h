@@ -288,10 +288,10 @@ pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes);
  *   PE3D_BATCH_PERSISTENT: one persistent kernel per call runs every step of
  *     every problem (the frequency loop of Fig. 2 on one device).  Its
  *     workgroups (as many as are resident at once, 256 lanes each) take
- *     tasks from a device list in order: one depth-pass tile or one group of
- *     azimuth-pass tiles of one problem at one step.  The list holds the same
- *     chains and groups as the launches, their phases (one pass of one step
- *     of one group) interleaved chain by chain.  A task starts once its
+ *     tasks from a device list in order: a run of depth-pass or azimuth-pass
+ *     tiles of one problem at one step.  The list holds the launches' chains,
+ *     one group per chain (group_bytes is not used), their phases (one pass
+ *     of one step of the group) interleaved chain by chain.  A task starts once its
  *     problem's counter shows that the other pass of its step (depth pass)
  *     or of the previous step (azimuth pass) has finished; every such wait
  *     is bounded by wait_limit_s (>= 0, finite; default 1 s): when a wait

@@ -1367,7 +1367,10 @@ void persist_shape(const pe3d_handle h, PersistProb& q) {
 
 pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
                        int nchains, long long group_bytes, bool persist, long long wait_ticks, BatchPlan& P) {
-  auto part = batch_partition(hs, n, nsteps, nchains, group_bytes);
+  // the persistent kernel takes one group per chain: its workgroups publish
+  // finished tasks in batches, which leaves the short phases of cache-sized
+  // groups waiting on each other
+  auto part = batch_partition(hs, n, nsteps, nchains, persist ? 0 : group_bytes);
   // problem slots in the descriptor table, in partition order
   std::vector<int> order;
   for (auto& c : part)

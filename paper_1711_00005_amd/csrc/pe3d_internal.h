@@ -150,6 +150,10 @@ int pass_b_lds(int prec, int W, int M, int nthr = kPassBThreads);
 // Control words and per-problem counters of the persistent march: one
 // 128-byte line each (the waiting workgroups poll them).
 constexpr int kPersistCounterStride = 32;
+// Finished tasks a workgroup of the persistent march publishes with one
+// device-scope release (at most; fewer before a wait and at the end of the
+// list).
+constexpr int kPersistPublishEvery = 8;
 inline int persist_ctl_ints(int nprob) { return (2 + nprob) * kPersistCounterStride; }
 // The persistent batched march: ctl_done (persist_ctl_ints ints) zeroed, then
 // march_persist over the task list with as many workgroups as fit on the

@@ -1444,13 +1444,16 @@ __global__ __launch_bounds__(kPassBThreads) void pass_b_pcr_single(ProbDesc d, i
 // finished before it may start: every task of the step's depth pass (for the
 // azimuth pass), or of the previous step (for the depth pass).  A workgroup
 // only ever waits for tasks that precede its own in the list, which were
-// taken by workgroups already running, so every wait ends without any
-// assumption on how many workgroups are resident.  Each wait is also bounded
+// taken by workgroups already running; a workgroup publishes its finished
+// tasks in small batches, but always before it waits and before it leaves,
+// so every finished task is published within a few tasks of its workgroup
+// and every wait ends without any assumption on how many workgroups are
+// resident.  Each wait is also bounded
 // in time: when it runs out, the workgroup counts the timeout
 // (g_wait_timeouts), raises the launch's abort flag and leaves; workgroups
 // that are waiting see the flag and leave too, so the kernel always ends
 // (the fields of that call are then undefined).  Ordering: a task's stores
-// are released at device scope before its problem's counter is incremented,
+// are released at device scope before its problem's counter counts it,
 // and a waiting workgroup acquires the counter at device scope before any of
 // its lanes reads the field (the L2 caches of the XCDs are not coherent with
 // each other without these fences).
@@ -1505,6 +1508,43 @@ void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__
   __shared__ int s_task;
   const bool first_wave = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;  // uniform per wavefront
   const int one = (threadIdx.x & 63) == 0 ? 1 : 0;                           // lane 0 of the wavefront
+  // finished tasks not yet published (first wavefront, scalar registers):
+  // pend_n[i] tasks of problem pend_p[i], i < npend; published together after
+  // one device-scope release
+  constexpr int KP = kPersistPublishEvery;
+  int pend_p[KP], pend_n[KP];
+  int npend = 0, nfin = 0;
+  auto publish = [&] {
+    if (npend) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      #pragma unroll
+      for (int i = 0; i < KP; ++i)
+        if (i < npend)
+          __hip_atomic_fetch_add(done + pend_p[i] * kPersistCounterStride, pend_n[i] * one, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    }
+    npend = 0;
+    nfin = 0;
+  };
+  auto finished = [&](int prob) {
+    bool found = false;
+    #pragma unroll
+    for (int i = 0; i < KP; ++i)
+      if (i < npend && pend_p[i] == prob) {
+        ++pend_n[i];
+        found = true;
+      }
+    if (!found) {
+      #pragma unroll
+      for (int i = 0; i < KP; ++i)
+        if (i == npend) {
+          pend_p[i] = prob;
+          pend_n[i] = 1;
+        }
+      ++npend;
+    }
+    if (++nfin >= KP) publish();
+  };
   for (;;) {
     if (first_wave) {
       int t = __builtin_amdgcn_readfirstlane(
@@ -1516,6 +1556,7 @@ void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__
           return __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         };
         if (count() < need) {
+          publish();  // never wait while holding unpublished tasks
           const long long t0 = (long long)wall_clock64();
           while (count() < need) {
             if (__builtin_amdgcn_readfirstlane(
@@ -1534,7 +1575,8 @@ void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      s_task = t;  // every lane writes the same value
+      if (t >= ntasks) publish();  // the workgroup leaves
+      s_task = t;                  // every lane writes the same value
     }
     // (the first wavefront's acquire covers the CU: its caches are shared by
     // the workgroup's wavefronts, which read only after this barrier)
@@ -1557,14 +1599,15 @@ void march_persist(const ProbDesc* __restrict__ descs, const PTask* __restrict__
         persist_pass_b<S>(d, tk.tile + q, tk.k, smem_p);
       }
     }
-    // every wavefront waits for its stores to complete, then the first
-    // wavefront publishes the task with one device-scope release (one write
-    // back of the XCD's L2 per task: such fences are the kernel's main
-    // overhead); LDS and s_task are then free for the next task
+    // every wavefront waits for its stores to complete; the first wavefront
+    // then counts the task as finished and publishes its finished tasks with
+    // one device-scope release (a write-back of the XCD's L2, the kernel's
+    // main overhead) once kPersistPublishEvery of them are pending, or
+    // before it waits or leaves (LDS and s_task are then free for the next
+    // task)
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (first_wave)
-      __hip_atomic_fetch_add(done + tk.prob * kPersistCounterStride, one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (first_wave) finished(tk.prob);
   }
 }
 

@@ -112,9 +112,10 @@ def test_persistent_equals_launches(torch, P, prec, use_graph, chains):
 
 
 def test_persistent_small_groups_and_profile(torch, P):
-    """Many groups per chain (16 KiB of field per group): the phases of
-    successive groups follow each other in the list; the profiled call
-    records one persistent launch with the call's algorithmic bytes."""
+    """A schedule of many groups per chain (16 KiB of field per group) for
+    the launches, which the persistent kernel replaces by one group per
+    chain; the profiled call records one persistent launch with the call's
+    algorithmic bytes."""
     prec = W.PREC_C64
     probs = problems(prec)
     u0s = fields(torch, probs, prec, 900)
