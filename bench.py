@@ -542,6 +542,25 @@ def range_report(P, nsteps=1000):
                                                         pt_steps_per_s=p.points / (g * 1e-3),
                                                         how="pe3d_march_batch of the one problem, "
                                                             "calls of 100 steps replayed from a graph")
+            # and with the persistent batch kernel (one launch per call)
+            P.set_batch_kernel(P.PE3D_BATCH_PERSISTENT)
+            try:
+                P.prepare_batch([m], 100, [u])
+                P.march_batch([m], 100, [u], use_graph=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(nsteps // 100):
+                    P.march_batch([m], 100, [u], use_graph=True)
+                e1.record()
+                torch.cuda.synchronize()
+            finally:
+                P.set_batch_kernel(P.PE3D_BATCH_LAUNCHES)
+            g = e0.elapsed_time(e1) / (100 * (nsteps // 100))
+            res["wedge_range_independent_persistent"] = dict(ms_per_step=round(g, 5),
+                                                             pt_steps_per_s=p.points / (g * 1e-3),
+                                                             how="pe3d_march_batch of the one problem with "
+                                                                 "the persistent kernel, calls of 100 steps "
+                                                                 "replayed from a graph")
         m.close()
     res.update(workload="config2 grid: periodic wedge vs slope_env (d0 400 m, 3 deg plane slope "
                         "clipped to 30-2500 m, rows every 250 m) vs front_env (the wedge under a Munk "

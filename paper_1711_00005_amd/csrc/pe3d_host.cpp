@@ -1339,18 +1339,23 @@ void persist_tasks(const std::vector<std::vector<std::vector<int>>>& chains, con
 
 // Tiles of the persistent kernel's tasks.  The depth pass's tiles are the
 // launches' (256 / L columns each); the azimuth pass's hold 256 lanes.  A
-// task takes consecutive tiles until it covers kPersistTaskPoints grid
-// points (at most kPersistMaxSub tiles), and an azimuth task at least enough
-// tiles to fill a 128-byte line of each depth line it touches: each task ends
-// with one device-scope release (a write-back of the XCD's L2), the kernel's
-// main overhead, so tasks must not be small.
+// task takes consecutive tiles until it covers `points` grid points (at most
+// kPersistMaxSub tiles), and an azimuth task at least enough tiles to fill a
+// 128-byte line of each depth line it touches.  Finished tasks are published
+// with device-scope releases (write-backs of the XCD's L2), the kernel's
+// main overhead, so tasks hold kPersistTaskPoints points unless the batch is
+// too small to give every resident workgroup two tasks per pass.
 constexpr int kPersistTaskPoints = 16384;
 constexpr int kPersistMaxSub = 16;
-void persist_shape(const pe3d_handle h, PersistProb& q) {
+int persist_task_points(double batch_points, int resident) {
+  const double per = batch_points / (2.0 * std::max(1, resident));
+  return int(std::max(1.0, std::min(double(kPersistTaskPoints), per)));
+}
+void persist_shape(const pe3d_handle h, int points, PersistProb& q) {
   const ProbDesc& d = h->desc;
   const int esz = h->prec ? 16 : 8;
-  auto sub_for = [](int pts_per_tile, int at_least) {
-    int s = std::max(at_least, (kPersistTaskPoints + pts_per_tile - 1) / std::max(1, pts_per_tile));
+  auto sub_for = [points](int pts_per_tile, int at_least) {
+    int s = std::max(at_least, (points + pts_per_tile - 1) / std::max(1, pts_per_tile));
     return std::max(1, std::min(kPersistMaxSub, s));
   };
   q.na = d.ntile_a;
@@ -1472,9 +1477,16 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::vector<PTask> tasks;
   if (persist) {
     std::vector<PersistProb> pp(np);
+    double batch_points = 0.0;
+    for (int p = 0; p < np; ++p) batch_points += double(hs[order[p]]->desc.nz) * hs[order[p]]->desc.nth;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hs[0]->device) != hipSuccess || ncu < 1)
+      ncu = 256;
+    // resident workgroups: 3 per CU (the kernel's complex64 occupancy; 2 for complex128)
+    const int points = persist_task_points(batch_points, ncu * (P.prec ? 2 : 3));
     for (int p = 0; p < np; ++p) {
       pe3d_handle h = hs[order[p]];
-      persist_shape(h, pp[p]);
+      persist_shape(h, points, pp[p]);
       pp[p].nsteps = nsteps[order[p]];
       const double esz = h->prec ? 16.0 : 8.0;
       const double pts = double(h->desc.nz) * h->desc.nth;
