@@ -60,3 +60,28 @@ def test_served_alone_equals_served_in_mix(torch):
     st = O.setup(p.env, p.grid, p.f_hz)
     ref = O.march(st, O.starter(st, p.zs), 0, p.nsteps)
     assert O.rel_l2(be.kept[small.rid].astype(np.complex128), ref) < 1e-5
+
+
+def test_served_with_persistent_kernel_equals_launches(torch):
+    """The same trace served with the persistent batch kernel (one launch per
+    iteration) gives every request the field the launches give, bit for
+    bit, and no wait runs out."""
+    from paper_1711_00005_amd import pe3d as P
+    from paper_1711_00005_amd.serve import Pe3dBackend, Scheduler, report
+    tr = trace(12, seed=2, max_steps=25)
+    keep = [r.rid for r in tr]
+    kept = {}
+    for kind in (P.PE3D_BATCH_LAUNCHES, P.PE3D_BATCH_PERSISTENT):
+        say("serve kind", kind, len(tr))
+        P.set_batch_kernel(kind)
+        try:
+            be = Pe3dBackend(keep_fields=keep)
+            recs = Scheduler(be, budget_bytes=256 << 20, chunk_steps=6).run(tr)
+        finally:
+            P.set_batch_kernel(P.PE3D_BATCH_LAUNCHES)
+        assert report(recs)["done"] == len(tr)
+        kept[kind] = be.kept
+    torch.cuda.synchronize()
+    assert P.pe3d_batch_wait_timeouts() == 0
+    for r in tr:
+        assert np.array_equal(kept[P.PE3D_BATCH_LAUNCHES][r.rid], kept[P.PE3D_BATCH_PERSISTENT][r.rid]), r.rid
