@@ -297,8 +297,10 @@ pe3d_status pe3d_set_batch_schedule(int32_t chains, int64_t group_bytes);
  *     is bounded by wait_limit_s (>= 0, finite; default 1 s): when a wait
  *     runs out the call's workgroups leave early, the call's fields and step
  *     counters are then undefined, and pe3d_batch_wait_timeouts reports it.
- *     A call whose problems include range rows (depth or water) uses the
- *     launches.  Results are bitwise identical to the launches.
+ *     A call whose problems include range rows (depth or water), or whose
+ *     task list would exceed 2^24 tasks (20 bytes each; about steps x grid
+ *     points / 16384 tasks), uses the launches.  Results are bitwise
+ *     identical to the launches.
  * Errors: PE3D_EINVAL (unknown kind, wait_limit_s negative, not finite or
  * above 3600). */
 #define PE3D_BATCH_LAUNCHES 0

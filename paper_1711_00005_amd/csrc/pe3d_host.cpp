@@ -5,7 +5,6 @@
 
 #include <algorithm>
 #include <array>
-#include <limits>
 #include <list>
 #include <cmath>
 #include <complex>
@@ -1370,6 +1369,36 @@ void persist_shape(const pe3d_handle h, int points, PersistProb& q) {
   q.bsub = sub_for(td * d.nth, 128 / (td * esz));
 }
 
+// Task lists of at most this many tasks (20 bytes each); a longer call (the
+// list grows with the steps) runs the launches.
+constexpr long long kPersistMaxTasks = 1ll << 24;
+
+// Grid points per task of the persistent kernel for these stepping problems.
+int persist_points_for(const pe3d_handle* hs, int n, const int32_t* nsteps) {
+  double batch_points = 0.0;
+  for (int i = 0; i < n; ++i)
+    if (nsteps[i] > 0) batch_points += double(hs[i]->desc.nz) * hs[i]->desc.nth;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hs[0]->device) != hipSuccess || ncu < 1)
+    ncu = 256;
+  // resident workgroups: 3 per CU (the kernel's complex64 occupancy; 2 for complex128)
+  return persist_task_points(batch_points, ncu * (hs[0]->prec ? 2 : 3));
+}
+
+// Length of the persistent kernel's task list for these problems.
+long long persist_task_count(const pe3d_handle* hs, int n, const int32_t* nsteps) {
+  const int points = persist_points_for(hs, n, nsteps);
+  long long total = 0;
+  for (int i = 0; i < n; ++i) {
+    if (nsteps[i] <= 0) continue;
+    PersistProb q{};
+    persist_shape(hs[i], points, q);
+    const long long per_step = (q.na + q.asub - 1) / q.asub + (q.nb > 0 ? (q.nb + q.bsub - 1) / q.bsub : 0);
+    total += per_step * nsteps[i];
+  }
+  return total;
+}
+
 pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void* const* u,
                        int nchains, long long group_bytes, bool persist, long long wait_ticks, BatchPlan& P) {
   // the persistent kernel takes one group per chain: its workgroups publish
@@ -1477,13 +1506,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
   std::vector<PTask> tasks;
   if (persist) {
     std::vector<PersistProb> pp(np);
-    double batch_points = 0.0;
-    for (int p = 0; p < np; ++p) batch_points += double(hs[order[p]]->desc.nz) * hs[order[p]]->desc.nth;
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hs[0]->device) != hipSuccess || ncu < 1)
-      ncu = 256;
-    // resident workgroups: 3 per CU (the kernel's complex64 occupancy; 2 for complex128)
-    const int points = persist_task_points(batch_points, ncu * (P.prec ? 2 : 3));
+    const int points = persist_points_for(hs, n, nsteps);
     for (int p = 0; p < np; ++p) {
       pe3d_handle h = hs[order[p]];
       persist_shape(h, points, pp[p]);
@@ -1497,7 +1520,7 @@ pe3d_status build_plan(const pe3d_handle* hs, int n, const int32_t* nsteps, void
                                                h->desc.mb, kPersistThreads));
     }
     persist_tasks(pchains, pp, tasks);
-    if (tasks.size() > size_t(std::numeric_limits<int>::max())) return PE3D_EUNSUPPORTED;
+    if (tasks.size() > size_t(kPersistMaxTasks)) return PE3D_EUNSUPPORTED;  // checked by the caller
     P.persist = true;
     P.ntasks = int(tasks.size());
     P.wait_ticks = wait_ticks;
@@ -1810,6 +1833,8 @@ extern "C" pe3d_status pe3d_march_batch(const pe3d_handle* hs, int32_t n, const 
   bool persist = g_batch_kernel.load() == PE3D_BATCH_PERSISTENT;
   for (int i = 0; i < n && persist; ++i)
     if (nsteps[i] > 0 && (hs[i]->desc.nbr || hs[i]->desc.nsr)) persist = false;
+  // (and unless its task list would be too long)
+  if (persist && persist_task_count(hs, n, nsteps) > kPersistMaxTasks) persist = false;
   const double wait_s = g_wait_limit_s.load();
   std::vector<uintptr_t> key;
   key.reserve(3 * n + 4);
