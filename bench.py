@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed range steps of the whole batch")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--chunk", type=int, default=50, help="range steps per batched call (one graph)")
+    ap.add_argument("--chunk", type=int, default=100, help="range steps per batched call (one graph)")
     ap.add_argument("--chains", type=int, default=2,
                     help="batch schedule: independent chains replayed on concurrent streams")
     ap.add_argument("--group-mib", type=int, default=112,
