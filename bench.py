@@ -226,11 +226,15 @@ def main():
         # near the source and half-way through the march
         from paper_1711_00005_amd import tune as T
         t0 = time.perf_counter()
-        probs, variants = T.tune_batch_azimuth(probs, far=max(1, probs[0].nsteps // 2) if len(probs) == 1
-                                               else 500)
+        tuned_probs, variants = T.tune_batch_azimuth(probs, far=max(1, probs[0].nsteps // 2) if len(probs) == 1
+                                                     else 500)
         chosen = [c["chosen"] for c in variants["classes"].values()]
+        # the per-class choice is kept only if the whole batch is faster with it
+        P.set_batch_schedule(args.chains, args.group_mib << 20)
+        probs, variants["whole_batch"] = T.keep_if_faster(probs, tuned_probs)
         variants.update(seconds=round(time.perf_counter() - t0, 2),
-                        summary=f"{chosen.count('chunked')} classes chunked, {chosen.count('pcr')} cyclic reduction")
+                        summary=f"{chosen.count('chunked')} classes chunked, {chosen.count('pcr')} cyclic reduction; "
+                                f"kept: {variants['whole_batch']['kept']}")
         log(f"azimuth solver: {variants['summary']} ({variants['seconds']} s)")
     ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in probs]
     us = [m.starter(p.zs) for m, p in zip(ms, probs)]

@@ -9,7 +9,10 @@ pass separately (the depth pass does not depend on the azimuth lanes and
 vice versa), with the library's own per-launch event timing, and returns the
 fastest of each.  `tune_batch_azimuth` chooses the azimuth solver per class
 of problems (same Ntheta and azimuth boundary) inside batched launches, where
-a problem shares the GPU with the others.  Lanes and solver change only how
+a problem shares the GPU with the others; `keep_if_faster` then times the
+whole batch in the library's batch schedule with the chosen solvers and with
+the default ones and keeps the faster (a class that wins alone can lengthen
+the schedule's launch tails in the mix).  Lanes and solver change only how
 the same systems are solved, so a tuned march agrees with the default one to
 rounding.
 """
@@ -147,3 +150,47 @@ def tune_batch_azimuth(problems, steps: int = 6, far: int = 0, reps: int = 2):
                        "pcr_ms": [round(t, 4) for t in times[P.PE3D_AZIMUTH_PCR]],
                        "chosen": "pcr" if best == P.PE3D_AZIMUTH_PCR else "chunked"}
     return out, {"near_steps_from": 1, "far_steps_from": far, "classes": report}
+
+
+def _batch_ms_per_step(problems, steps: int, reps: int) -> float:
+    """Best ms per batch step of the problems marched together in the
+    library's current batch schedule, calls of `steps` steps replayed from a
+    captured graph (events around the calls)."""
+    import torch
+    ms = [P.Pe3d(p.env, p.grid, p.f_hz) for p in problems]
+    try:
+        us = [m.starter(p.zs) for m, p in zip(ms, problems)]
+        P.prepare_batch(ms, steps, us)
+        P.march_batch(ms, steps, us)  # first replay
+        torch.cuda.synchronize()
+        best = float("inf")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(reps):
+            e0.record()
+            P.march_batch(ms, steps, us)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / steps)
+        return best
+    finally:
+        for m in ms:
+            m.close()
+
+
+def keep_if_faster(default, tuned, steps: int = 20, reps: int = 3):
+    """The tuned problems if the whole batch marches faster with them than
+    with the default solvers (same schedule, same calls), else the default
+    ones; and a report {default_ms_per_step, tuned_ms_per_step, kept}.  The
+    two sets are timed alternately."""
+    changed = any(a.grid != b.grid for a, b in zip(default, tuned))
+    if not changed:
+        return tuned, {"kept": "tuned", "note": "the choice equals the default"}
+    td, tt = float("inf"), float("inf")
+    for _ in range(2):
+        td = min(td, _batch_ms_per_step(default, steps, reps))
+        tt = min(tt, _batch_ms_per_step(tuned, steps, reps))
+    kept = "tuned" if tt < td else "default"
+    return (tuned if kept == "tuned" else default), {
+        "default_ms_per_step": round(td, 4), "tuned_ms_per_step": round(tt, 4), "kept": kept,
+        "how": f"whole batch, library batch schedule, calls of {steps} steps replayed from a graph, "
+               f"best of {2 * reps} per set, sets alternated"}

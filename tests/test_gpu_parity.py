@@ -387,6 +387,26 @@ def test_tune_batch_azimuth_chooses_per_class_by_measurement(torch, P):
     assert O.rel_l2(got, ref) < TOL[p.grid.precision]
 
 
+def test_keep_if_faster_times_the_whole_batch(torch, P):
+    """The whole-batch check of the in-batch solver choice: both sets timed in
+    the batch schedule, the faster kept and reported; an unchanged choice is
+    kept without timing."""
+    from paper_1711_00005_amd import tune as T
+    env = W.wedge_env()
+    base = [W.Problem(env, W.Grid(nz=200, ntheta=nt, theta0=0.0, width=W.TWO_PI, dr=10.0), 40.0, 100.0, 30, f"p{i}")
+            for i, nt in enumerate([24, 64, 64])]
+    tuned = [dataclasses.replace(p, grid=dataclasses.replace(p.grid, azimuth_solver=W.AZ_PCR))
+             if p.grid.ntheta == 64 else p for p in base]
+    say("keep if faster")
+    out, rep = T.keep_if_faster(base, tuned, steps=5, reps=1)
+    assert rep["kept"] in ("tuned", "default")
+    assert rep["default_ms_per_step"] > 0 and rep["tuned_ms_per_step"] > 0
+    assert out is (tuned if rep["kept"] == "tuned" else base)
+    assert (rep["tuned_ms_per_step"] < rep["default_ms_per_step"]) == (rep["kept"] == "tuned")
+    same, rep2 = T.keep_if_faster(base, list(base))
+    assert rep2["kept"] == "tuned" and "note" in rep2 and same == base
+
+
 def test_tune_nx2d_times_the_depth_pass_only(torch, P):
     """The tuner of an N x 2D shape searches the depth lanes only (there is
     no azimuth pass) and its choice matches the oracle."""
