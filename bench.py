@@ -84,7 +84,7 @@ def parse():
                     help="requests of the served stream (the first n of the 2000-request trace)")
     ap.add_argument("--serve-range-scale", type=float, default=1.0,
                     help="multiply every served request's range (and steps) by this factor")
-    ap.add_argument("--serve-chunk", type=int, default=20,
+    ap.add_argument("--serve-chunk", type=int, default=40,
                     help="range steps every resident request advances per served iteration")
     ap.add_argument("--serve-backlog-chunk", type=int, default=100,
                     help="range steps per served iteration while requests wait for admission")

@@ -138,7 +138,7 @@ class Pe3dBackend(Backend):
 
 
 class Scheduler:
-    def __init__(self, backend: Backend, budget_bytes: int, chunk_steps: int = 20,
+    def __init__(self, backend: Backend, budget_bytes: int, chunk_steps: int = 40,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, log: Optional[Callable] = None,
                  backlog_chunk_steps: Optional[int] = None):
@@ -284,7 +284,7 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--budget-gib", type=float, default=1.0)
-    ap.add_argument("--chunk", type=int, default=20)
+    ap.add_argument("--chunk", type=int, default=40)
     ap.add_argument("--backlog-chunk", type=int, default=100,
                     help="steps per iteration while requests wait for admission")
     ap.add_argument("--range-scale", type=float, default=1.0,
